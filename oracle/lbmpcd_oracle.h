@@ -1,0 +1,115 @@
+/*
+ * lbmpcd_oracle.h -- plain, slow, single-threaded FP64 CPU reference of the
+ * coupled lattice-Boltzmann / multiparticle-collision (LB-MPCD) time step of
+ * Montessori, Tiribocchi, Lauricella and Succi, "A coupled lattice
+ * Boltzmann-Multiparticle collision method for multi-resolution
+ * hydrodynamics" (arXiv 2004.00304).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP path.  Only
+ * the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+ * load it.  It shares no source with the HIP library (its own parameter
+ * struct, its own Philox, its own lattice tables) and never includes the
+ * product headers.
+ *
+ * Everything is double precision.  When part_fp32 is set, particle positions
+ * and velocities are rounded to binary32 at every point where they are stored,
+ * and the streaming update is evaluated in binary32, so that the oracle takes
+ * the same float-valued binning decisions as a binary32 particle store.
+ *
+ * Errors: functions returning int return 0 on success and a positive code on
+ * failure (1 = invalid parameters, 2 = out of memory).
+ */
+#ifndef LBMPCD_ORACLE_H
+#define LBMPCD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Problem statement of the paper's results section (Poiseuille channel, body
+ * force along the flow, periodic along the flow, no-slip walls) extended to
+ * D3Q19 and to a refined MPCD slab with buffers (Sec. 2.3, Alg. 1 and 2). */
+typedef struct orc_params {
+    int32_t dim;            /* 2 (D2Q9) or 3 (D3Q19) */
+    int32_t nx, ny, nz;     /* LB nodes; nz = 1 in 2D */
+    double tau, rho0;       /* BGK relaxation time (Eq. 1), initial density */
+    double g[3];            /* body acceleration; LB force density is rho*g */
+    int32_t walls_y;        /* 1: half-way bounce-back walls at y=0 and y=ny; 0: periodic y */
+    int32_t mpcd;           /* 0: LB only */
+    int32_t ylo, yhi;       /* MPCD slab [ylo, yhi) in LB rows, full x and z extent */
+    int32_t buf_lo, buf_hi; /* buffer (coupling region) depth in LB rows at the LB-facing faces */
+    int32_t refine;         /* r: collision cell side a = 1/r LB units */
+    int32_t substeps;       /* S: MPCD steps per LB step, delta_t = 1/S */
+    int32_t ppc;            /* initial particles per collision cell */
+    int32_t part_fp32;      /* 1: binary32 particle store */
+    double mass, kT, alpha_deg;
+    int32_t grid_shift;     /* 1: random grid shift every MPCD step */
+    int32_t feedback;       /* 1: project MPCD averages back onto LB equilibria */
+    int32_t init_flow;      /* 0: rest, 1: discrete Poiseuille steady profile */
+    uint64_t seed;
+    uint32_t instance;
+} orc_params;
+
+typedef struct orc_state orc_state;
+
+/* ---- stateful simulation --------------------------------------------- */
+int  orc_create(const orc_params* p, orc_state** out);
+void orc_destroy(orc_state* s);
+int  orc_step(orc_state* s, int32_t n_lb_steps);
+/* mode 1: reset and start accumulating the time-averaged profile; 0: stop */
+void orc_sample(orc_state* s, int32_t mode);
+
+int64_t orc_num_particles(const orc_state* s);
+int32_t orc_num_cells(const orc_state* s);       /* cells of the shifted binning grid */
+int32_t orc_num_fine_rows(const orc_state* s);   /* fine rows of the slab */
+int64_t orc_lb_step_count(const orc_state* s);
+
+/* post-stream populations f[q][z][y][x] */
+void orc_get_f(const orc_state* s, double* f);
+void orc_set_f(orc_state* s, const double* f);
+/* post-collision populations (BGK+Guo collision of the stored state) */
+void orc_get_fstar(const orc_state* s, double* f);
+/* rho[N], u[3][N] (u includes the half-force shift), pi[6][N] (xx,yy,zz,xy,xz,yz) */
+void orc_get_moments(const orc_state* s, double* rho, double* u, double* pi);
+/* particles by id: pos[d][Np], vel[d][Np] */
+void orc_get_particles(const orc_state* s, double* pos, double* vel);
+void orc_set_particles(orc_state* s, const double* pos, const double* vel);
+/* binning of the last MPCD step: cell of each particle, cell counts, cell
+ * starts of the stable counting sort, sorted order (particle ids), and the
+ * centre-of-mass velocity of every cell (virtual wall particles included) */
+void orc_get_binning(const orc_state* s, int32_t* cell_of, int32_t* count,
+                     int32_t* start, int32_t* order, double* vcm);
+/* interpolated LB velocity at every fine cell of the slab, [d][K][J][I] */
+void orc_get_ufine(const orc_state* s, double* ufine);
+/* time-averaged profile accumulators per fine row: [J][0]=sum n, [J][1+k]=sum v_k */
+void orc_get_profile(const orc_state* s, double* acc, int64_t* n_lb_steps_sampled);
+/* per-LB-step sample accumulators of the slab [(iz*R + J)*nx + ix][4] */
+void orc_get_step_acc(const orc_state* s, double* acc);
+/* grid shift of the last MPCD step */
+void orc_get_shift(const orc_state* s, double sh[3]);
+/* recompute the buffer fine-cell velocities from the current populations */
+void orc_refresh_ufine(orc_state* s);
+
+/* ---- building blocks, exported for the pins ---------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_u01(uint32_t lo, uint32_t hi);
+/* lattice tables: returns Q; c is Q*3 ints, w is Q doubles, opp is Q ints */
+int  orc_lattice(int32_t dim, int32_t* c, double* w, int32_t* opp);
+void orc_feq(int32_t dim, double rho, const double u[3], double* feq);
+/* one BGK+Guo collision of a single node's populations (in place) */
+void orc_collide_node(int32_t dim, double tau, const double g[3], double* f);
+/* Box-Muller pair from two uniforms */
+void orc_box_muller(double u0, double u1, double* z0, double* z1);
+/* SRD rotation of n velocities (vel[d][n]) about their centre of mass */
+void orc_srd_rotate(int32_t dim, int32_t n, double* vel, double cos_a, double sin_a,
+                    double sign2d, const double axis[3], const double p_virt[3], double m_virt,
+                    double vcm_out[3]);
+/* stable counting sort of cell ids: count[nc], start[nc], order[n] */
+void orc_counting_sort(int32_t n, const int32_t* cell, int32_t nc,
+                       int32_t* count, int32_t* start, int32_t* order);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

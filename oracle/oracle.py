@@ -1,0 +1,296 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``liblbmpcd_oracle.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
+CPU-baseline leg of the benchmark.  The product path never imports it.  It is
+driven from the neutral parameter dicts of ``paper_2004_00304_amd.workloads``
+and shares nothing else with the HIP binding.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmpcd_oracle.so")
+SRC = os.path.join(_HERE, "lbmpcd_oracle.c")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: -O2, no fast-math, no FMA contraction."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("tau", C.c_double), ("rho0", C.c_double), ("g", C.c_double * 3),
+        ("walls_y", C.c_int32), ("mpcd", C.c_int32), ("ylo", C.c_int32), ("yhi", C.c_int32),
+        ("buf_lo", C.c_int32), ("buf_hi", C.c_int32), ("refine", C.c_int32),
+        ("substeps", C.c_int32), ("ppc", C.c_int32), ("part_fp32", C.c_int32),
+        ("mass", C.c_double), ("kT", C.c_double), ("alpha_deg", C.c_double),
+        ("grid_shift", C.c_int32), ("feedback", C.c_int32), ("init_flow", C.c_int32),
+        ("seed", C.c_uint64), ("instance", C.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.orc_create.argtypes = [C.POINTER(_Params), C.POINTER(C.c_void_p)]
+        L.orc_create.restype = C.c_int
+        L.orc_destroy.argtypes = [P]
+        L.orc_step.argtypes = [P, C.c_int32]
+        L.orc_step.restype = C.c_int
+        L.orc_sample.argtypes = [P, C.c_int32]
+        for name in ("orc_num_particles", "orc_lb_step_count"):
+            getattr(L, name).argtypes = [P]
+            getattr(L, name).restype = C.c_int64
+        for name in ("orc_num_cells", "orc_num_fine_rows"):
+            getattr(L, name).argtypes = [P]
+            getattr(L, name).restype = C.c_int32
+        for name in ("orc_get_f", "orc_set_f", "orc_get_fstar", "orc_get_ufine", "orc_get_step_acc"):
+            getattr(L, name).argtypes = [P, P]
+        L.orc_get_moments.argtypes = [P, P, P, P]
+        L.orc_get_shift.argtypes = [P, P]
+        L.orc_refresh_ufine.argtypes = [P]
+        L.orc_get_particles.argtypes = [P, P, P]
+        L.orc_set_particles.argtypes = [P, P, P]
+        L.orc_get_binning.argtypes = [P, P, P, P, P, P]
+        L.orc_get_profile.argtypes = [P, P, P]
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_u01.argtypes = [C.c_uint32, C.c_uint32]
+        L.orc_u01.restype = C.c_double
+        L.orc_lattice.argtypes = [C.c_int32, P, P, P]
+        L.orc_lattice.restype = C.c_int
+        L.orc_feq.argtypes = [C.c_int32, C.c_double, P, P]
+        L.orc_collide_node.argtypes = [C.c_int32, C.c_double, P, P]
+        L.orc_box_muller.argtypes = [C.c_double, C.c_double, P, P]
+        L.orc_srd_rotate.argtypes = [C.c_int32, C.c_int32, P, C.c_double, C.c_double,
+                                     C.c_double, P, P, C.c_double, P]
+        L.orc_counting_sort.argtypes = [C.c_int32, P, C.c_int32, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def params_struct(p: dict) -> _Params:
+    s = _Params()
+    s.dim = p["dim"]
+    s.nx, s.ny, s.nz = p["n"]
+    s.tau, s.rho0 = p["tau"], p["rho0"]
+    for k in range(3):
+        s.g[k] = p["g"][k]
+    s.walls_y, s.mpcd = p["walls_y"], p["mpcd"]
+    s.ylo, s.yhi, s.buf_lo, s.buf_hi = p["ylo"], p["yhi"], p["buf_lo"], p["buf_hi"]
+    s.refine, s.substeps, s.ppc = p["refine"], p["substeps"], p["ppc"]
+    s.part_fp32 = 1 if p["part_fp"] == 32 else 0
+    s.mass, s.kT, s.alpha_deg = p["mass"], p["kT"], p["alpha_deg"]
+    s.grid_shift, s.feedback, s.init_flow = p["grid_shift"], p["feedback"], p["init_flow"]
+    s.seed, s.instance = p["seed"], p["instance"]
+    return s
+
+
+class Oracle:
+    """One simulated channel held in host memory by the C oracle."""
+
+    def __init__(self, p: dict):
+        self.p = dict(p)
+        if p.get("collision", 0) != 0:
+            raise ValueError("oracle implements the SRD collision only")
+        self._L = lib()
+        self._ps = params_struct(p)
+        h = C.c_void_p()
+        rc = self._L.orc_create(C.byref(self._ps), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"orc_create failed ({rc}) for {p}")
+        self._h = h
+        self.dim = p["dim"]
+        self.Q = 9 if p["dim"] == 2 else 19
+        self.N = p["n"][0] * p["n"][1] * p["n"][2]
+        self.Np = int(self._L.orc_num_particles(h))
+        self.ncells = int(self._L.orc_num_cells(h)) if p["mpcd"] else 0
+        self.R = int(self._L.orc_num_fine_rows(h)) if p["mpcd"] else 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._L.orc_destroy(h)
+            self._h = None
+
+    # -- stepping
+    def step(self, n: int = 1):
+        rc = self._L.orc_step(self._h, int(n))
+        if rc != 0:
+            raise RuntimeError(f"orc_step failed ({rc})")
+
+    def sample(self, mode: int):
+        self._L.orc_sample(self._h, int(mode))
+
+    @property
+    def t(self) -> int:
+        return int(self._L.orc_lb_step_count(self._h))
+
+    # -- state
+    def shape(self):
+        nx, ny, nz = self.p["n"]
+        return (nz, ny, nx)
+
+    def f(self) -> np.ndarray:
+        out = np.empty((self.Q,) + self.shape(), np.float64)
+        self._L.orc_get_f(self._h, _ptr(out))
+        return out
+
+    def set_f(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, np.float64)
+        self._L.orc_set_f(self._h, _ptr(f))
+
+    def fstar(self) -> np.ndarray:
+        out = np.empty((self.Q,) + self.shape(), np.float64)
+        self._L.orc_get_fstar(self._h, _ptr(out))
+        return out
+
+    def moments(self):
+        rho = np.empty(self.shape(), np.float64)
+        u = np.empty((3,) + self.shape(), np.float64)
+        pi = np.empty((6,) + self.shape(), np.float64)
+        self._L.orc_get_moments(self._h, _ptr(rho), _ptr(u), _ptr(pi))
+        return rho, u, pi
+
+    def particles(self):
+        pos = np.zeros((self.dim, self.Np), np.float64)
+        vel = np.zeros((self.dim, self.Np), np.float64)
+        self._L.orc_get_particles(self._h, _ptr(pos), _ptr(vel))
+        return pos, vel
+
+    def set_particles(self, pos=None, vel=None):
+        pa = np.ascontiguousarray(pos, np.float64) if pos is not None else None
+        va = np.ascontiguousarray(vel, np.float64) if vel is not None else None
+        self._L.orc_set_particles(self._h, _ptr(pa) if pa is not None else None,
+                                  _ptr(va) if va is not None else None)
+
+    def binning(self):
+        cell = np.empty(self.Np, np.int32)
+        count = np.empty(self.ncells, np.int32)
+        start = np.empty(self.ncells, np.int32)
+        order = np.empty(self.Np, np.int32)
+        vcm = np.empty((3, self.ncells), np.float64)
+        self._L.orc_get_binning(self._h, _ptr(cell), _ptr(count), _ptr(start), _ptr(order),
+                                _ptr(vcm))
+        return dict(cell=cell, count=count, start=start, order=order, vcm=vcm[: self.dim])
+
+    def ufine(self) -> np.ndarray:
+        p = self.p
+        r = p["refine"]
+        Cx = p["n"][0] * r
+        Cz = p["n"][2] * r if self.dim == 3 else 1
+        out = np.empty((3, Cz, self.R, Cx), np.float64)
+        self._L.orc_get_ufine(self._h, _ptr(out))
+        return out[: self.dim]
+
+    def shift(self) -> np.ndarray:
+        out = np.zeros(3, np.float64)
+        self._L.orc_get_shift(self._h, _ptr(out))
+        return out[: self.dim]
+
+    def refresh_ufine(self):
+        self._L.orc_refresh_ufine(self._h)
+
+    def profile(self):
+        acc = np.empty((self.R, 4), np.float64)
+        n = C.c_int64()
+        self._L.orc_get_profile(self._h, _ptr(acc), C.byref(n))
+        return acc, int(n.value)
+
+    def step_acc(self) -> np.ndarray:
+        nx, _, nz = self.p["n"]
+        out = np.empty((nz, self.R, nx, 4), np.float64)
+        self._L.orc_get_step_acc(self._h, _ptr(out))
+        return out
+
+
+# ---- building blocks -----------------------------------------------------------
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, np.uint32)
+    k = np.asarray(key, np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def u01(lo: int, hi: int) -> float:
+    return float(lib().orc_u01(lo, hi))
+
+
+def lattice(dim: int):
+    c = np.empty((19, 3), np.int32)
+    w = np.empty(19, np.float64)
+    opp = np.empty(19, np.int32)
+    Q = lib().orc_lattice(dim, _ptr(c), _ptr(w), _ptr(opp))
+    return c[:Q].copy(), w[:Q].copy(), opp[:Q].copy()
+
+
+def feq(dim: int, rho: float, u) -> np.ndarray:
+    uu = np.zeros(3, np.float64)
+    uu[: len(u)] = u
+    out = np.empty(19, np.float64)
+    lib().orc_feq(dim, float(rho), _ptr(uu), _ptr(out))
+    return out[: (9 if dim == 2 else 19)].copy()
+
+
+def collide_node(dim: int, tau: float, g, f) -> np.ndarray:
+    gg = np.zeros(3, np.float64)
+    gg[: len(g)] = g
+    ff = np.zeros(19, np.float64)
+    Q = 9 if dim == 2 else 19
+    ff[:Q] = f
+    lib().orc_collide_node(dim, float(tau), _ptr(gg), _ptr(ff))
+    return ff[:Q].copy()
+
+
+def box_muller(u0: float, u1: float):
+    z0 = np.zeros(1)
+    z1 = np.zeros(1)
+    lib().orc_box_muller(float(u0), float(u1), _ptr(z0), _ptr(z1))
+    return float(z0[0]), float(z1[0])
+
+
+def srd_rotate(dim, vel, alpha_deg, sign2d=1.0, axis=(0.0, 0.0, 1.0), p_virt=(0, 0, 0), m_virt=0.0):
+    v = np.ascontiguousarray(vel, np.float64).copy()
+    n = v.shape[1]
+    a = np.radians(alpha_deg)
+    ax = np.asarray(axis, np.float64)
+    pv = np.asarray(p_virt, np.float64)
+    vcm = np.zeros(3)
+    lib().orc_srd_rotate(dim, n, _ptr(v), float(np.cos(a)), float(np.sin(a)), float(sign2d),
+                         _ptr(ax), _ptr(pv), float(m_virt), _ptr(vcm))
+    return v, vcm[:dim]
+
+
+def counting_sort(cell, nc):
+    cell = np.ascontiguousarray(cell, np.int32)
+    count = np.empty(nc, np.int32)
+    start = np.empty(nc, np.int32)
+    order = np.empty(len(cell), np.int32)
+    lib().orc_counting_sort(len(cell), _ptr(cell), nc, _ptr(count), _ptr(start), _ptr(order))
+    return count, start, order
