@@ -641,8 +641,10 @@ static void stream_particle(orc_state* s, int64_t k) {
     for (int d = 0; d < p->dim; ++d) { s->pos[d][k] = r1[d]; s->vel[d][k] = v1[d]; }
 }
 
-/* READING: the sample instant is right after streaming; the per-LB-step
- * accumulators feed the feedback and the time-averaged profiles. */
+/* READING: the sample instant is right after streaming.  The per-LB-step
+ * accumulators feed the feedback; while sampling is on every MPCD step also
+ * adds to the time-averaged profile of its fine row (the paper averages the
+ * profiles over samples to suppress the particle noise, Sec. 3.1). */
 static void sample_particle(orc_state* s, int64_t k) {
     const orc_params* p = &s->p;
     int ix = clampi((int)floor(s->pos[0][k]), 0, p->nx - 1);
@@ -651,6 +653,11 @@ static void sample_particle(orc_state* s, int64_t k) {
     double* a = s->acc + 4 * (((int64_t)iz * s->R + J) * p->nx + ix);
     a[0] += 1.0;
     for (int d = 0; d < p->dim; ++d) a[1 + d] += s->vel[d][k];
+    if (s->sampling) {
+        double* q = s->prof + 4 * J;
+        q[0] += 1.0;
+        for (int d = 0; d < p->dim; ++d) q[1 + d] += s->vel[d][k];
+    }
 }
 
 /* READING: random grid shift (Ihle-Kroll) drawn once per MPCD step,
@@ -759,29 +766,16 @@ static void mpcd_substep(orc_state* s, uint32_t t, uint32_t sub) {
     collide_cells(s, t, sub, sh);
 }
 
-static void profile_and_reset(orc_state* s) {
-    const orc_params* p = &s->p;
-    if (s->sampling) {
-        for (int z = 0; z < p->nz; ++z)
-            for (int J = 0; J < s->R; ++J)
-                for (int x = 0; x < p->nx; ++x) {
-                    const double* a = s->acc + 4 * (((int64_t)z * s->R + J) * p->nx + x);
-                    for (int k = 0; k < 4; ++k) s->prof[4 * J + k] += a[k];
-                }
-        s->prof_steps++;
-    }
-    memset(s->acc, 0, sizeof(double) * 4 * (size_t)p->nx * s->R * p->nz);
-}
-
 int orc_step(orc_state* s, int32_t n_lb_steps) {
     const orc_params* p = &s->p;
     for (int32_t it = 0; it < n_lb_steps; ++it) {
         lb_collide_stream(s);
         if (p->mpcd) {
             if (p->feedback) feedback_override(s);
-            profile_and_reset(s);
+            memset(s->acc, 0, sizeof(double) * 4 * (size_t)p->nx * s->R * p->nz);
             interpolate_buffers(s);
             for (int sub = 0; sub < p->substeps; ++sub) mpcd_substep(s, (uint32_t)s->t, (uint32_t)sub);
+            if (s->sampling) s->prof_steps++;
         }
         s->t++;
     }

@@ -342,10 +342,34 @@ def test_feedback_sets_node_velocity_to_particle_mean(oracle_lib):
 def test_profile_counts(oracle_lib):
     p = W.small_2d()
     o = oracle_lib.Oracle(p)
+    o.step(1)
     o.sample(1)
     o.step(3)
     acc, nsteps = o.profile()
-    # the flush happens at the start of each LB step: 3 flushes, the first of
-    # an empty accumulator
+    # every particle is sampled once per MPCD step while sampling is on
     assert nsteps == 3
-    assert acc[:, 0].sum() == o.Np * p["substeps"] * 2
+    assert acc[:, 0].sum() == o.Np * p["substeps"] * 3
+    o.sample(0)
+    o.step(1)
+    acc2, nsteps2 = o.profile()
+    assert nsteps2 == 3 and (acc2 == acc).all()
+
+
+def test_profile_is_row_average_of_samples(oracle_lib):
+    """With alpha = 0 the collision is the identity, so with one MPCD step per
+    LB step the samples taken after streaming are the particle states seen
+    after each step: the profile is their per-fine-row sum (brute force)."""
+    p = W.small_2d(alpha_deg=0.0, substeps=1)
+    o = oracle_lib.Oracle(p)
+    o.sample(1)
+    ref = np.zeros((o.R, 4))
+    for _ in range(3):
+        o.step(1)
+        pos, vel = o.particles()
+        J = np.clip(np.floor((pos[1] - p["ylo"]) * p["refine"]).astype(int), 0, o.R - 1)
+        ref[:, 0] += np.bincount(J, minlength=o.R)
+        for d in range(2):
+            ref[:, 1 + d] += np.bincount(J, weights=vel[d], minlength=o.R)
+    acc, _ = o.profile()
+    assert (acc[:, 0] == ref[:, 0]).all()
+    assert np.abs(acc[:, 1:3] - ref[:, 1:3]).max() < 1e-11
