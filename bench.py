@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled LB-MPCD time step on one MI355X.
+
+Workload: the 3D channel -- D3Q19 128x64x64 (tau 0.8, g 1e-6 along x, walls
+at y = 0 and 64, periodic x and z) coupled to an MPCD slab y in [24, 40) with
+2-row buffers, cell side 1/4 (512x64x256 cells), 20 particles per cell
+(167,772,160 binary32 particles, FP64 cell sums), SRD 120 deg about a random
+axis, 4 MPCD steps per LB step, random grid shift, feedback on.  Synthetic,
+seeded: positions uniform in cells, Maxwell-Boltzmann velocities.
+
+One "step" is one coupled LB step (LB collide-stream, feedback projection,
+interpolation to the buffer cells, 4 fused MPCD steps).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+PMC_FILE = os.path.join(ROOT, "profiles", "k_particles_channel_3d_pmc.json")
+KERNEL_SOURCES = ["paper_2004_00304_amd/csrc/kernels_mpcd.hip", "paper_2004_00304_amd/csrc/common.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str) -> dict:
+    from paper_2004_00304_amd import workloads as W
+    return {"channel_3d": W.channel_3d, "channel_2d": W.channel_2d, "thin_film_3d": W.thin_film_3d}[name]()
+
+
+def measured_traffic(per_launch_particles: int):
+    """HBM bytes per launch of the particle kernel from the committed rocprofv3
+    PMC summary (FETCH_SIZE, WRITE_SIZE scaled by a plain copy of known size),
+    or None when the summary is absent or the kernel changed since."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    with open(PMC_FILE) as f:
+        pmc = json.load(f)
+    if pmc.get("kernel_hash") != kernel_hash():
+        return None
+    return pmc.get("bytes_per_launch")
+
+
+def cpu_baseline(p: dict, seconds_cap: float = 25.0) -> dict:
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    x and z cut by 8 (same per-node and per-particle work), single thread."""
+    from oracle import oracle as O
+    from paper_2004_00304_amd import workloads as W
+
+    if not os.path.exists(O.LIB_PATH):
+        O.build()
+    q = W.make(**{**p, "n": (p["n"][0] // 8, p["n"][1], p["n"][2] // 8)})
+    o = O.Oracle(q)
+    full = W.sizes(p)
+    samp = W.sizes(q)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        if time.perf_counter() - t0 > seconds_cap / 3 or steps >= 3:
+            break
+    dt = time.perf_counter() - t0
+    sample_sps = steps / dt
+    scale = samp["particles"] / full["particles"]
+    return dict(value=sample_sps * scale, unit="coupled LB steps/s", cores=1, kind="oracle",
+                sample=(f"{q['n'][0]}x{q['n'][1]}x{q['n'][2]} nodes, {samp['particles']} particles "
+                        f"(x and z cut 8x), {steps} LB steps in {dt:.1f} s, scaled by the particle "
+                        f"ratio {scale:.5f}"),
+                particle_updates_per_s=samp["particles"] * p["substeps"] * sample_sps,
+                lb_mlups=samp["nodes"] * sample_sps / 1e6)
+
+
+def calib_copy():
+    """Plain device copy of known size, for scaling the PMC byte counters."""
+    import torch
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": n}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="channel_3d")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU "
+              "sharding of the coupled step is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2004_00304_amd import lbmpcd
+    from paper_2004_00304_amd import workloads as W
+
+    if args.calib_copy:
+        calib_copy()
+    p = workload(args.workload)
+    sz = W.sizes(p)
+    ab = W.algorithmic_bytes_per_lb_step(p)
+    torch.cuda.set_device(0)
+    sim = lbmpcd.Sim(p, device="cuda:0")
+    print(f"[bench] {args.workload}: {sz['nodes']} nodes, {sz['particles']} particles, "
+          f"workspace {sim.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    sim.sync()
+    st0 = sim.stats()
+    sim.timing(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.timing(0)
+    kt = sim.timing_read()
+    sim.sync()
+    st = sim.stats()
+    if st["dropped"] or st["misplaced"]:
+        raise SystemExit(f"invalid run: {st}")
+    dt = t1 - t0
+    sps = args.steps / dt
+    ms_per_step = 1e3 * dt / args.steps
+    kp = kt["particles"]
+    part_ms = kp["ms"] / max(kp["launches"], 1)
+    per_launch = ab["per_particle_update"] * sz["particles"]
+    achieved = per_launch / (part_ms * 1e-3) / 1e9
+    traffic = measured_traffic(sz["particles"])
+    out = {
+        "metric": "coupled steps/s: LB MLUPS + MPCD particle-updates/s, % HBM roofline",
+        "value": sps,
+        "unit": "coupled LB steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 particles / f64 LB and cell sums" if p["part_fp"] == 32 else "f64",
+        "data": "synthetic (seeded Poiseuille channel; uniform-in-cell positions, Maxwellian velocities)",
+        "config": {
+            "workload": (f"{args.workload}: D3Q19 {p['n'][0]}x{p['n'][1]}x{p['n'][2]} tau {p['tau']}, "
+                         f"slab y[{p['ylo']},{p['yhi']}) buffers {p['buf_lo']}/{p['buf_hi']}, r {p['refine']}, "
+                         f"{p['ppc']} ppc ({sz['particles']} particles), S {p['substeps']}, "
+                         f"SRD {p['alpha_deg']} deg, feedback {p['feedback']}"),
+            "lb_nodes": sz["nodes"], "particles": sz["particles"], "substeps": p["substeps"],
+        },
+        "lb_mlups": sz["nodes"] * sps / 1e6,
+        "mpcd_particle_updates_per_s": sz["particles"] * p["substeps"] * sps,
+        "coupled_hbm_frac": ab["total"] * sps / 1e9 / HBM_PEAK_GBS,
+        "kernels_ms_per_launch": {k: v["ms"] / max(v["launches"], 1) for k, v in kt.items()},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_particles (fused MPCD step)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": per_launch,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * lbmpcd.h -- C ABI of the MI355X coupled lattice-Boltzmann / multiparticle
+ * collision (LB-MPCD) time step (Montessori, Tiribocchi, Lauricella, Succi,
+ * arXiv 2004.00304).
+ *
+ * The library advances one or more independent channels: a coarse LB solver
+ * over the whole channel (Sec. 2.1, Eq. 1-2; BGK with a body force, periodic
+ * along x and z, half-way bounce-back walls at y = 0 and y = ny) coupled to a
+ * fine MPCD solver in a slab y in [ylo, yhi) (Sec. 2.2, Eq. 3-4: ballistic
+ * streaming, random grid shift, cell binning, stochastic rotation).  The two
+ * are joined by the coupling procedure of Alg. 1 and Alg. 2: after each LB
+ * step the LB velocity is interpolated to the fine cells of the buffer and
+ * the buffer particles are redrawn from the Maxwell-Boltzmann distribution
+ * about it (Box-Muller); optionally the MPCD averages are projected back onto
+ * LB equilibria in the slab interior.
+ *
+ * Conventions (lattice units, dx = dt_LB = 1):
+ *   - node (i,j,k) sits at (i+1/2, j+1/2, k+1/2); walls at y = 0 and y = ny;
+ *   - populations are stored SoA, f[q][z][y][x] with x fastest; D2Q9 order
+ *     (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1); D3Q19
+ *     order rest, +-x, +-y, +-z, (+-1,+-1,0), (+-1,0,+-1), (0,+-1,+-1) in the
+ *     pairs (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) and likewise;
+ *   - the stored LB state is the post-stream population (after the optional
+ *     feedback projection); reported velocity = first moment / rho + g/2;
+ *   - the MPCD collision cell side is a = 1/refine, the MPCD step is
+ *     dt = 1/substeps; particle ids are 0..Np-1 in initial cell order.
+ *
+ * Ownership: the caller owns all device memory (one workspace buffer of
+ * lbmpcd_workspace_size bytes, on the device that is current at init) and
+ * the HIP stream.  The library never allocates device memory; it owns only
+ * the host-side context.  All calls enqueue work on the stream given at init
+ * and return without synchronising, except where a host buffer is read or
+ * written (then the call synchronises the stream).
+ *
+ * Errors: every int-returning call returns 0 (LBMPCD_OK) or a positive code
+ * below; no exception or abort crosses the ABI.  lbmpcd_last_error gives a
+ * message.  Device-side overflow or state corruption is latched and reported
+ * by the next synchronising call (lbmpcd_sync, moments, get_state).
+ * A context is not thread-safe; use one context per stream.
+ */
+#ifndef LBMPCD_H
+#define LBMPCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBMPCD_ABI_VERSION 1u
+
+enum lbmpcd_status {
+    LBMPCD_OK = 0,
+    LBMPCD_E_INVALID = 1,     /* bad argument or parameter set */
+    LBMPCD_E_NOMEM = 2,       /* workspace too small, host allocation failed */
+    LBMPCD_E_DEVICE = 3,      /* a HIP call failed */
+    LBMPCD_E_OVERFLOW = 4,    /* a particle tile overflowed its capacity */
+    LBMPCD_E_STATE = 5,       /* device state is inconsistent */
+    LBMPCD_E_UNSUPPORTED = 6  /* valid but not implemented combination */
+};
+
+/* Fields of lbmpcd_moments / lbmpcd_get_state / lbmpcd_set_state. */
+enum lbmpcd_field {
+    LBMPCD_RHO = 0,        /* double[nz][ny][nx]                                   */
+    LBMPCD_U = 1,          /* double[3][nz][ny][nx], physical velocity (incl. g/2) */
+    LBMPCD_PI = 2,         /* double[6][nz][ny][nx]: xx yy zz xy xz yz, sum f (cc - I/3) */
+    LBMPCD_POP = 3,        /* lb_fp[Q][nz][ny][nx] post-stream populations (get/set) */
+    LBMPCD_PART_POS = 4,   /* double[dim][Np] by particle id (get/set)             */
+    LBMPCD_PART_VEL = 5,   /* double[dim][Np] by particle id (get/set)             */
+    LBMPCD_CELL_ID = 6,    /* int32[Np]: cell of each particle in the last binning */
+    LBMPCD_CELL_COUNT = 7, /* int32[ncells]: occupancy of the last binning         */
+    LBMPCD_CELL_VCM = 8,   /* double[dim][ncells]: centre-of-mass velocity         */
+    LBMPCD_PROFILE = 9,    /* double[R][4]: per fine row sum n, sum v_x, v_y, v_z  */
+    LBMPCD_UFINE = 10,     /* double[dim][nz*r][R][nx*r]: buffer-cell LB velocity  */
+    LBMPCD_STATS = 11      /* int64[8]: lb steps, sampled steps, dropped particles,
+                              misplaced particles, far moves, max tile fill,
+                              particles, cells                                     */
+};
+
+typedef struct lbmpcd_params {
+    uint32_t abi_version;  /* LBMPCD_ABI_VERSION */
+    uint32_t struct_size;  /* sizeof(lbmpcd_params) */
+    int32_t dim;           /* 2: D2Q9, 3: D3Q19 */
+    int32_t n[3];          /* LB nodes nx, ny, nz (nz = 1 in 2D) */
+    int32_t lb_fp;         /* population storage: 32 or 64 */
+    double tau, rho0;      /* BGK relaxation time (> 1/2), initial density */
+    double g[3];           /* body acceleration; LB force density rho*g (Guo forcing) */
+    int32_t walls_y;       /* 1: bounce-back walls at y = 0, ny; 0: periodic y */
+    int32_t mpcd;          /* 0: LB only */
+    int32_t ylo, yhi;      /* MPCD slab rows [ylo, yhi), full x and z extent */
+    int32_t buf_lo, buf_hi;/* buffer depth (LB rows) at the LB-facing faces; a face
+                              on a wall has no buffer */
+    int32_t refine;        /* r: cell side a = 1/r */
+    int32_t substeps;      /* S: MPCD steps per LB step */
+    int32_t ppc;           /* initial particles per cell */
+    int32_t part_fp;       /* particle storage: 32 or 64 (cell sums always 64) */
+    double mass, kT, alpha_deg;
+    int32_t collision;     /* 0: SRD (stochastic rotation); others unsupported */
+    int32_t grid_shift;    /* 1: random grid shift every MPCD step */
+    int32_t feedback;      /* 1: project MPCD averages onto LB equilibria */
+    int32_t init_flow;     /* 0: rest, 1: discrete Poiseuille profile (needs walls) */
+    uint64_t seed;         /* Philox key (low, high ^ instance) */
+    uint32_t instance;     /* instance number inside the key */
+    int32_t tile[3];       /* particle tile in cells per axis; 0 = default */
+    double capacity_factor;/* tile capacity / expected occupancy; 0 = default 1.3 */
+} lbmpcd_params;
+
+/*
+ * Workspace bytes for n_inst channels described by p[0..n_inst-1].  All
+ * channels of one context share dim, lb_fp, part_fp, substeps and refine.
+ * Returns E_INVALID (with no context, see lbmpcd_strerror) for bad params.
+ */
+int lbmpcd_workspace_size(const lbmpcd_params* p, int32_t n_inst, size_t* bytes);
+
+/*
+ * Initialise n_inst channels in the caller's device workspace (bytes at
+ * least lbmpcd_workspace_size) and bind them to hip_stream (a hipStream_t,
+ * may be NULL for the default stream).  Particles: exactly ppc per fine cell,
+ * uniform inside the cell, Maxwell-Boltzmann velocities of variance kT/m
+ * about the initial flow; LB: equilibrium at rho0 and the initial flow.
+ * *out receives the context, or NULL on failure.
+ */
+int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, size_t bytes,
+                void* hip_stream, struct lbmpcd_ctx** out);
+
+/*
+ * Advance every channel by n_lb_steps coupled steps (Alg. 1/2): LB collide
+ * and stream, optional feedback projection, interpolation of the LB
+ * velocity to the buffer cells, then per MPCD step: Maxwell-Boltzmann redraw
+ * in the buffer, streaming with wall / periodic / slab re-wrap conditions,
+ * random grid shift, binning and SRD collision.  Asynchronous.
+ */
+int lbmpcd_step(struct lbmpcd_ctx* c, int32_t n_lb_steps);
+
+/*
+ * Derived fields of instance inst (RHO, U, PI, CELL_ID, CELL_COUNT,
+ * CELL_VCM, PROFILE, UFINE, STATS) into dst (dst_bytes at least the field's
+ * size, see lbmpcd_field_bytes).  dst_on_device = 1: dst is device memory on
+ * the context's device and the call is asynchronous; 0: host memory, the
+ * call synchronises.  Host transfers of fields larger than the workspace's
+ * staging area return E_INVALID.
+ */
+int lbmpcd_moments(struct lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst,
+                   size_t dst_bytes, int32_t dst_on_device);
+
+/* Bytes of a field of instance inst. */
+int lbmpcd_field_bytes(const struct lbmpcd_ctx* c, int32_t field, int32_t inst, size_t* bytes);
+
+/*
+ * Time averaging of the MPCD velocity profile (Sec. 3.1: averaging over
+ * samples suppresses the particle noise).  mode 1: zero the accumulators and
+ * start sampling every MPCD step; 0: stop.
+ */
+int lbmpcd_sample(struct lbmpcd_ctx* c, int32_t mode);
+
+/*
+ * Checkpoint / restore of POP, PART_POS, PART_VEL of instance inst.  get has
+ * the same transfer rules as moments; set replaces the field (particle
+ * positions must lie inside the slab) and leaves the state fully collided.
+ */
+int lbmpcd_get_state(struct lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t bytes,
+                     int32_t dst_on_device);
+int lbmpcd_set_state(struct lbmpcd_ctx* c, int32_t field, int32_t inst, const void* src,
+                     size_t bytes, int32_t src_on_device);
+
+/* Wait for the stream and report latched device errors. */
+int lbmpcd_sync(struct lbmpcd_ctx* c);
+
+/*
+ * Kernel timing with HIP events recorded on the context's stream around every
+ * launch of lbmpcd_step.  mode 1: reset and start; 0: stop.  Kernel classes:
+ * 0 LB collide-stream, 1 feedback/band, 2 interpolation, 3 particle (MPCD)
+ * step.  lbmpcd_timing_read synchronises and writes, for k < n_classes,
+ * out[2k] = summed milliseconds and out[2k+1] = number of launches.
+ */
+int lbmpcd_timing(struct lbmpcd_ctx* c, int32_t mode);
+int lbmpcd_timing_read(struct lbmpcd_ctx* c, double* out, int32_t n_classes);
+
+/* Free the host context; never frees caller memory. */
+void lbmpcd_destroy(struct lbmpcd_ctx* c);
+
+const char* lbmpcd_strerror(int code);
+const char* lbmpcd_last_error(const struct lbmpcd_ctx* c);
+
+typedef struct lbmpcd_ctx lbmpcd_ctx;
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,741 @@
+// api.hip -- host side of the C ABI declared in include/lbmpcd.h: parameter
+// validation, workspace layout, launch sequencing on the caller's stream,
+// transfers and error reporting.  The library allocates no device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmpcd.h"
+#include "common.hpp"
+#include "launch.hpp"
+
+using namespace lbmpcd;
+
+struct lbmpcd_ctx {
+    int n_inst = 0, dim = 2, lb_fp = 64, part_fp = 64, S = 1, Q = 9, mpcd = 0;
+    std::vector<lbmpcd_params> params;
+    std::vector<InstDesc> desc;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    InstDesc* d_desc = nullptr;
+    int* d_tile_inst = nullptr;
+    void* f[2] = {nullptr, nullptr};
+    int fcur = 0;
+    PartBuf part[2];
+    int pcur = 0;
+    uint32_t* fill[2] = {nullptr, nullptr};
+    double* ub = nullptr;
+    double* uf = nullptr;
+    double* acc = nullptr;
+    double* prof = nullptr;
+    DevStats* stats = nullptr;
+    long long* clock = nullptr;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    size_t prof_bytes = 0, acc_bytes = 0;
+    long long total_nodes = 0, total_band = 0, total_ufine = 0, total_tiles = 0, total_slots = 0,
+              total_particles = 0, total_slab = 0;
+    int ppt = 4;
+    size_t lds = 0;
+    long long t = 0;
+    bool pending = false, sampling = false, any_feedback = false;
+    long long sampled_steps = 0;
+    std::string err;
+    int sticky = 0;
+    // kernel timing (host-side event objects only)
+    bool timing = false;
+    struct Mark { int cls; hipEvent_t a, b; };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> pool;
+    double timing_ms[4] = {0, 0, 0, 0};
+    long long timing_n[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(lbmpcd_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg; else g_err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(ctx, LBMPCD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Geometry {
+    // per-instance derived sizes
+    int R = 0, Cx = 0, Cz = 1, CyB = 0, ywrap = 0, bot_wall = 0, top_wall = 0;
+    int Tx = 1, Ty = 1, Tz = 1, ntx = 0, nty = 0, ntz = 0, cap = 0, nct = 0;
+    long long ncells = 0, Np = 0, ntiles = 0, init_per = 0;
+    int by0 = 0, nyb = 0, NB = 0;
+    long long nband = 0, nufine = 0, nslab = 0;
+};
+
+int choose_tile(const lbmpcd_params& p, Geometry& g, std::string& msg) {
+    int T[3] = {p.tile[0], p.tile[1], p.tile[2]};
+    if (T[0] <= 0 || T[1] <= 0 || (p.dim == 3 && T[2] <= 0)) {
+        // aim at ~640 expected particles per tile
+        int target = std::max(8, std::min(MAX_NCT, 640 / std::max(1, p.ppc)));
+        static const int opts3[][3] = {{2, 2, 2}, {4, 2, 2}, {4, 4, 2}, {4, 4, 4}, {4, 4, 8}};
+        static const int opts2[][3] = {{4, 2, 1}, {4, 4, 1}, {8, 4, 1}, {8, 8, 1}, {16, 8, 1}};
+        const int(*opts)[3] = p.dim == 3 ? opts3 : opts2;
+        int pick = 4;
+        for (int i = 0; i < 5; ++i) {
+            if (opts[i][0] * opts[i][1] * opts[i][2] >= target) { pick = i; break; }
+        }
+        T[0] = opts[pick][0]; T[1] = opts[pick][1]; T[2] = opts[pick][2];
+    }
+    if (p.dim == 2) T[2] = 1;
+    g.Tx = T[0]; g.Ty = T[1]; g.Tz = T[2];
+    g.nct = g.Tx * g.Ty * g.Tz;
+    if (g.nct > MAX_NCT) { msg = "tile has more than 128 cells"; return 1; }
+    double cf = p.capacity_factor > 0 ? p.capacity_factor : 1.3;
+    long long cap = (long long)std::ceil(cf * p.ppc * g.nct) + 64;
+    cap = (long long)align_up((size_t)cap, 64);
+    if (cap > 8 * WG) { msg = "tile capacity exceeds 2048 particles; use a smaller tile"; return 1; }
+    g.cap = (int)cap;
+    return 0;
+}
+
+int geometry(const lbmpcd_params& p, Geometry& g, std::string& msg) {
+    if (!p.mpcd) return 0;
+    const int r = p.refine;
+    g.R = (p.yhi - p.ylo) * r;
+    g.Cx = p.n[0] * r;
+    g.Cz = p.dim == 3 ? p.n[2] * r : 1;
+    g.ywrap = (!p.walls_y && p.ylo == 0 && p.yhi == p.n[1] && p.buf_lo == 0 && p.buf_hi == 0) ? 1 : 0;
+    g.CyB = g.ywrap ? g.R : g.R + 1;
+    g.bot_wall = (p.walls_y && p.ylo == 0) ? 1 : 0;
+    g.top_wall = (p.walls_y && p.yhi == p.n[1]) ? 1 : 0;
+    g.ncells = (long long)g.Cx * g.CyB * g.Cz;
+    g.Np = (long long)g.Cx * g.R * g.Cz * p.ppc;
+    if (choose_tile(p, g, msg)) return 1;
+    g.ntx = (g.Cx + g.Tx - 1) / g.Tx;
+    g.nty = (g.CyB + g.Ty - 1) / g.Ty;
+    g.ntz = (g.Cz + g.Tz - 1) / g.Tz;
+    g.ntiles = (long long)g.ntx * g.nty * g.ntz;
+    g.init_per = (g.Np + g.ntiles - 1) / g.ntiles;
+    if (g.init_per > g.cap) { msg = "initial placement exceeds the tile capacity"; return 1; }
+    g.by0 = std::max(p.ylo - 1, 0);
+    int by1 = std::min(p.yhi + 1, p.n[1]);
+    g.nyb = by1 - g.by0;
+    g.nband = (long long)p.n[0] * g.nyb * p.n[2];
+    g.NB = (p.buf_lo + p.buf_hi) * r;
+    g.nufine = (long long)g.Cx * g.NB * g.Cz;
+    g.nslab = (long long)p.n[0] * (p.yhi - p.ylo) * p.n[2];
+    return 0;
+}
+
+int validate_one(const lbmpcd_params& p, std::string& msg) {
+    if (p.abi_version != LBMPCD_ABI_VERSION) { msg = "abi_version mismatch"; return LBMPCD_E_INVALID; }
+    if (p.struct_size != sizeof(lbmpcd_params)) { msg = "struct_size mismatch"; return LBMPCD_E_INVALID; }
+    if (p.dim != 2 && p.dim != 3) { msg = "dim must be 2 or 3"; return LBMPCD_E_INVALID; }
+    if (p.n[0] < 1 || p.n[1] < 1 || p.n[2] < 1) { msg = "n must be positive"; return LBMPCD_E_INVALID; }
+    if (p.dim == 2 && (p.n[2] != 1 || p.g[2] != 0.0)) { msg = "2D needs nz = 1 and g_z = 0"; return LBMPCD_E_INVALID; }
+    if (p.lb_fp != 32 && p.lb_fp != 64) { msg = "lb_fp must be 32 or 64"; return LBMPCD_E_INVALID; }
+    if (!(p.tau > 0.5)) { msg = "tau must exceed 1/2"; return LBMPCD_E_INVALID; }
+    if (!(p.rho0 > 0.0)) { msg = "rho0 must be positive"; return LBMPCD_E_INVALID; }
+    if (p.init_flow && !p.walls_y) { msg = "init_flow needs walls"; return LBMPCD_E_INVALID; }
+    if ((long long)p.n[0] * p.n[1] * p.n[2] > (1LL << 40)) { msg = "domain too large"; return LBMPCD_E_INVALID; }
+    if (!p.mpcd) return 0;
+    if (p.collision != 0) { msg = "only the SRD collision (0) is implemented"; return LBMPCD_E_UNSUPPORTED; }
+    if (p.part_fp != 32 && p.part_fp != 64) { msg = "part_fp must be 32 or 64"; return LBMPCD_E_INVALID; }
+    if (p.ylo < 0 || p.yhi > p.n[1] || p.ylo >= p.yhi) { msg = "slab outside the domain"; return LBMPCD_E_INVALID; }
+    if (p.refine < 1 || p.substeps < 1 || p.ppc < 1) { msg = "refine, substeps, ppc must be >= 1"; return LBMPCD_E_INVALID; }
+    if (p.substeps > 255) { msg = "at most 255 substeps"; return LBMPCD_E_INVALID; }
+    if (p.buf_lo < 0 || p.buf_hi < 0 || p.buf_lo + p.buf_hi > p.yhi - p.ylo) { msg = "buffers exceed the slab"; return LBMPCD_E_INVALID; }
+    const bool bw = p.walls_y && p.ylo == 0, tw = p.walls_y && p.yhi == p.n[1];
+    if ((bw && p.buf_lo) || (tw && p.buf_hi)) { msg = "a wall face has no buffer"; return LBMPCD_E_INVALID; }
+    if ((bw || tw) && p.g[1] != 0.0) { msg = "walls in the slab need g_y = 0"; return LBMPCD_E_INVALID; }
+    if (!(p.mass > 0.0) || p.kT < 0.0) { msg = "mass must be positive, kT non-negative"; return LBMPCD_E_INVALID; }
+    const bool ywrap = !p.walls_y && p.ylo == 0 && p.yhi == p.n[1] && p.buf_lo == 0 && p.buf_hi == 0;
+    if (!p.walls_y && !ywrap && (p.ylo < 1 || p.yhi > p.n[1] - 1)) {
+        msg = "without walls the slab must be the whole periodic box or stay one row clear of y = 0, ny";
+        return LBMPCD_E_UNSUPPORTED;
+    }
+    Geometry g;
+    if (geometry(p, g, msg)) return LBMPCD_E_INVALID;
+    if (g.Np >= (1LL << 32) - 1) { msg = "too many particles for 32-bit ids"; return LBMPCD_E_INVALID; }
+    return 0;
+}
+
+struct Layout {
+    size_t desc, tile_inst, f0, f1, ub, uf, acc, prof, fill0, fill1, stats, clock, scratch, end;
+    size_t part[2][7];
+    size_t acc_bytes, prof_bytes, scratch_bytes;
+};
+
+int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, long long tot[7], std::string& msg) {
+    D.assign(n, InstDesc{});
+    long long node = 0, band = 0, ufine = 0, tiles = 0, slots = 0, parts = 0, slab = 0, prow = 0;
+    size_t max_field = 0;
+    const int Q = p[0].dim == 2 ? 9 : 19;
+    for (int i = 0; i < n; ++i) {
+        const lbmpcd_params& q = p[i];
+        Geometry g;
+        if (geometry(q, g, msg)) return LBMPCD_E_INVALID;
+        InstDesc& d = D[i];
+        d.nx = q.n[0]; d.ny = q.n[1]; d.nz = q.n[2]; d.walls_y = q.walls_y;
+        d.N = (long long)q.n[0] * q.n[1] * q.n[2];
+        d.node_off = node;
+        d.omega = 1.0 / q.tau;
+        d.src = 1.0 - 0.5 / q.tau;
+        for (int k = 0; k < 3; ++k) d.g[k] = q.g[k];
+        d.rho0 = q.rho0; d.tau = q.tau; d.init_flow = q.init_flow; d.mpcd = q.mpcd;
+        d.ylo = q.ylo; d.yhi = q.yhi; d.buf_lo = q.buf_lo; d.buf_hi = q.buf_hi;
+        d.r = q.refine; d.R = g.R; d.Cx = g.Cx; d.Cz = g.Cz; d.CyB = g.CyB; d.ywrap = g.ywrap;
+        d.bot_wall = g.bot_wall; d.top_wall = g.top_wall; d.ppc = q.ppc; d.feedback = q.feedback;
+        d.grid_shift = q.grid_shift;
+        d.ncells = g.ncells; d.Np = g.Np; d.part_off = parts; d.init_per = g.init_per;
+        d.Tx = g.Tx; d.Ty = g.Ty; d.Tz = g.Tz; d.ntx = g.ntx; d.nty = g.nty; d.ntz = g.ntz;
+        d.cap = g.cap; d.nct = g.nct; d.ntiles = g.ntiles; d.tile_off = tiles; d.slot_off = slots;
+        d.by0 = g.by0; d.nyb = g.nyb; d.band_off = band; d.NB = g.NB; d.ufine_off = ufine;
+        d.nslab = g.nslab; d.acc_off = slab; d.prof_off = prow;
+        d.a = q.mpcd ? 1.0 / q.refine : 0.0;
+        d.dt = q.mpcd ? 1.0 / q.substeps : 0.0;
+        for (int k = 0; k < 3; ++k) { d.gh[k] = 0.5 * q.g[k] * d.dt; d.gdt[k] = q.g[k] * d.dt; }
+        d.sd = q.mass > 0 ? std::sqrt(q.kT / q.mass) : 0.0;
+        const double alpha = q.alpha_deg * 3.141592653589793 / 180.0;
+        d.cos_a = std::cos(alpha);
+        d.sin_a = std::sin(alpha);
+        d.mass = q.mass; d.kT = q.kT;
+        d.key0 = (uint32_t)(q.seed & 0xFFFFFFFFu);
+        d.key1 = (uint32_t)(q.seed >> 32) ^ q.instance;
+        node += d.N;
+        band += g.nband;
+        ufine += g.nufine;
+        tiles += g.ntiles;
+        slots += g.ntiles * (long long)g.cap;
+        parts += g.Np;
+        slab += g.nslab;
+        prow += (long long)NCOPY * g.R;
+        size_t fsz = std::max<size_t>((size_t)d.N * 8 * 6, (size_t)d.N * Q * 8);
+        fsz = std::max<size_t>(fsz, (size_t)g.Np * 8 * q.dim);
+        fsz = std::max<size_t>(fsz, (size_t)g.ncells * 8 * q.dim);
+        max_field = std::max(max_field, fsz);
+    }
+    if (slots >= (1LL << 32) - 1) { msg = "too many particle slots for 32-bit slot indices"; return LBMPCD_E_INVALID; }
+    tot[0] = node; tot[1] = band; tot[2] = ufine; tot[3] = tiles; tot[4] = slots; tot[5] = parts; tot[6] = slab;
+    const int dim = p[0].dim;
+    const size_t lbw = p[0].lb_fp == 64 ? 8 : 4, pw = p[0].part_fp == 64 ? 8 : 4;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1), 256); return at; };
+    L.desc = take(sizeof(InstDesc) * n);
+    L.tile_inst = take(4 * (size_t)tiles);
+    L.f0 = take((size_t)Q * node * lbw);
+    L.f1 = take((size_t)Q * node * lbw);
+    L.ub = take(3 * (size_t)band * 8);
+    L.uf = take((size_t)dim * ufine * 8);
+    L.acc_bytes = 4 * (size_t)slab * 8;
+    L.acc = take(L.acc_bytes);
+    L.prof_bytes = 4 * (size_t)prow * 8;
+    L.prof = take(L.prof_bytes);
+    L.fill0 = take(4 * (size_t)tiles);
+    L.fill1 = take(4 * (size_t)tiles);
+    for (int b = 0; b < 2; ++b) {
+        for (int k = 0; k < 6; ++k) L.part[b][k] = (k % 3 < dim) ? take((size_t)slots * pw) : 0;
+        L.part[b][6] = take((size_t)slots * 4);
+    }
+    L.stats = take(sizeof(DevStats));
+    L.clock = take(sizeof(long long));
+    L.scratch_bytes = std::min<size_t>(align_up(max_field, 256), (size_t)64 << 20);
+    L.scratch = take(L.scratch_bytes);
+    L.end = o;
+    return 0;
+}
+
+int validate_all(const lbmpcd_params* p, int n, std::string& msg) {
+    if (!p || n < 1) { msg = "need at least one instance"; return LBMPCD_E_INVALID; }
+    for (int i = 0; i < n; ++i) {
+        int e = validate_one(p[i], msg);
+        if (e) { msg = "instance " + std::to_string(i) + ": " + msg; return e; }
+        if (p[i].dim != p[0].dim || p[i].lb_fp != p[0].lb_fp || p[i].mpcd != p[0].mpcd ||
+            (p[0].mpcd && (p[i].part_fp != p[0].part_fp || p[i].substeps != p[0].substeps))) {
+            msg = "all instances must share dim, lb_fp, mpcd, part_fp and substeps";
+            return LBMPCD_E_INVALID;
+        }
+    }
+    return 0;
+}
+
+hipEvent_t take_event(lbmpcd_ctx* c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Fold recorded event pairs into the per-class sums (synchronises).
+int drain_marks(lbmpcd_ctx* c) {
+    if (c->marks.empty()) return 0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto& m : c->marks) {
+        float ms = 0.f;
+        if (m.a && m.b && hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+            c->timing_ms[m.cls] += ms;
+            c->timing_n[m.cls] += 1;
+        }
+        if (m.a) c->pool.push_back(m.a);
+        if (m.b) c->pool.push_back(m.b);
+    }
+    c->marks.clear();
+    return 0;
+}
+
+// Launch `f` bracketed by timing events of class `cls` when timing is on.
+template <typename F>
+hipError_t timed(lbmpcd_ctx* c, int cls, F f) {
+    if (!c->timing) return f();
+    if (c->marks.size() > 4096) drain_marks(c);
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (a) (void)hipEventRecord(a, c->stream);
+    hipError_t e = f();
+    if (b) (void)hipEventRecord(b, c->stream);
+    c->marks.push_back({cls, a, b});
+    return e;
+}
+
+int finalize(lbmpcd_ctx* c) {
+    if (!c->pending || !c->mpcd) return 0;
+    ParticleLaunch L{};
+    L.dim = c->dim; L.part_fp = c->part_fp; L.ppt = c->ppt; L.mode = 1;
+    L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
+    L.in = c->part[c->pcur]; L.out = c->part[c->pcur];
+    L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
+    L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
+    L.stats = c->stats; L.clock = c->clock;
+    L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
+    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds;
+    HIPCHK(c, launch_particles(L, c->stream));
+    c->pending = false;
+    return 0;
+}
+
+int check_device_errors(lbmpcd_ctx* c) {
+    DevStats s;
+    HIPCHK(c, hipMemcpyAsync(&s, c->stats, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (s.dropped) {
+        c->sticky = LBMPCD_E_OVERFLOW;
+        c->err = std::to_string(s.dropped) + " particles dropped by tile overflow (raise capacity_factor)";
+    } else if (s.misplaced) {
+        c->sticky = LBMPCD_E_STATE;
+        c->err = std::to_string(s.misplaced) + " particles found outside their tile";
+    }
+    return c->sticky;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbmpcd_strerror(int code) {
+    switch (code) {
+        case LBMPCD_OK: return "ok";
+        case LBMPCD_E_INVALID: return "invalid argument";
+        case LBMPCD_E_NOMEM: return "workspace too small or host allocation failed";
+        case LBMPCD_E_DEVICE: return "HIP error";
+        case LBMPCD_E_OVERFLOW: return "particle tile overflow";
+        case LBMPCD_E_STATE: return "inconsistent device state";
+        case LBMPCD_E_UNSUPPORTED: return "unsupported parameter combination";
+        default: return "unknown error";
+    }
+}
+
+const char* lbmpcd_last_error(const lbmpcd_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+int lbmpcd_workspace_size(const lbmpcd_params* p, int32_t n_inst, size_t* bytes) {
+    if (!bytes) return fail(nullptr, LBMPCD_E_INVALID, "bytes is null");
+    std::string msg;
+    int e = validate_all(p, n_inst, msg);
+    if (e) return fail(nullptr, e, msg);
+    std::vector<InstDesc> D;
+    Layout L;
+    long long tot[7];
+    e = build(p, n_inst, D, L, tot, msg);
+    if (e) return fail(nullptr, e, msg);
+    *bytes = L.end;
+    return 0;
+}
+
+int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, size_t bytes, void* hip_stream,
+                lbmpcd_ctx** out) {
+    if (!out) return fail(nullptr, LBMPCD_E_INVALID, "out is null");
+    *out = nullptr;
+    std::string msg;
+    int e = validate_all(p, n_inst, msg);
+    if (e) return fail(nullptr, e, msg);
+    lbmpcd_ctx* c = new (std::nothrow) lbmpcd_ctx();
+    if (!c) return fail(nullptr, LBMPCD_E_NOMEM, "host allocation failed");
+    Layout L;
+    long long tot[7];
+    e = build(p, n_inst, c->desc, L, tot, msg);
+    if (e) { delete c; return fail(nullptr, e, msg); }
+    if (!dev_workspace || bytes < L.end) {
+        delete c;
+        return fail(nullptr, LBMPCD_E_NOMEM, "workspace is null or smaller than lbmpcd_workspace_size");
+    }
+    c->n_inst = n_inst;
+    c->params.assign(p, p + n_inst);
+    c->dim = p[0].dim; c->lb_fp = p[0].lb_fp; c->part_fp = p[0].part_fp; c->S = p[0].substeps;
+    c->Q = c->dim == 2 ? 9 : 19; c->mpcd = p[0].mpcd;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return fail(nullptr, LBMPCD_E_DEVICE, "no HIP device"); }
+    c->ws = (char*)dev_workspace;
+    c->ws_bytes = bytes;
+    c->total_nodes = tot[0]; c->total_band = tot[1]; c->total_ufine = tot[2]; c->total_tiles = tot[3];
+    c->total_slots = tot[4]; c->total_particles = tot[5]; c->total_slab = tot[6];
+    c->d_desc = (InstDesc*)(c->ws + L.desc);
+    c->d_tile_inst = (int*)(c->ws + L.tile_inst);
+    c->f[0] = c->ws + L.f0;
+    c->f[1] = c->ws + L.f1;
+    c->ub = (double*)(c->ws + L.ub);
+    c->uf = (double*)(c->ws + L.uf);
+    c->acc = (double*)(c->ws + L.acc);
+    c->prof = (double*)(c->ws + L.prof);
+    c->acc_bytes = L.acc_bytes;
+    c->prof_bytes = L.prof_bytes;
+    c->fill[0] = (uint32_t*)(c->ws + L.fill0);
+    c->fill[1] = (uint32_t*)(c->ws + L.fill1);
+    for (int b = 0; b < 2; ++b) {
+        for (int k = 0; k < 3; ++k) {
+            c->part[b].pos[k] = L.part[b][k] ? c->ws + L.part[b][k] : nullptr;
+            c->part[b].vel[k] = L.part[b][3 + k] ? c->ws + L.part[b][3 + k] : nullptr;
+        }
+        c->part[b].id = (uint32_t*)(c->ws + L.part[b][6]);
+    }
+    c->stats = (DevStats*)(c->ws + L.stats);
+    c->clock = (long long*)(c->ws + L.clock);
+    c->scratch = c->ws + L.scratch;
+    c->scratch_bytes = L.scratch_bytes;
+    int cap_max = 64;
+    for (const InstDesc& d : c->desc) {
+        cap_max = std::max(cap_max, d.cap);
+        if (d.feedback) c->any_feedback = true;
+    }
+    c->ppt = cap_max <= 2 * WG ? 2 : (cap_max <= 4 * WG ? 4 : 8);
+    c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max);
+
+    // tile -> instance table
+    std::vector<int> tinst((size_t)std::max<long long>(c->total_tiles, 1));
+    for (int i = 0; i < n_inst; ++i)
+        for (long long T = 0; T < c->desc[i].ntiles; ++T) tinst[(size_t)(c->desc[i].tile_off + T)] = i;
+    hipStream_t s = c->stream;
+    auto chk = [&](hipError_t he, const char* what) -> int {
+        if (he != hipSuccess) {
+            g_err = std::string(what) + ": " + hipGetErrorString(he);
+            return LBMPCD_E_DEVICE;
+        }
+        return 0;
+    };
+    const long long clock0 = -1;
+    int rc = 0;
+    rc = rc ? rc : chk(hipMemcpyAsync(c->d_desc, c->desc.data(), sizeof(InstDesc) * n_inst, hipMemcpyHostToDevice, s), "desc");
+    rc = rc ? rc : chk(hipMemcpyAsync(c->d_tile_inst, tinst.data(), 4 * (size_t)c->total_tiles, hipMemcpyHostToDevice, s), "tile table");
+    rc = rc ? rc : chk(hipMemcpyAsync(c->clock, &clock0, sizeof(clock0), hipMemcpyHostToDevice, s), "clock");
+    rc = rc ? rc : chk(launch_zero(c->stats, sizeof(DevStats), s), "stats");
+    rc = rc ? rc : chk(launch_zero(c->acc, c->acc_bytes, s), "acc");
+    rc = rc ? rc : chk(launch_zero(c->prof, c->prof_bytes, s), "prof");
+    rc = rc ? rc : chk(launch_zero(c->ub, 3 * 8 * (size_t)c->total_band, s), "ub");
+    rc = rc ? rc : chk(launch_zero(c->uf, (size_t)c->dim * 8 * c->total_ufine, s), "uf");
+    rc = rc ? rc : chk(launch_lb_init(c->dim, c->lb_fp, c->d_desc, n_inst, c->total_nodes, c->f[0], s), "lb init");
+    if (c->mpcd) {
+        rc = rc ? rc : chk(launch_fill_sequential(c->d_desc, n_inst, c->total_tiles, c->fill[0], c->fill[1], s), "fill");
+        rc = rc ? rc : chk(launch_part_init(c->dim, c->part_fp, c->d_desc, n_inst, c->total_particles, c->part[0], s), "particles");
+    }
+    rc = rc ? rc : chk(hipStreamSynchronize(s), "init sync");
+    if (rc) { delete c; return rc; }
+    *out = c;
+    return 0;
+}
+
+int lbmpcd_step(lbmpcd_ctx* c, int32_t n_lb_steps) {
+    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
+    if (c->sticky) return c->sticky;
+    if (n_lb_steps < 0) return fail(c, LBMPCD_E_INVALID, "negative step count");
+    hipStream_t s = c->stream;
+    for (int it = 0; it < n_lb_steps; ++it) {
+        HIPCHK(c, timed(c, 0, [&] {
+                   return launch_lb_step(c->dim, c->lb_fp, c->d_desc, c->n_inst, c->total_nodes, c->f[c->fcur],
+                                         c->f[c->fcur ^ 1], c->clock, s);
+               }));
+        c->fcur ^= 1;
+        if (c->mpcd) {
+            HIPCHK(c, timed(c, 1, [&] {
+                       return launch_band(c->dim, c->lb_fp, c->d_desc, c->n_inst, c->total_band, c->f[c->fcur],
+                                          c->acc, c->ub, c->any_feedback ? 1 : 0, s);
+                   }));
+            HIPCHK(c, timed(c, 2, [&] {
+                       return launch_interp(c->dim, c->d_desc, c->n_inst, c->total_ufine, c->ub, c->uf, s);
+                   }));
+            for (int sub = 0; sub < c->S; ++sub) {
+                ParticleLaunch L{};
+                L.dim = c->dim; L.part_fp = c->part_fp; L.ppt = c->ppt;
+                L.mode = (sub == 0 && !c->pending) ? 2 : 3;
+                L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
+                L.in = c->part[c->pcur]; L.out = c->part[c->pcur ^ 1];
+                L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
+                L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
+                L.stats = c->stats; L.clock = c->clock;
+                L.coll_dt = sub > 0 ? 0 : -1;
+                L.coll_s = sub > 0 ? sub - 1 : c->S - 1;
+                L.str_s = sub;
+                L.do_fb = c->any_feedback ? 1 : 0;
+                L.do_prof = c->sampling ? 1 : 0;
+                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds;
+                HIPCHK(c, timed(c, 3, [&] { return launch_particles(L, s); }));
+                c->pcur ^= 1;
+                c->pending = true;
+            }
+        }
+        c->t++;
+        if (c->sampling) c->sampled_steps++;
+    }
+    return 0;
+}
+
+int lbmpcd_field_bytes(const lbmpcd_ctx* c, int32_t field, int32_t inst, size_t* bytes) {
+    if (!c || !bytes || inst < 0 || inst >= c->n_inst) return LBMPCD_E_INVALID;
+    const InstDesc& d = c->desc[inst];
+    const size_t N = (size_t)d.N;
+    switch (field) {
+        case LBMPCD_RHO: *bytes = N * 8; break;
+        case LBMPCD_U: *bytes = 3 * N * 8; break;
+        case LBMPCD_PI: *bytes = 6 * N * 8; break;
+        case LBMPCD_POP: *bytes = (size_t)c->Q * N * (c->lb_fp == 64 ? 8 : 4); break;
+        case LBMPCD_PART_POS:
+        case LBMPCD_PART_VEL: *bytes = (size_t)c->dim * d.Np * 8; break;
+        case LBMPCD_CELL_ID: *bytes = (size_t)d.Np * 4; break;
+        case LBMPCD_CELL_COUNT: *bytes = (size_t)d.ncells * 4; break;
+        case LBMPCD_CELL_VCM: *bytes = (size_t)c->dim * d.ncells * 8; break;
+        case LBMPCD_PROFILE: *bytes = (size_t)d.R * 4 * 8; break;
+        case LBMPCD_UFINE: *bytes = (size_t)c->dim * d.Cx * d.R * d.Cz * 8; break;
+        case LBMPCD_STATS: *bytes = 8 * 8; break;
+        default: return LBMPCD_E_INVALID;
+    }
+    return 0;
+}
+
+namespace {
+
+// Produce a derived field into device memory `dst`.
+int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes) {
+    const InstDesc& d = c->desc[inst];
+    hipStream_t s = c->stream;
+    const long long slots = d.ntiles * (long long)d.cap;
+    const long long tl = c->t - 1;
+    const int sl = c->S - 1;
+    switch (field) {
+        case LBMPCD_RHO:
+            HIPCHK(c, launch_moments(c->dim, c->lb_fp, c->d_desc, inst, d.N, c->f[c->fcur], (double*)dst, nullptr, nullptr, s));
+            return 0;
+        case LBMPCD_U:
+            HIPCHK(c, launch_moments(c->dim, c->lb_fp, c->d_desc, inst, d.N, c->f[c->fcur], nullptr, (double*)dst, nullptr, s));
+            return 0;
+        case LBMPCD_PI:
+            HIPCHK(c, launch_moments(c->dim, c->lb_fp, c->d_desc, inst, d.N, c->f[c->fcur], nullptr, nullptr, (double*)dst, s));
+            return 0;
+        case LBMPCD_POP: {
+            const size_t w = c->lb_fp == 64 ? 8 : 4;
+            HIPCHK(c, hipMemcpyAsync(dst, (char*)c->f[c->fcur] + (size_t)d.node_off * c->Q * w, nbytes,
+                                     hipMemcpyDeviceToDevice, s));
+            return 0;
+        }
+        case LBMPCD_PART_POS:
+        case LBMPCD_PART_VEL:
+            if (int e = finalize(c)) return e;
+            HIPCHK(c, launch_gather(c->dim, c->part_fp, c->d_desc, inst, c->part[c->pcur], c->fill[c->pcur],
+                                    field == LBMPCD_PART_POS ? (double*)dst : nullptr,
+                                    field == LBMPCD_PART_VEL ? (double*)dst : nullptr, nullptr, slots, tl, sl, s));
+            return 0;
+        case LBMPCD_CELL_ID:
+            if (c->t == 0) return fail(c, LBMPCD_E_STATE, "no binning before the first step");
+            HIPCHK(c, launch_gather(c->dim, c->part_fp, c->d_desc, inst, c->part[c->pcur], c->fill[c->pcur],
+                                    nullptr, nullptr, (int*)dst, slots, tl, sl, s));
+            return 0;
+        case LBMPCD_CELL_COUNT:
+            if (c->t == 0) return fail(c, LBMPCD_E_STATE, "no binning before the first step");
+            HIPCHK(c, launch_zero(dst, nbytes, s));
+            HIPCHK(c, launch_cell_count(c->dim, c->part_fp, c->d_desc, inst, c->part[c->pcur], c->fill[c->pcur],
+                                        (int*)dst, slots, tl, sl, s));
+            return 0;
+        case LBMPCD_CELL_VCM: {
+            if (!c->pending) return fail(c, LBMPCD_E_STATE, "cell velocities exist only right after lbmpcd_step");
+            HIPCHK(c, launch_zero(dst, nbytes, s));
+            ParticleLaunch L{};
+            L.dim = c->dim; L.part_fp = c->part_fp; L.ppt = c->ppt; L.mode = 1;
+            L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
+            L.in = c->part[c->pcur]; L.out = c->part[c->pcur];
+            L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
+            L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
+            L.stats = c->stats; L.clock = c->clock;
+            L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
+            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds;
+            HIPCHK(c, launch_particles(L, s));
+            c->pending = false;
+            return 0;
+        }
+        case LBMPCD_PROFILE:
+            HIPCHK(c, launch_profile_reduce(c->d_desc, inst, d.R, c->prof, (double*)dst, s));
+            return 0;
+        case LBMPCD_UFINE: {
+            // expand the buffer rows to the full slab layout [dim][Cz][R][Cx]
+            HIPCHK(c, launch_zero(dst, nbytes, s));
+            const size_t row = (size_t)d.Cx * 8;
+            for (int q = 0; q < c->dim; ++q)
+                for (int K = 0; K < d.Cz; ++K)
+                    for (int Jb = 0; Jb < d.NB; ++Jb) {
+                        const int J = Jb < d.buf_lo * d.r ? Jb : Jb + (d.R - d.NB);
+                        const double* src = c->uf + d.ufine_off * c->dim + (size_t)q * d.Cx * d.NB * d.Cz +
+                                            ((size_t)K * d.NB + Jb) * d.Cx;
+                        double* to = (double*)dst + (size_t)q * d.Cx * d.R * d.Cz + ((size_t)K * d.R + J) * d.Cx;
+                        HIPCHK(c, hipMemcpyAsync(to, src, row, hipMemcpyDeviceToDevice, s));
+                    }
+            return 0;
+        }
+        default:
+            return fail(c, LBMPCD_E_INVALID, "unknown field");
+    }
+}
+
+}  // namespace
+
+int lbmpcd_moments(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t dst_bytes, int32_t on_dev) {
+    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
+    if (inst < 0 || inst >= c->n_inst) return fail(c, LBMPCD_E_INVALID, "bad instance");
+    size_t need = 0;
+    if (lbmpcd_field_bytes(c, field, inst, &need)) return fail(c, LBMPCD_E_INVALID, "bad field");
+    if (!dst || dst_bytes < need) return fail(c, LBMPCD_E_INVALID, "destination too small");
+    if (field == LBMPCD_STATS) {
+        DevStats s;
+        HIPCHK(c, hipMemcpyAsync(&s, c->stats, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        int64_t v[8] = {c->t, c->sampled_steps, (int64_t)s.dropped, (int64_t)s.misplaced, (int64_t)s.far_moves,
+                        (int64_t)s.max_fill, c->desc[inst].Np, c->desc[inst].ncells};
+        if (on_dev) HIPCHK(c, hipMemcpy(dst, v, sizeof(v), hipMemcpyHostToDevice));
+        else std::memcpy(dst, v, sizeof(v));
+        return 0;
+    }
+    if (!c->mpcd && field >= LBMPCD_PART_POS && field != LBMPCD_STATS)
+        return fail(c, LBMPCD_E_INVALID, "no particles in this context");
+    if (on_dev) return produce(c, field, inst, dst, need);
+    if (need > c->scratch_bytes) return fail(c, LBMPCD_E_INVALID, "field too large for a host transfer; pass device memory");
+    if (int e = produce(c, field, inst, c->scratch, need)) return e;
+    HIPCHK(c, hipMemcpyAsync(dst, c->scratch, need, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return check_device_errors(c);
+}
+
+int lbmpcd_get_state(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t bytes, int32_t on_dev) {
+    if (field != LBMPCD_POP && field != LBMPCD_PART_POS && field != LBMPCD_PART_VEL)
+        return fail(c, LBMPCD_E_INVALID, "get_state handles POP, PART_POS, PART_VEL");
+    return lbmpcd_moments(c, field, inst, dst, bytes, on_dev);
+}
+
+int lbmpcd_set_state(lbmpcd_ctx* c, int32_t field, int32_t inst, const void* src, size_t bytes, int32_t on_dev) {
+    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
+    if (inst < 0 || inst >= c->n_inst) return fail(c, LBMPCD_E_INVALID, "bad instance");
+    if (field != LBMPCD_POP && field != LBMPCD_PART_POS && field != LBMPCD_PART_VEL)
+        return fail(c, LBMPCD_E_INVALID, "set_state handles POP, PART_POS, PART_VEL");
+    size_t need = 0;
+    lbmpcd_field_bytes(c, field, inst, &need);
+    if (!src || bytes < need) return fail(c, LBMPCD_E_INVALID, "source too small");
+    const InstDesc& d = c->desc[inst];
+    hipStream_t s = c->stream;
+    if (field == LBMPCD_POP) {
+        const size_t w = c->lb_fp == 64 ? 8 : 4;
+        HIPCHK(c, hipMemcpyAsync((char*)c->f[c->fcur] + (size_t)d.node_off * c->Q * w, src, need,
+                                 on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return 0;
+    }
+    if (!c->mpcd) return fail(c, LBMPCD_E_INVALID, "no particles in this context");
+    if (int e = finalize(c)) return e;
+    const void* dsrc = src;
+    if (!on_dev) {
+        if (need > c->scratch_bytes) return fail(c, LBMPCD_E_INVALID, "field too large for a host transfer");
+        HIPCHK(c, hipMemcpyAsync(c->scratch, src, need, hipMemcpyHostToDevice, s));
+        dsrc = c->scratch;
+    }
+    HIPCHK(c, launch_set_field(c->dim, c->part_fp, c->d_desc, inst, c->part[c->pcur], c->fill[c->pcur],
+                               field == LBMPCD_PART_POS ? 0 : 1, (const double*)dsrc,
+                               d.ntiles * (long long)d.cap, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return 0;
+}
+
+int lbmpcd_sample(lbmpcd_ctx* c, int32_t mode) {
+    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
+    if (mode == 1) {
+        HIPCHK(c, launch_zero(c->prof, c->prof_bytes, c->stream));
+        c->sampling = true;
+        c->sampled_steps = 0;
+    } else if (mode == 0) {
+        c->sampling = false;
+    } else {
+        return fail(c, LBMPCD_E_INVALID, "mode must be 0 or 1");
+    }
+    return 0;
+}
+
+int lbmpcd_sync(lbmpcd_ctx* c) {
+    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->mpcd) return check_device_errors(c);
+    return c->sticky;
+}
+
+int lbmpcd_timing(lbmpcd_ctx* c, int32_t mode) {
+    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
+    if (mode == 1) {
+        if (int e = drain_marks(c)) return e;
+        for (int k = 0; k < 4; ++k) { c->timing_ms[k] = 0; c->timing_n[k] = 0; }
+        c->timing = true;
+    } else if (mode == 0) {
+        c->timing = false;
+    } else {
+        return fail(c, LBMPCD_E_INVALID, "mode must be 0 or 1");
+    }
+    return 0;
+}
+
+int lbmpcd_timing_read(lbmpcd_ctx* c, double* out, int32_t n_classes) {
+    if (!c || !out || n_classes < 0) return fail(c, LBMPCD_E_INVALID, "bad arguments");
+    if (int e = drain_marks(c)) return e;
+    for (int k = 0; k < n_classes; ++k) {
+        out[2 * k] = k < 4 ? c->timing_ms[k] : 0.0;
+        out[2 * k + 1] = k < 4 ? (double)c->timing_n[k] : 0.0;
+    }
+    return 0;
+}
+
+void lbmpcd_destroy(lbmpcd_ctx* c) {
+    if (!c) return;
+    for (auto& m : c->marks) {
+        if (m.a) (void)hipEventDestroy(m.a);
+        if (m.b) (void)hipEventDestroy(m.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

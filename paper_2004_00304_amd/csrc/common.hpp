@@ -1,0 +1,179 @@
+// common.hpp -- device-side building blocks of the coupled LB-MPCD step for
+// gfx950: instance descriptors, counter-based random numbers, lattice tables.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmpcd {
+
+constexpr int WG = 256;           // threads per workgroup of every kernel
+constexpr int NCOPY = 64;         // replicas of the profile accumulators
+constexpr int MAX_NCT = 128;      // cells per particle tile
+constexpr int MAX_WIN = 64;       // LDS bins of the feedback sample window
+constexpr int MAX_WJ = 64;        // LDS rows of the profile sample window
+constexpr uint32_t BAD_SLOT = 0xFFFFFFFFu;
+
+// Purposes of the random streams: the counter of every draw is
+// (element, LB step, substep << 8 | purpose, block).
+enum Purpose : uint32_t { P_INIT_POS = 1, P_INIT_VEL = 2, P_REINJ = 3, P_SHIFT = 4, P_ROT = 5, P_WALL = 6 };
+
+// Everything a kernel needs to know about one channel.  One array of these
+// lives in the workspace; kernels find their instance from a global index by
+// binary search over the *_off fields.
+struct InstDesc {
+    // lattice Boltzmann
+    int nx, ny, nz, walls_y;
+    long long N;          // nodes
+    long long node_off;   // first node of this instance in the concatenated node arrays
+    double omega, src;    // 1/tau and 1 - 1/(2 tau)
+    double g[3];
+    double rho0, tau;
+    int init_flow, mpcd;
+    // slab and its cells
+    int ylo, yhi, buf_lo, buf_hi;
+    int r, R, Cx, Cz, CyB, ywrap, bot_wall, top_wall, ppc, feedback, grid_shift, pad0;
+    long long ncells, Np;
+    long long part_off;   // first particle of this instance in the init enumeration
+    long long init_per;   // particles per tile in the initial placement
+    // particle tiles
+    int Tx, Ty, Tz, ntx, nty, ntz, cap, nct;
+    long long ntiles, tile_off, slot_off;
+    // band (rows of node velocities used by the interpolation)
+    int by0, nyb;
+    long long band_off;   // first band node
+    int NB, pad1;         // buffer fine rows
+    long long ufine_off;  // first buffer fine cell
+    long long nslab, acc_off;  // slab nodes, first slab node in the feedback sums
+    long long prof_off;   // first profile row (NCOPY copies of R rows each)
+    // MPCD constants
+    double a, dt, gh[3], gdt[3], sd, cos_a, sin_a, mass, kT;
+    uint32_t key0, key1;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplies whose high halves are mixed with the odd counter words and the
+// key; the key advances by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        U4 n;
+        n.x = hi1 ^ c.y ^ k0;
+        n.y = lo1;
+        n.z = hi0 ^ c.w ^ k1;
+        n.w = lo0;
+        c = n;
+    }
+    return c;
+}
+
+__host__ __device__ __forceinline__ double u01(uint32_t lo, uint32_t hi) {
+    uint64_t v = ((uint64_t)hi << 32) | (uint64_t)lo;
+    return (double)(v >> 11) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ U4 rng_block(const InstDesc& d, uint32_t elem, uint32_t t, uint32_t sub,
+                                        uint32_t purpose, uint32_t blk) {
+    return philox(U4{elem, t, (sub << 8) | purpose, blk}, d.key0, d.key1);
+}
+
+// Four uniforms of one stream element (two Philox blocks, 53 bits each).
+__device__ __forceinline__ void rng_uniforms4(const InstDesc& d, uint32_t elem, uint32_t t,
+                                              uint32_t sub, uint32_t purpose, double u[4]) {
+    U4 w = rng_block(d, elem, t, sub, purpose, 0);
+    u[0] = u01(w.x, w.y);
+    u[1] = u01(w.z, w.w);
+    w = rng_block(d, elem, t, sub, purpose, 1);
+    u[2] = u01(w.x, w.y);
+    u[3] = u01(w.z, w.w);
+}
+
+// Box-Muller pair (the exchange step's generator of normal deviates).
+__device__ __forceinline__ void box_muller(double u0, double u1, double& z0, double& z1) {
+    double r = sqrt(-2.0 * log(1.0 - u0));
+    double th = 6.283185307179586 * u1;
+    double s, c;
+    sincos(th, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// DIM standard normals of one element; the third comes from a second pair.
+template <int DIM>
+__device__ __forceinline__ void rng_normals(const InstDesc& d, uint32_t elem, uint32_t t, uint32_t sub,
+                                            uint32_t purpose, double z[3]) {
+    if constexpr (DIM == 2) {
+        U4 w = rng_block(d, elem, t, sub, purpose, 0);
+        box_muller(u01(w.x, w.y), u01(w.z, w.w), z[0], z[1]);
+        z[2] = 0.0;
+    } else {
+        double u[4], dummy;
+        rng_uniforms4(d, elem, t, sub, purpose, u);
+        box_muller(u[0], u[1], z[0], z[1]);
+        box_muller(u[2], u[3], z[2], dummy);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lattices: D2Q9 and D3Q19 with the textbook weights (c_s^2 = 1/3).
+// ---------------------------------------------------------------------------
+template <int DIM> struct Lat;
+
+template <> struct Lat<2> {
+    static constexpr int Q = 9;
+    static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    static constexpr double w[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                                    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+};
+
+template <> struct Lat<3> {
+    static constexpr int Q = 19;
+    static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    static constexpr double w[19] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                                     1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+};
+
+// Instance lookup: largest i with key(D[i]) <= gid (offsets are ascending).
+template <typename F>
+__device__ __forceinline__ int find_inst(const InstDesc* __restrict__ D, int n_inst, long long gid, F key) {
+    int lo = 0, hi = n_inst - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (key(D[mid]) <= gid) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Device error and statistics block.
+struct DevStats {
+    unsigned long long dropped;     // particles lost to tile overflow
+    unsigned long long misplaced;   // particles found outside their tile
+    unsigned long long far_moves;   // particles moving beyond the neighbour tiles
+    unsigned int max_fill;          // largest tile occupancy seen
+    unsigned int pad;
+};
+
+// Particle arrays of one buffer: positions, velocities, ids (slot-indexed).
+template <typename PT>
+struct PartPtrs {
+    PT* pos[3];
+    PT* vel[3];
+    uint32_t* id;
+};
+
+}  // namespace lbmpcd

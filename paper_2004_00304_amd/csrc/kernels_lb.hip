@@ -1,0 +1,394 @@
+// kernels_lb.hip -- lattice-Boltzmann kernels for gfx950.
+//
+// k_lb_step: one thread per node; reads the Q post-stream populations of its
+// node (SoA, coalesced along x), applies the BGK collision with Guo forcing
+// (Eq. 1-2 with a constant body force) in FP64, and pushes every
+// post-collision population to the neighbour along c_i, or back into the
+// opposite direction of the same node where the link crosses a wall
+// (half-way bounce-back).  HBM-bound: one read and one write of Q values.
+//
+// k_band: per node of the rows the coupling needs; projects the sampled MPCD
+// velocity onto the equilibrium at interior slab nodes (feedback), clears the
+// sample sums, and stores the node velocity for the interpolation.
+//
+// k_interp: per buffer fine cell, bi/trilinear interpolation of the node
+// velocity to the cell centre (Alg. 2).
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace lbmpcd {
+
+template <int DIM>
+__device__ __forceinline__ void equilibrium_guo(const double* f, double omega, double src, const double g[3],
+                                                double* fs) {
+    using L = Lat<DIM>;
+    constexpr int Q = L::Q;
+    double rho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rho += f[i];
+        j0 += f[i] * (double)L::cx[i];
+        j1 += f[i] * (double)L::cy[i];
+        j2 += f[i] * (double)L::cz[i];
+    }
+    double u0 = j0 / rho + 0.5 * g[0];
+    double u1 = j1 / rho + 0.5 * g[1];
+    double u2 = j2 / rho + 0.5 * g[2];
+    double F0 = rho * g[0], F1 = rho * g[1], F2 = rho * g[2];
+    double uu = u0 * u0 + u1 * u1 + u2 * u2;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double c0 = L::cx[i], c1 = L::cy[i], c2 = L::cz[i];
+        double cu = c0 * u0 + c1 * u1 + c2 * u2;
+        double feq = L::w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        double Fi = 0.0;
+        Fi += (3.0 * (c0 - u0) + 9.0 * cu * c0) * F0;
+        Fi += (3.0 * (c1 - u1) + 9.0 * cu * c1) * F1;
+        Fi += (3.0 * (c2 - u2) + 9.0 * cu * c2) * F2;
+        Fi *= L::w[i];
+        fs[i] = f[i] - omega * (f[i] - feq) + src * Fi;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void feq_of(double rho, double u0, double u1, double u2, double* feq) {
+    using L = Lat<DIM>;
+    double uu = u0 * u0 + u1 * u1 + u2 * u2;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        double cu = (double)L::cx[i] * u0 + (double)L::cy[i] * u1 + (double)L::cz[i] * u2;
+        feq[i] = L::w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    }
+}
+
+template <int DIM, typename LT>
+__global__ void __launch_bounds__(WG) k_lb_step(const InstDesc* __restrict__ D, int n_inst, long long total,
+                                                const LT* __restrict__ fin, LT* __restrict__ fout,
+                                                long long* __restrict__ clock) {
+    using L = Lat<DIM>;
+    constexpr int Q = L::Q;
+    if (blockIdx.x == 0 && threadIdx.x == 0) clock[0] = clock[0] + 1;
+    long long gid = (long long)blockIdx.x * WG + threadIdx.x;
+    if (gid >= total) return;
+    int ii = find_inst(D, n_inst, gid, [](const InstDesc& d) { return d.node_off; });
+    const InstDesc& d = D[ii];
+    long long n = gid - d.node_off;
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    int x = (int)(n % nx);
+    int y = (int)((n / nx) % ny);
+    int z = (int)(n / ((long long)nx * ny));
+    const long long N = d.N;
+    const LT* f_in = fin + d.node_off * Q;
+    LT* f_out = fout + d.node_off * Q;
+    double f[Q], fs[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = (double)f_in[i * N + n];
+    double g[3] = {d.g[0], d.g[1], d.g[2]};
+    equilibrium_guo<DIM>(f, d.omega, d.src, g, fs);
+    const long long sxy = (long long)nx * ny;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int yd = y + L::cy[i];
+        if (d.walls_y && (yd < 0 || yd >= ny)) {
+            f_out[L::opp[i] * N + n] = (LT)fs[i];
+            continue;
+        }
+        if (yd < 0) yd += ny; else if (yd >= ny) yd -= ny;
+        int xd = x + L::cx[i];
+        if (xd < 0) xd += nx; else if (xd >= nx) xd -= nx;
+        int zd = z;
+        if constexpr (DIM == 3) {
+            zd = z + L::cz[i];
+            if (zd < 0) zd += nz; else if (zd >= nz) zd -= nz;
+        }
+        f_out[i * N + (long long)zd * sxy + (long long)yd * nx + xd] = (LT)fs[i];
+    }
+}
+
+// Feedback projection, sample reset and node velocity of the band rows.
+template <int DIM, typename LT>
+__global__ void __launch_bounds__(WG) k_band(const InstDesc* __restrict__ D, int n_inst, long long total,
+                                             LT* __restrict__ f, double* __restrict__ acc,
+                                             double* __restrict__ ub, int do_feedback) {
+    using L = Lat<DIM>;
+    constexpr int Q = L::Q;
+    long long gid = (long long)blockIdx.x * WG + threadIdx.x;
+    if (gid >= total) return;
+    int ii = find_inst(D, n_inst, gid, [](const InstDesc& d) { return d.band_off; });
+    const InstDesc& d = D[ii];
+    long long b = gid - d.band_off;
+    const int nx = d.nx;
+    int x = (int)(b % nx);
+    int yb = (int)((b / nx) % d.nyb);
+    int z = (int)(b / ((long long)nx * d.nyb));
+    int y = d.by0 + yb;
+    long long n = ((long long)z * d.ny + y) * nx + x;
+    LT* fp = f + d.node_off * Q;
+    const long long N = d.N;
+    double fl[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fl[i] = (double)fp[i * N + n];
+    if (do_feedback && y >= d.ylo && y < d.yhi) {
+        long long s = ((long long)z * (d.yhi - d.ylo) + (y - d.ylo)) * nx + x;
+        double* a = acc + (d.acc_off + s) * 4;
+        double cnt = a[0], s0 = a[1], s1 = a[2], s2 = a[3];
+        a[0] = 0.0; a[1] = 0.0; a[2] = 0.0; a[3] = 0.0;
+        if (y >= d.ylo + d.buf_lo && y < d.yhi - d.buf_hi && cnt > 0.0) {
+            double rho = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) rho += fl[i];
+            double u0 = s0 / cnt - 0.5 * d.g[0];
+            double u1 = s1 / cnt - 0.5 * d.g[1];
+            double u2 = (DIM == 3 ? s2 / cnt : 0.0) - 0.5 * d.g[2];
+            feq_of<DIM>(rho, u0, u1, u2, fl);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) fp[i * N + n] = (LT)fl[i];
+            // the velocity below is taken from the stored (rounded) values
+#pragma unroll
+            for (int i = 0; i < Q; ++i) fl[i] = (double)(LT)fl[i];
+        }
+    }
+    double rho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rho += fl[i];
+        j0 += fl[i] * (double)L::cx[i];
+        j1 += fl[i] * (double)L::cy[i];
+        j2 += fl[i] * (double)L::cz[i];
+    }
+    const long long NBd = (long long)nx * d.nyb * d.nz;
+    double* u = ub + d.band_off * 3;
+    u[b] = j0 / rho + 0.5 * d.g[0];
+    u[NBd + b] = j1 / rho + 0.5 * d.g[1];
+    u[2 * NBd + b] = j2 / rho + 0.5 * d.g[2];
+}
+
+// One interpolation axis: lower/upper node and weights.  Periodic axes wrap;
+// on a walled axis the missing neighbour is the wall with zero velocity.
+__device__ __forceinline__ void interp_axis(int Lx, int periodic, double X, int& i0, int& i1, double& w0,
+                                            double& w1) {
+    double xs = X - 0.5;
+    double fl = floor(xs);
+    int j0 = (int)fl;
+    double wx = xs - fl;
+    int j1 = j0 + 1;
+    if (periodic) {
+        j0 = ((j0 % Lx) + Lx) % Lx;
+        j1 = ((j1 % Lx) + Lx) % Lx;
+        i0 = j0; i1 = j1; w0 = 1.0 - wx; w1 = wx;
+        return;
+    }
+    if (j0 < 0) {
+        i0 = -1; i1 = 0; w0 = 0.0; w1 = 2.0 * X;
+    } else if (j1 > Lx - 1) {
+        i0 = Lx - 1; i1 = -1; w0 = 2.0 * (Lx - X); w1 = 0.0;
+    } else {
+        i0 = j0; i1 = j1; w0 = 1.0 - wx; w1 = wx;
+    }
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(WG) k_interp(const InstDesc* __restrict__ D, int n_inst, long long total,
+                                               const double* __restrict__ ub, double* __restrict__ uf) {
+    long long gid = (long long)blockIdx.x * WG + threadIdx.x;
+    if (gid >= total) return;
+    int ii = find_inst(D, n_inst, gid, [](const InstDesc& d) { return d.ufine_off; });
+    const InstDesc& d = D[ii];
+    long long q = gid - d.ufine_off;
+    const int Cx = d.Cx, NB = d.NB;
+    int I = (int)(q % Cx);
+    int Jb = (int)((q / Cx) % NB);
+    int K = (int)(q / ((long long)Cx * NB));
+    int J = (Jb < d.buf_lo * d.r) ? Jb : Jb + (d.R - NB);
+    const double r = (double)d.r;
+    double X = ((double)I + 0.5) / r;
+    double Y = (double)d.ylo + ((double)J + 0.5) / r;
+    double Z = (DIM == 3) ? ((double)K + 0.5) / r : 0.5;
+    int ix[2], iy[2], iz[2];
+    double wx[2], wy[2], wz[2];
+    interp_axis(d.nx, 1, X, ix[0], ix[1], wx[0], wx[1]);
+    interp_axis(d.ny, !d.walls_y, Y, iy[0], iy[1], wy[0], wy[1]);
+    if (DIM == 3) {
+        interp_axis(d.nz, 1, Z, iz[0], iz[1], wz[0], wz[1]);
+    } else {
+        iz[0] = 0; iz[1] = 0; wz[0] = 1.0; wz[1] = 0.0;
+    }
+    const long long NBd = (long long)d.nx * d.nyb * d.nz;
+    const double* u = ub + d.band_off * 3;
+    const long long NF = (long long)Cx * NB * d.Cz;
+    double* out = uf + d.ufine_off * DIM;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double val[2] = {0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c) {
+            double row[2];
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) {
+                double a0 = 0.0, a1 = 0.0;
+                if (iy[bb] >= 0) {
+                    long long base = ((long long)iz[c] * d.nyb + (iy[bb] - d.by0)) * d.nx;
+                    a0 = u[k * NBd + base + ix[0]];
+                    a1 = u[k * NBd + base + ix[1]];
+                }
+                row[bb] = wx[0] * a0 + wx[1] * a1;
+            }
+            val[c] = wy[0] * row[0] + wy[1] * row[1];
+        }
+        double v = (DIM == 3) ? wz[0] * val[0] + wz[1] * val[1] : val[0];
+        out[k * NF + q] = v;
+    }
+}
+
+// LB initial state: equilibrium at rho0 and the initial flow (physical
+// velocity = first moment + g/2).
+__device__ __forceinline__ double poiseuille(const InstDesc& d, double gk, double y) {
+    double nu = (d.tau - 0.5) / 3.0, H = (double)d.ny, tau = d.tau;
+    return gk * y * (H - y) / (2.0 * nu) + gk * (16.0 * tau * tau - 16.0 * tau + 1.0) / (24.0 * nu);
+}
+
+template <int DIM, typename LT>
+__global__ void __launch_bounds__(WG) k_lb_init(const InstDesc* __restrict__ D, int n_inst, long long total,
+                                                LT* __restrict__ f) {
+    using L = Lat<DIM>;
+    long long gid = (long long)blockIdx.x * WG + threadIdx.x;
+    if (gid >= total) return;
+    int ii = find_inst(D, n_inst, gid, [](const InstDesc& d) { return d.node_off; });
+    const InstDesc& d = D[ii];
+    long long n = gid - d.node_off;
+    int y = (int)((n / d.nx) % d.ny);
+    double u[3];
+    for (int k = 0; k < 3; ++k) {
+        double u0 = d.init_flow ? poiseuille(d, d.g[k], y + 0.5) : 0.0;
+        u[k] = u0 - 0.5 * d.g[k];
+    }
+    double feq[L::Q];
+    feq_of<DIM>(d.rho0, u[0], u[1], u[2], feq);
+    LT* fp = f + d.node_off * L::Q;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) fp[i * d.N + n] = (LT)feq[i];
+}
+
+// Moments of the post-stream populations of one instance: rho, physical u,
+// Pi = sum f (c c - I/3).
+template <int DIM, typename LT>
+__global__ void __launch_bounds__(WG) k_moments(const InstDesc* __restrict__ D, int inst,
+                                                const LT* __restrict__ f, double* __restrict__ rho_out,
+                                                double* __restrict__ u_out, double* __restrict__ pi_out) {
+    using L = Lat<DIM>;
+    constexpr int Q = L::Q;
+    const InstDesc& d = D[inst];
+    long long n = (long long)blockIdx.x * WG + threadIdx.x;
+    if (n >= d.N) return;
+    const LT* fp = f + d.node_off * Q;
+    double fl[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fl[i] = (double)fp[i * d.N + n];
+    double rho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rho += fl[i];
+        j0 += fl[i] * (double)L::cx[i];
+        j1 += fl[i] * (double)L::cy[i];
+        j2 += fl[i] * (double)L::cz[i];
+    }
+    if (rho_out) rho_out[n] = rho;
+    if (u_out) {
+        u_out[n] = j0 / rho + 0.5 * d.g[0];
+        u_out[d.N + n] = j1 / rho + 0.5 * d.g[1];
+        u_out[2 * d.N + n] = j2 / rho + 0.5 * d.g[2];
+    }
+    if (pi_out) {
+        const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int ca = A[m] == 0 ? L::cx[i] : (A[m] == 1 ? L::cy[i] : L::cz[i]);
+                const int cb = B[m] == 0 ? L::cx[i] : (B[m] == 1 ? L::cy[i] : L::cz[i]);
+                double cc = (double)(ca * cb) - (A[m] == B[m] ? 1.0 / 3.0 : 0.0);
+                acc += fl[i] * cc;
+            }
+            pi_out[m * d.N + n] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(long long n) { return (unsigned)((n + WG - 1) / WG); }
+
+hipError_t launch_lb_step(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, const void* fin,
+                          void* fout, long long* clock, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    dim3 g(blocks_for(total)), b(WG);
+    if (dim == 2 && lb_fp == 64)
+        hipLaunchKernelGGL((k_lb_step<2, double>), g, b, 0, s, D, n_inst, total, (const double*)fin, (double*)fout, clock);
+    else if (dim == 2)
+        hipLaunchKernelGGL((k_lb_step<2, float>), g, b, 0, s, D, n_inst, total, (const float*)fin, (float*)fout, clock);
+    else if (lb_fp == 64)
+        hipLaunchKernelGGL((k_lb_step<3, double>), g, b, 0, s, D, n_inst, total, (const double*)fin, (double*)fout, clock);
+    else
+        hipLaunchKernelGGL((k_lb_step<3, float>), g, b, 0, s, D, n_inst, total, (const float*)fin, (float*)fout, clock);
+    return hipGetLastError();
+}
+
+hipError_t launch_band(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f, double* acc,
+                       double* ub, int do_feedback, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    dim3 g(blocks_for(total)), b(WG);
+    if (dim == 2 && lb_fp == 64)
+        hipLaunchKernelGGL((k_band<2, double>), g, b, 0, s, D, n_inst, total, (double*)f, acc, ub, do_feedback);
+    else if (dim == 2)
+        hipLaunchKernelGGL((k_band<2, float>), g, b, 0, s, D, n_inst, total, (float*)f, acc, ub, do_feedback);
+    else if (lb_fp == 64)
+        hipLaunchKernelGGL((k_band<3, double>), g, b, 0, s, D, n_inst, total, (double*)f, acc, ub, do_feedback);
+    else
+        hipLaunchKernelGGL((k_band<3, float>), g, b, 0, s, D, n_inst, total, (float*)f, acc, ub, do_feedback);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(int dim, const InstDesc* D, int n_inst, long long total, const double* ub, double* uf,
+                         hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    dim3 g(blocks_for(total)), b(WG);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_interp<2>), g, b, 0, s, D, n_inst, total, ub, uf);
+    else
+        hipLaunchKernelGGL((k_interp<3>), g, b, 0, s, D, n_inst, total, ub, uf);
+    return hipGetLastError();
+}
+
+hipError_t launch_lb_init(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f,
+                          hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    dim3 g(blocks_for(total)), b(WG);
+    if (dim == 2 && lb_fp == 64)
+        hipLaunchKernelGGL((k_lb_init<2, double>), g, b, 0, s, D, n_inst, total, (double*)f);
+    else if (dim == 2)
+        hipLaunchKernelGGL((k_lb_init<2, float>), g, b, 0, s, D, n_inst, total, (float*)f);
+    else if (lb_fp == 64)
+        hipLaunchKernelGGL((k_lb_init<3, double>), g, b, 0, s, D, n_inst, total, (double*)f);
+    else
+        hipLaunchKernelGGL((k_lb_init<3, float>), g, b, 0, s, D, n_inst, total, (float*)f);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int dim, int lb_fp, const InstDesc* D, int inst, long long N, const void* f,
+                          double* rho, double* u, double* pi, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    dim3 g(blocks_for(N)), b(WG);
+    if (dim == 2 && lb_fp == 64)
+        hipLaunchKernelGGL((k_moments<2, double>), g, b, 0, s, D, inst, (const double*)f, rho, u, pi);
+    else if (dim == 2)
+        hipLaunchKernelGGL((k_moments<2, float>), g, b, 0, s, D, inst, (const float*)f, rho, u, pi);
+    else if (lb_fp == 64)
+        hipLaunchKernelGGL((k_moments<3, double>), g, b, 0, s, D, inst, (const double*)f, rho, u, pi);
+    else
+        hipLaunchKernelGGL((k_moments<3, float>), g, b, 0, s, D, inst, (const float*)f, rho, u, pi);
+    return hipGetLastError();
+}
+
+}  // namespace lbmpcd

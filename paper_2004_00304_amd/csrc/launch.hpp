@@ -1,0 +1,68 @@
+// launch.hpp -- host-side launchers of the gfx950 kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace lbmpcd {
+
+hipError_t launch_lb_step(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, const void* fin,
+                          void* fout, long long* clock, hipStream_t s);
+hipError_t launch_band(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f, double* acc,
+                       double* ub, int do_feedback, hipStream_t s);
+hipError_t launch_interp(int dim, const InstDesc* D, int n_inst, long long total, const double* ub, double* uf,
+                         hipStream_t s);
+hipError_t launch_lb_init(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f,
+                          hipStream_t s);
+hipError_t launch_moments(int dim, int lb_fp, const InstDesc* D, int inst, long long N, const void* f,
+                          double* rho, double* u, double* pi, hipStream_t s);
+
+// Buffers of one particle store, type-erased (positions, velocities, ids).
+struct PartBuf {
+    void* pos[3];
+    void* vel[3];
+    uint32_t* id;
+};
+
+struct ParticleLaunch {
+    int dim, part_fp, ppt, mode;  // mode bit 0: collide, bit 1: stream
+    const InstDesc* D;
+    int n_inst;
+    long long tiles;              // workgroups (tiles of all instances)
+    PartBuf in, out;
+    uint32_t* fill_in;
+    uint32_t* fill_out;
+    const int* tile_inst;
+    const double* ufine;
+    double* acc;
+    double* prof;
+    DevStats* stats;
+    const long long* clock;
+    int coll_dt, coll_s, str_s;   // collision step = clock + coll_dt, substeps
+    int do_fb, do_prof;
+    int diag_inst;                // instance whose cell centre-of-mass velocities are written
+    double* cell_vcm;             // [dim][ncells] or null
+    size_t lds_bytes;
+};
+
+hipError_t launch_particles(const ParticleLaunch& L, hipStream_t s);
+size_t particle_lds_bytes(int dim, int part_fp, int cap);
+
+hipError_t launch_part_init(int dim, int part_fp, const InstDesc* D, int n_inst, long long total_particles,
+                            PartBuf buf, hipStream_t s);
+hipError_t launch_fill_sequential(const InstDesc* D, int n_inst, long long tiles, uint32_t* fill,
+                                  uint32_t* fill_other, hipStream_t s);
+// Per-instance kernels cover `slots` = ntiles * cap of that instance.
+hipError_t launch_gather(int dim, int part_fp, const InstDesc* D, int inst, PartBuf buf, const uint32_t* fill,
+                         double* pos_out, double* vel_out, int* cell_out, long long slots, long long t, int sub,
+                         hipStream_t s);
+hipError_t launch_cell_count(int dim, int part_fp, const InstDesc* D, int inst, PartBuf buf, const uint32_t* fill,
+                             int* count_out, long long slots, long long t, int sub, hipStream_t s);
+hipError_t launch_set_field(int dim, int part_fp, const InstDesc* D, int inst, PartBuf buf, const uint32_t* fill,
+                            int which, const double* src, long long slots, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_profile_reduce(const InstDesc* D, int inst, int R, const double* prof, double* out,
+                                 hipStream_t s);
+
+}  // namespace lbmpcd

@@ -1,0 +1,271 @@
+"""Python binding of the HIP library ``liblbmpcd.so`` (C ABI in include/lbmpcd.h).
+
+Argument marshalling only: every step of the coupled LB-MPCD method runs in the
+library's gfx950 kernels.  PyTorch supplies the device memory (one workspace
+tensor) and the HIP stream.  Importing this module loads the library and fails
+loudly when it has not been built (``python -m paper_2004_00304_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmpcd.so")
+
+ABI_VERSION = 1
+
+RHO, U, PI, POP, PART_POS, PART_VEL, CELL_ID, CELL_COUNT, CELL_VCM, PROFILE, UFINE, STATS = range(12)
+FIELD_NAMES = dict(rho=RHO, u=U, pi=PI, pop=POP, pos=PART_POS, vel=PART_VEL, cell_id=CELL_ID,
+                   cell_count=CELL_COUNT, cell_vcm=CELL_VCM, profile=PROFILE, ufine=UFINE, stats=STATS)
+ERRORS = {1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_OVERFLOW", 5: "E_STATE", 6: "E_UNSUPPORTED"}
+
+
+class LbmpcdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("struct_size", C.c_uint32),
+        ("dim", C.c_int32), ("n", C.c_int32 * 3), ("lb_fp", C.c_int32),
+        ("tau", C.c_double), ("rho0", C.c_double), ("g", C.c_double * 3),
+        ("walls_y", C.c_int32), ("mpcd", C.c_int32), ("ylo", C.c_int32), ("yhi", C.c_int32),
+        ("buf_lo", C.c_int32), ("buf_hi", C.c_int32), ("refine", C.c_int32), ("substeps", C.c_int32),
+        ("ppc", C.c_int32), ("part_fp", C.c_int32),
+        ("mass", C.c_double), ("kT", C.c_double), ("alpha_deg", C.c_double),
+        ("collision", C.c_int32), ("grid_shift", C.c_int32), ("feedback", C.c_int32),
+        ("init_flow", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint32),
+        ("tile", C.c_int32 * 3), ("capacity_factor", C.c_double),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2004_00304_amd.build` "
+                          "(the HIP library is the only compute path; there is no fallback)")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    L.lbmpcd_workspace_size.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+    L.lbmpcd_init.argtypes = [P, C.c_int32, P, C.c_size_t, P, C.POINTER(C.c_void_p)]
+    L.lbmpcd_step.argtypes = [P, C.c_int32]
+    L.lbmpcd_moments.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, C.c_int32]
+    L.lbmpcd_field_bytes.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+    L.lbmpcd_sample.argtypes = [P, C.c_int32]
+    L.lbmpcd_get_state.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, C.c_int32]
+    L.lbmpcd_set_state.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, C.c_int32]
+    L.lbmpcd_sync.argtypes = [P]
+    L.lbmpcd_destroy.argtypes = [P]
+    L.lbmpcd_destroy.restype = None
+    L.lbmpcd_timing.argtypes = [P, C.c_int32]
+    L.lbmpcd_timing.restype = C.c_int
+    L.lbmpcd_timing_read.argtypes = [P, P, C.c_int32]
+    L.lbmpcd_timing_read.restype = C.c_int
+    L.lbmpcd_strerror.argtypes = [C.c_int]
+    L.lbmpcd_strerror.restype = C.c_char_p
+    L.lbmpcd_last_error.argtypes = [P]
+    L.lbmpcd_last_error.restype = C.c_char_p
+    for name in ("lbmpcd_workspace_size", "lbmpcd_init", "lbmpcd_step", "lbmpcd_moments",
+                 "lbmpcd_field_bytes", "lbmpcd_sample", "lbmpcd_get_state", "lbmpcd_set_state",
+                 "lbmpcd_sync"):
+        getattr(L, name).restype = C.c_int
+    return L
+
+
+_lib = _load()
+EXPORTED = ("lbmpcd_workspace_size", "lbmpcd_init", "lbmpcd_step", "lbmpcd_moments",
+            "lbmpcd_field_bytes", "lbmpcd_sample", "lbmpcd_get_state", "lbmpcd_set_state",
+            "lbmpcd_sync", "lbmpcd_destroy", "lbmpcd_strerror", "lbmpcd_last_error", "lbmpcd_timing",
+            "lbmpcd_timing_read")
+
+
+def lib():
+    return _lib
+
+
+def params_struct(p: dict) -> Params:
+    s = Params()
+    s.abi_version = ABI_VERSION
+    s.struct_size = C.sizeof(Params)
+    s.dim = p["dim"]
+    for k in range(3):
+        s.n[k] = p["n"][k]
+        s.g[k] = p["g"][k]
+        s.tile[k] = p.get("tile", (0, 0, 0))[k]
+    s.lb_fp = p["lb_fp"]
+    s.tau, s.rho0 = p["tau"], p["rho0"]
+    s.walls_y, s.mpcd = p["walls_y"], p["mpcd"]
+    s.ylo, s.yhi, s.buf_lo, s.buf_hi = p["ylo"], p["yhi"], p["buf_lo"], p["buf_hi"]
+    s.refine, s.substeps, s.ppc, s.part_fp = p["refine"], p["substeps"], p["ppc"], p["part_fp"]
+    s.mass, s.kT, s.alpha_deg = p["mass"], p["kT"], p["alpha_deg"]
+    s.collision, s.grid_shift, s.feedback, s.init_flow = (p["collision"], p["grid_shift"],
+                                                          p["feedback"], p["init_flow"])
+    s.seed, s.instance = p["seed"], p["instance"]
+    s.capacity_factor = p.get("capacity_factor", 0.0)
+    return s
+
+
+def _check(rc: int, ctx=None):
+    if rc != 0:
+        raise LbmpcdError(rc, _lib.lbmpcd_last_error(ctx).decode())
+
+
+def workspace_size(params) -> int:
+    plist = params if isinstance(params, (list, tuple)) else [params]
+    arr = (Params * len(plist))(*[params_struct(p) for p in plist])
+    n = C.c_size_t()
+    _check(_lib.lbmpcd_workspace_size(C.cast(arr, C.c_void_p), len(plist), C.byref(n)))
+    return int(n.value)
+
+
+class Sim:
+    """One or more coupled channels advanced by the HIP library on one GPU."""
+
+    def __init__(self, params, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.plist = list(params) if isinstance(params, (list, tuple)) else [params]
+        self.n_inst = len(self.plist)
+        self.dim = self.plist[0]["dim"]
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self._arr = (Params * self.n_inst)(*[params_struct(p) for p in self.plist])
+        nbytes = workspace_size(self.plist)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            h = C.c_void_p()
+            rc = _lib.lbmpcd_init(C.cast(self._arr, C.c_void_p), self.n_inst,
+                                  C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h))
+            _check(rc, None)
+        self._h = h
+        self.workspace_bytes = nbytes
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                _lib.lbmpcd_sync(h)
+            finally:
+                _lib.lbmpcd_destroy(h)
+            self._h = None
+
+    # -- stepping
+    def step(self, n: int = 1):
+        _check(_lib.lbmpcd_step(self._h, int(n)), self._h)
+
+    def sync(self):
+        _check(_lib.lbmpcd_sync(self._h), self._h)
+
+    def sample(self, mode: int):
+        _check(_lib.lbmpcd_sample(self._h, int(mode)), self._h)
+
+    # -- fields (device tensors)
+    def field_bytes(self, field: int, inst: int = 0) -> int:
+        n = C.c_size_t()
+        _check(_lib.lbmpcd_field_bytes(self._h, field, inst, C.byref(n)), self._h)
+        return int(n.value)
+
+    def _alloc(self, field, inst, dtype):
+        torch = self.torch
+        nb = self.field_bytes(field, inst)
+        item = torch.empty((), dtype=dtype).element_size()
+        return torch.empty(nb // item, dtype=dtype, device=self.device)
+
+    def moments(self, field, inst: int = 0):
+        torch = self.torch
+        field = FIELD_NAMES.get(field, field) if isinstance(field, str) else field
+        if field == STATS:
+            out = np.zeros(8, np.int64)
+            _check(_lib.lbmpcd_moments(self._h, STATS, inst, out.ctypes.data_as(C.c_void_p), 64, 0),
+                   self._h)
+            keys = ("lb_steps", "sampled_steps", "dropped", "misplaced", "far_moves", "max_fill",
+                    "particles", "cells")
+            return dict(zip(keys, (int(x) for x in out)))
+        dtype = torch.int32 if field in (CELL_ID, CELL_COUNT) else torch.float64
+        if field == POP:
+            dtype = torch.float64 if self.plist[inst]["lb_fp"] == 64 else torch.float32
+        out = self._alloc(field, inst, dtype)
+        with torch.cuda.device(self.device):
+            _check(_lib.lbmpcd_moments(self._h, field, inst, C.c_void_p(out.data_ptr()),
+                                       out.numel() * out.element_size(), 1), self._h)
+        return out
+
+    def get_state(self, field, inst: int = 0):
+        field = FIELD_NAMES.get(field, field) if isinstance(field, str) else field
+        return self.moments(field, inst)
+
+    def set_state(self, field, src, inst: int = 0):
+        torch = self.torch
+        field = FIELD_NAMES.get(field, field) if isinstance(field, str) else field
+        dtype = torch.float64
+        if field == POP and self.plist[inst]["lb_fp"] == 32:
+            dtype = torch.float32
+        t = torch.as_tensor(src).to(device=self.device, dtype=dtype).contiguous()
+        with torch.cuda.device(self.device):
+            _check(_lib.lbmpcd_set_state(self._h, field, inst, C.c_void_p(t.data_ptr()),
+                                         t.numel() * t.element_size(), 1), self._h)
+
+    # -- numpy views in the oracle's layouts
+    def shape(self, inst=0):
+        nx, ny, nz = self.plist[inst]["n"]
+        return (nz, ny, nx)
+
+    def f(self, inst=0) -> np.ndarray:
+        p = self.plist[inst]
+        Q = 9 if p["dim"] == 2 else 19
+        return self.get_state(POP, inst).cpu().numpy().reshape((Q,) + self.shape(inst)).astype(np.float64)
+
+    def fields(self, inst=0):
+        sh = self.shape(inst)
+        rho = self.moments(RHO, inst).cpu().numpy().reshape(sh)
+        u = self.moments(U, inst).cpu().numpy().reshape((3,) + sh)
+        pi = self.moments(PI, inst).cpu().numpy().reshape((6,) + sh)
+        return rho, u, pi
+
+    def particles(self, inst=0):
+        d = self.plist[inst]["dim"]
+        pos = self.get_state(PART_POS, inst).cpu().numpy().reshape(d, -1)
+        vel = self.get_state(PART_VEL, inst).cpu().numpy().reshape(d, -1)
+        return pos, vel
+
+    def binning(self, inst=0):
+        """Cell of every particle (by id), cell counts and the cell centre-of-mass
+        velocities of the last MPCD step (call right after step())."""
+        d = self.plist[inst]["dim"]
+        vcm = self.moments(CELL_VCM, inst).cpu().numpy().reshape(d, -1)
+        cell = self.moments(CELL_ID, inst).cpu().numpy()
+        count = self.moments(CELL_COUNT, inst).cpu().numpy()
+        return dict(cell=cell, count=count, vcm=vcm)
+
+    def profile(self, inst=0) -> np.ndarray:
+        return self.moments(PROFILE, inst).cpu().numpy().reshape(-1, 4)
+
+    def ufine(self, inst=0) -> np.ndarray:
+        p = self.plist[inst]
+        r = p["refine"]
+        R = (p["yhi"] - p["ylo"]) * r
+        Cz = p["n"][2] * r if p["dim"] == 3 else 1
+        return self.moments(UFINE, inst).cpu().numpy().reshape(p["dim"], Cz, R, p["n"][0] * r)
+
+    def stats(self, inst=0) -> dict:
+        return self.moments(STATS, inst)
+
+    # -- kernel timing (HIP events on the context's stream)
+    KERNEL_CLASSES = ("lb_step", "band", "interp", "particles")
+
+    def timing(self, mode: int):
+        _check(_lib.lbmpcd_timing(self._h, int(mode)), self._h)
+
+    def timing_read(self) -> dict:
+        out = np.zeros(8, np.float64)
+        _check(_lib.lbmpcd_timing_read(self._h, out.ctypes.data_as(C.c_void_p), 4), self._h)
+        return {k: dict(ms=float(out[2 * i]), launches=int(out[2 * i + 1]))
+                for i, k in enumerate(self.KERNEL_CLASSES)}

@@ -1,0 +1,93 @@
+"""The C-ABI library loads on a CPU-only host, exports every entry point that
+include/lbmpcd.h declares, sizes workspaces and rejects bad parameters
+(host logic only; no compute call needs a GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2004_00304_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def binding():
+    from paper_2004_00304_amd import lbmpcd
+    return lbmpcd
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbmpcd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbmpcd_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(binding):
+    names = declared_functions()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(binding.EXPORTED)
+
+
+def test_params_struct_matches_header(binding):
+    """The ctypes mirror has the size the library checks (struct_size)."""
+    p = binding.params_struct(W.channel_2d())
+    assert p.struct_size == ctypes.sizeof(binding.Params)
+    assert binding.workspace_size(W.channel_2d()) > 0
+
+
+def test_workspace_sizes(binding):
+    s1 = binding.workspace_size(W.channel_2d())
+    s3 = binding.workspace_size(W.channel_3d())
+    # the 3D channel holds 167,772,160 FP32 particles in two tile stores
+    assert s3 > 2 * 167_772_160 * 28
+    assert s3 < 40 * 2 ** 30
+    assert s1 < s3
+    big = binding.workspace_size(W.thin_film_3d())
+    assert big < 200 * 2 ** 30  # fits one MI355X (288 GB)
+    ens = binding.workspace_size(W.ensemble(8))
+    assert ens > 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(tau=0.5), 1), (dict(dim=4), 1), (dict(lb_fp=16), 1), (dict(ylo=20, yhi=10), 1),
+    (dict(buf_lo=5, buf_hi=5), 1), (dict(walls_y=1, ylo=0, buf_lo=1), 1), (dict(collision=1), 6),
+    (dict(part_fp=16), 1), (dict(refine=0), 1), (dict(n=(8, 8, 2)), 1),
+    (dict(walls_y=0, ylo=0, yhi=8), 6), (dict(substeps=300), 1),
+])
+def test_invalid_params(binding, kw, code):
+    with pytest.raises(binding.LbmpcdError) as e:
+        binding.workspace_size(W.make(**kw))
+    assert e.value.code == code
+
+
+def test_mixed_batch_rejected(binding):
+    with pytest.raises(binding.LbmpcdError):
+        binding.workspace_size([W.channel_2d(), W.small_3d()])
+
+
+def test_abi_version_checked(binding):
+    p = binding.params_struct(W.channel_2d())
+    p.abi_version = 99
+    n = ctypes.c_size_t()
+    rc = binding.lib().lbmpcd_workspace_size(ctypes.byref(p), 1, ctypes.byref(n))
+    assert rc == 1
+    assert b"abi" in binding.lib().lbmpcd_last_error(None)
+
+
+def test_strerror(binding):
+    L = binding.lib()
+    assert L.lbmpcd_strerror(0) == b"ok"
+    assert L.lbmpcd_strerror(4) == b"particle tile overflow"
+    assert L.lbmpcd_strerror(77) == b"unknown error"
+
+
+def test_null_context_calls_fail_cleanly(binding):
+    L = binding.lib()
+    assert L.lbmpcd_step(None, 1) == 1
+    assert L.lbmpcd_sync(None) == 1
+    L.lbmpcd_destroy(None)

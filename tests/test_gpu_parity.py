@@ -1,0 +1,140 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeds, element by element.  FP64: every field within 1e-11 of its scale;
+binning (cell of every particle, cell counts) bit-exact.  Binary32 particle
+stores: within 2e-6 of the thermal scale, binning bit-exact."""
+import numpy as np
+import pytest
+
+from paper_2004_00304_amd import workloads as W
+from tests.gpu_util import RTOL32, RTOL64, assert_parity, banner, compare_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as O
+    from paper_2004_00304_amd import lbmpcd
+    return O, lbmpcd
+
+
+CASES = {
+    "channel_2d_fp64": (W.channel_2d(), 10, RTOL64),
+    "small_2d_oneway": (W.small_2d(feedback=0), 6, RTOL64),
+    "small_2d_ragged_tiles": (W.small_2d(n=(37, 24, 1), tile=(8, 4, 0)), 5, RTOL64),
+    "small_3d_fp64": (W.small_3d(), 5, RTOL64),
+    "small_3d_fp32": (W.small_3d(part_fp=32), 5, RTOL32),
+    "small_3d_lb32": (W.small_3d(lb_fp=32, part_fp=32), 4, 2e-6),
+    "walled_2d": (W.walled_2d(), 6, RTOL64),
+    "walled_2d_fp32": (W.walled_2d(part_fp=32, ppc=5), 6, RTOL32),
+    "periodic_2d": (W.periodic_2d(), 6, RTOL64),
+    "no_shift": (W.small_2d(grid_shift=0), 4, RTOL64),
+    "poiseuille_init": (W.small_2d(init_flow=1, g=(2e-5, 0, 0)), 4, RTOL64),
+}
+
+
+def _params(p):
+    return {k: v for k, v in p.items() if k not in ("tile",)}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity(env, name):
+    O, lbmpcd = env
+    p, steps, rtol = CASES[name]
+    banner(f"parity {name} steps={steps} n={p['n']} dim={p['dim']}")
+    sim = lbmpcd.Sim(p)
+    orc = O.Oracle(_params(p))
+    sim.step(steps)
+    orc.step(steps)
+    rep = compare_state(sim, orc, p, rtol)
+    banner(f"{name}: {rep}")
+    assert_parity(rep, rtol)
+
+
+def test_parity_lb_only(env):
+    O, lbmpcd = env
+    for dim in (2, 3):
+        p = W.make(dim=dim, n=(9, 12, 7) if dim == 3 else (33, 17, 1), mpcd=0, tau=0.7, g=(3e-5, 0, 0))
+        banner(f"lb-only dim={dim}")
+        sim = lbmpcd.Sim(p)
+        orc = O.Oracle(p)
+        sim.step(25)
+        orc.step(25)
+        rep = compare_state(sim, orc, p, RTOL64)
+        assert_parity(rep, 1e-13)
+
+
+def test_parity_step_splitting(env):
+    """Results do not depend on how the steps are split across calls or on
+    reading the particles in between (the pending collision is completed the
+    same way)."""
+    O, lbmpcd = env
+    p = W.small_2d()
+    a = lbmpcd.Sim(p)
+    b = lbmpcd.Sim(p)
+    orc = O.Oracle(p)
+    a.step(6)
+    for k in range(3):
+        b.step(2)
+        if k < 2:
+            b.particles()  # completes the pending collision between calls
+    orc.step(6)
+    ra = compare_state(a, orc, p, RTOL64)
+    rb = compare_state(b, orc, p, RTOL64)
+    assert_parity(ra, RTOL64)
+    assert_parity(rb, RTOL64)
+
+
+def test_parity_profile_sampling(env):
+    O, lbmpcd = env
+    p = W.small_2d()
+    sim = lbmpcd.Sim(p)
+    orc = O.Oracle(p)
+    sim.step(2)
+    orc.step(2)
+    sim.sample(1)
+    orc.sample(1)
+    sim.step(3)
+    orc.step(3)
+    pg = sim.profile()
+    po, nsteps = orc.profile()
+    assert sim.stats()["sampled_steps"] == nsteps == 3
+    assert (pg[:, 0] == po[:, 0]).all()
+    assert np.abs(pg[:, 1:3] - po[:, 1:3]).max() <= 1e-11 * np.abs(po[:, 0]).max()
+
+
+def test_parity_set_state_roundtrip(env):
+    O, lbmpcd = env
+    p = W.small_2d()
+    sim = lbmpcd.Sim(p)
+    orc = O.Oracle(p)
+    rng = np.random.default_rng(4)
+    pos, vel = orc.particles()
+    vel = vel + 0.01 * rng.standard_normal(vel.shape)
+    orc.set_particles(pos, vel)
+    sim.set_state("vel", vel.reshape(-1))
+    f = orc.f() * (1 + 1e-3 * rng.standard_normal(orc.f().shape))
+    orc.set_f(f)
+    sim.set_state("pop", f.reshape(-1))
+    sim.step(3)
+    orc.step(3)
+    rep = compare_state(sim, orc, p, RTOL64)
+    assert_parity(rep, RTOL64)
+
+
+def test_batched_instances_match_standalone(env):
+    """A batch of uneven channels in one context equals each channel run
+    alone through the oracle (instance i keyed by (seed, i))."""
+    O, lbmpcd = env
+    ps = [W.small_2d(n=(24 + 8 * i, 20 + 2 * i, 1), ylo=6, yhi=14, ppc=5 + i, instance=i) for i in range(3)]
+    sim = lbmpcd.Sim(ps)
+    sim.step(4)
+    for i, p in enumerate(ps):
+        orc = O.Oracle(p)
+        orc.step(4)
+        rep = compare_state(sim, orc, p, RTOL64, inst=i)
+        banner(f"batch inst {i}: {rep}")
+        assert_parity(rep, RTOL64)
