@@ -70,12 +70,16 @@ enum lbmpcd_field {
     LBMPCD_PART_VEL = 5,   /* double[dim][Np] by particle id (get/set)             */
     LBMPCD_CELL_ID = 6,    /* int32[Np]: cell of each particle in the last binning */
     LBMPCD_CELL_COUNT = 7, /* int32[ncells]: occupancy of the last binning         */
-    LBMPCD_CELL_VCM = 8,   /* double[dim][ncells]: centre-of-mass velocity         */
+    LBMPCD_CELL_VCM = 8,   /* double[dim][ncells]: centre-of-mass velocity of the
+                              pending collision (only right after lbmpcd_step; the
+                              state is not changed)                               */
     LBMPCD_PROFILE = 9,    /* double[R][4]: per fine row sum n, sum v_x, v_y, v_z  */
     LBMPCD_UFINE = 10,     /* double[dim][nz*r][R][nx*r]: buffer-cell LB velocity  */
-    LBMPCD_STATS = 11      /* int64[8]: lb steps, sampled steps, dropped particles,
+    LBMPCD_STATS = 11,     /* int64[8]: lb steps, sampled steps, dropped particles,
                               misplaced particles, far moves, max tile fill,
                               particles, cells                                     */
+    LBMPCD_PART_VEL_PENDING = 12 /* double[dim][Np] by id: velocities before the
+                              collision of the last MPCD step (get only)          */
 };
 
 typedef struct lbmpcd_params {
@@ -176,6 +180,15 @@ int lbmpcd_sync(struct lbmpcd_ctx* c);
  */
 int lbmpcd_timing(struct lbmpcd_ctx* c, int32_t mode);
 int lbmpcd_timing_read(struct lbmpcd_ctx* c, double* out, int32_t n_classes);
+
+/*
+ * Replay of steady-state steps from a captured HIP graph (default on).  Two
+ * coupled steps are recorded once per buffer parity and sampling state and
+ * replayed on the context's stream; steps with a pending state change, with
+ * timing on, or an odd remainder are launched directly.  enable 0 launches
+ * every kernel directly.
+ */
+int lbmpcd_graphs(struct lbmpcd_ctx* c, int32_t enable);
 
 /* Free the host context; never frees caller memory. */
 void lbmpcd_destroy(struct lbmpcd_ctx* c);

@@ -298,6 +298,41 @@ void orc_destroy(orc_state* s) {
     free(s);
 }
 
+/* Slab and cell geometry of the parameter set (no arrays). */
+static void setup_geometry(orc_state* s) {
+    const orc_params* p = &s->p;
+    int r = p->refine, d = p->dim;
+    s->R = (p->yhi - p->ylo) * r;
+    s->Cx = p->nx * r;
+    s->Cz = (d == 3) ? p->nz * r : 1;
+    s->ywrap = (!p->walls_y && p->ylo == 0 && p->yhi == p->ny && p->buf_lo == 0 && p->buf_hi == 0);
+    s->CyB = s->ywrap ? s->R : s->R + 1;
+    s->bot_wall = p->walls_y && p->ylo == 0;
+    s->top_wall = p->walls_y && p->yhi == p->ny;
+    s->ncells = s->Cx * s->CyB * s->Cz;
+    s->Np = (int64_t)s->Cx * s->R * s->Cz * p->ppc;
+    s->a = 1.0 / r;
+    s->dt = 1.0 / p->substeps;
+    double alpha = p->alpha_deg * 3.141592653589793 / 180.0;
+    s->cos_a = cos(alpha);
+    s->sin_a = sin(alpha);
+}
+
+int orc_create_geometry(const orc_params* p, orc_state** out) {
+    *out = NULL;
+    int e = validate(p);
+    if (e) return e;
+    if (!p->mpcd) return 1;
+    orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
+    if (!s) return 2;
+    s->p = *p;
+    s->Q = orc_lattice(p->dim, s->c, s->w, s->opp);
+    s->N = (int64_t)p->nx * p->ny * p->nz;
+    setup_geometry(s);
+    *out = s;
+    return 0;
+}
+
 int orc_create(const orc_params* p, orc_state** out) {
     *out = NULL;
     int e = validate(p);
@@ -328,20 +363,7 @@ int orc_create(const orc_params* p, orc_state** out) {
 
     if (p->mpcd) {
         int r = p->refine, d = p->dim;
-        s->R = (p->yhi - p->ylo) * r;
-        s->Cx = p->nx * r;
-        s->Cz = (d == 3) ? p->nz * r : 1;
-        s->ywrap = (!p->walls_y && p->ylo == 0 && p->yhi == p->ny && p->buf_lo == 0 && p->buf_hi == 0);
-        s->CyB = s->ywrap ? s->R : s->R + 1;
-        s->bot_wall = p->walls_y && p->ylo == 0;
-        s->top_wall = p->walls_y && p->yhi == p->ny;
-        s->ncells = s->Cx * s->CyB * s->Cz;
-        s->Np = (int64_t)s->Cx * s->R * s->Cz * p->ppc;
-        s->a = 1.0 / r;
-        s->dt = 1.0 / p->substeps;
-        double alpha = p->alpha_deg * 3.141592653589793 / 180.0;
-        s->cos_a = cos(alpha);
-        s->sin_a = sin(alpha);
+        setup_geometry(s);
         for (int k = 0; k < 3; ++k) {
             s->pos[k] = (double*)calloc((size_t)s->Np, sizeof(double));
             s->vel[k] = (double*)calloc((size_t)s->Np, sizeof(double));
@@ -493,13 +515,20 @@ static void interp_axis(int L, int periodic, double X, int* i0, int* i1, double*
     }
 }
 
+static void interpolate_from(const orc_state* s, const double* unode, double* ufine);
+
 static void interpolate_buffers(orc_state* s) {
-    const orc_params* p = &s->p;
     for (int64_t n = 0; n < s->N; ++n) {
         double rho, u[3];
         node_moments(s, n, &rho, u);
         for (int k = 0; k < 3; ++k) s->unode[k * s->N + n] = u[k];
     }
+    interpolate_from(s, s->unode, s->ufine);
+}
+
+/* buffer fine-cell velocities ufine[3][Cz][R][Cx] from node velocities unode[3][N] */
+static void interpolate_from(const orc_state* s, const double* unode, double* ufine) {
+    const orc_params* p = &s->p;
     int r = p->refine;
     int64_t nf = (int64_t)s->Cx * s->R * s->Cz;
     for (int K = 0; K < s->Cz; ++K)
@@ -523,14 +552,14 @@ static void interpolate_buffers(orc_state* s) {
                     for (int c = 0; c < (p->dim == 3 ? 2 : 1); ++c) {
                         double row[2];
                         for (int b = 0; b < 2; ++b) {
-                            double u0 = (iy[b] < 0) ? 0.0 : s->unode[k * s->N + node_index(s, ix[0], iy[b], iz[c])];
-                            double u1 = (iy[b] < 0) ? 0.0 : s->unode[k * s->N + node_index(s, ix[1], iy[b], iz[c])];
+                            double u0 = (iy[b] < 0) ? 0.0 : unode[k * s->N + node_index(s, ix[0], iy[b], iz[c])];
+                            double u1 = (iy[b] < 0) ? 0.0 : unode[k * s->N + node_index(s, ix[1], iy[b], iz[c])];
                             row[b] = wx[0] * u0 + wx[1] * u1;
                         }
                         val[c] = wy[0] * row[0] + wy[1] * row[1];
                     }
                     double v = (p->dim == 3) ? wz[0] * val[0] + wz[1] * val[1] : val[0];
-                    s->ufine[k * nf + ((int64_t)K * s->R + J) * s->Cx + I] = v;
+                    ufine[k * nf + ((int64_t)K * s->R + J) * s->Cx + I] = v;
                 }
             }
         }
@@ -549,21 +578,38 @@ static int fine_row(const orc_state* s, double y) {
 /* Exchange step (Alg. 1): particles whose unshifted position lies in a
  * buffer get a fresh velocity from the Maxwell-Boltzmann distribution about
  * the interpolated LB velocity; variance kT/m per component. */
-static void reinject(orc_state* s, uint32_t t, uint32_t sub) {
+/* fine cell (unshifted) of a position; -1 when it is not a buffer cell */
+static int64_t buffer_cell(const orc_state* s, const double r[3]) {
     const orc_params* p = &s->p;
-    int r = p->refine;
-    int64_t nf = (int64_t)s->Cx * s->R * s->Cz;
+    int rf = p->refine;
+    int J = fine_row(s, r[1]);
+    int inbuf = (J < p->buf_lo * rf) || (J >= s->R - p->buf_hi * rf);
+    if (!inbuf) return -1;
+    int I = clampi((int)floor(r[0] * rf), 0, s->Cx - 1);
+    int K = (p->dim == 3) ? clampi((int)floor(r[2] * rf), 0, s->Cz - 1) : 0;
+    return ((int64_t)K * s->R + J) * s->Cx + I;
+}
+
+/* redraw one buffer particle about the LB velocity u of its fine cell */
+static void reinject_one(const orc_state* s, uint32_t id, uint32_t t, uint32_t sub, const double u[3],
+                         double v[3]) {
+    const orc_params* p = &s->p;
     double sd = sqrt(p->kT / p->mass);
+    double z[3];
+    rng_normals(p, id, t, sub, P_REINJ, z);
+    for (int d = 0; d < p->dim; ++d) v[d] = st(s, u[d] + sd * z[d]);
+}
+
+static void reinject(orc_state* s, uint32_t t, uint32_t sub) {
+    int64_t nf = (int64_t)s->Cx * s->R * s->Cz;
     for (int64_t k = 0; k < s->Np; ++k) {
-        int J = fine_row(s, s->pos[1][k]);
-        int inbuf = (J < p->buf_lo * r) || (J >= s->R - p->buf_hi * r);
-        if (!inbuf) continue;
-        int I = clampi((int)floor(s->pos[0][k] * r), 0, s->Cx - 1);
-        int K = (p->dim == 3) ? clampi((int)floor(s->pos[2][k] * r), 0, s->Cz - 1) : 0;
-        int64_t fc = ((int64_t)K * s->R + J) * s->Cx + I;
-        double z[3];
-        rng_normals(p, (uint32_t)k, t, sub, P_REINJ, z);
-        for (int d = 0; d < p->dim; ++d) s->vel[d][k] = st(s, s->ufine[d * nf + fc] + sd * z[d]);
+        double r[3] = {s->pos[0][k], s->pos[1][k], s->pos[2][k]};
+        int64_t fc = buffer_cell(s, r);
+        if (fc < 0) continue;
+        double u[3] = {0.0, 0.0, 0.0}, v[3];
+        for (int d = 0; d < s->p.dim; ++d) u[d] = s->ufine[d * nf + fc];
+        reinject_one(s, (uint32_t)k, t, sub, u, v);
+        for (int d = 0; d < s->p.dim; ++d) s->vel[d][k] = v[d];
     }
 }
 
@@ -586,11 +632,11 @@ static double wrap_periodic(const orc_state* s, double x, double lo, double L) {
  * LB-facing slab face the particle is re-wrapped periodically across the
  * slab (paper: no particles are injected, mass is conserved), or, when the
  * opposite face is a wall, reflected specularly. */
-static void stream_particle(orc_state* s, int64_t k) {
+static void stream_one(const orc_state* s, double r[3], double v[3]) {
     const orc_params* p = &s->p;
     double dt = s->dt;
     double r0[3], v0[3];
-    for (int d = 0; d < 3; ++d) { r0[d] = s->pos[d][k]; v0[d] = s->vel[d][k]; }
+    for (int d = 0; d < 3; ++d) { r0[d] = r[d]; v0[d] = v[d]; }
     double r1[3] = {r0[0], r0[1], r0[2]}, v1[3] = {v0[0], v0[1], v0[2]};
     for (int d = 0; d < p->dim; ++d) {
         double gh = 0.5 * p->g[d] * dt, gdt = p->g[d] * dt;
@@ -638,7 +684,14 @@ static void stream_particle(orc_state* s, int64_t k) {
     }
     r1[0] = wrap_periodic(s, r1[0], 0.0, (double)p->nx);
     if (p->dim == 3) r1[2] = wrap_periodic(s, r1[2], 0.0, (double)p->nz);
-    for (int d = 0; d < p->dim; ++d) { s->pos[d][k] = r1[d]; s->vel[d][k] = v1[d]; }
+    for (int d = 0; d < p->dim; ++d) { r[d] = r1[d]; v[d] = v1[d]; }
+}
+
+static void stream_particle(orc_state* s, int64_t k) {
+    double r[3], v[3];
+    for (int d = 0; d < 3; ++d) { r[d] = s->pos[d][k]; v[d] = s->vel[d][k]; }
+    stream_one(s, r, v);
+    for (int d = 0; d < s->p.dim; ++d) { s->pos[d][k] = r[d]; s->vel[d][k] = v[d]; }
 }
 
 /* READING: the sample instant is right after streaming.  The per-LB-step
@@ -685,23 +738,67 @@ static int bin_coord(const orc_state* s, double x, double lo, double sh) {
     return (int)floor(t);
 }
 
-static int32_t particle_cell(const orc_state* s, int64_t k, const double sh[3]) {
+static int32_t cell_of_pos(const orc_state* s, const double r[3], const double sh[3]) {
     const orc_params* p = &s->p;
-    int ix = bin_coord(s, s->pos[0][k], 0.0, sh[0]);
+    int ix = bin_coord(s, r[0], 0.0, sh[0]);
     if (ix >= s->Cx) ix -= s->Cx;
-    int iy = bin_coord(s, s->pos[1][k], (double)p->ylo, sh[1]);
+    int iy = bin_coord(s, r[1], (double)p->ylo, sh[1]);
     if (s->ywrap && iy >= s->R) iy -= s->R;
     int iz = 0;
     if (p->dim == 3) {
-        iz = bin_coord(s, s->pos[2][k], 0.0, sh[2]);
+        iz = bin_coord(s, r[2], 0.0, sh[2]);
         if (iz >= s->Cz) iz -= s->Cz;
     }
     return (int32_t)(ix + s->Cx * (iy + s->CyB * iz));
 }
 
+static int32_t particle_cell(const orc_state* s, int64_t k, const double sh[3]) {
+    double r[3] = {s->pos[0][k], s->pos[1][k], s->pos[2][k]};
+    return cell_of_pos(s, r, sh);
+}
+
 /* SRD collision of every cell (Eq. 4).  READING: 2D sign and 3D axis per
  * cell and step from the ROT stream; cells cut by a wall get virtual
  * particles up to the nominal occupancy. */
+/* SRD collision of the n particles of cell c: v is [dim][n] (unit-mass
+ * velocities, updated in place and rounded to the store precision); vcm
+ * receives the centre-of-mass velocity including virtual wall particles. */
+static void collide_one(const orc_state* s, int32_t c, uint32_t t, uint32_t sub, const double sh[3], int32_t n,
+                        double* v, double vcm_out[3]) {
+    const orc_params* p = &s->p;
+    int d = p->dim;
+    int iy = (c / s->Cx) % s->CyB;
+    double pv[3] = {0.0, 0.0, 0.0}, mv = 0.0;
+    int cut = (sh[1] > 0.0) && ((s->bot_wall && iy == 0) || (s->top_wall && iy == s->R));
+    if (cut && n < p->ppc) {
+        double z[3];
+        rng_normals(p, (uint32_t)c, t, sub, P_WALL, z);
+        int nv = p->ppc - n;
+        double sdv = sqrt((double)nv * p->kT / p->mass);
+        for (int k = 0; k < d; ++k) pv[k] = sdv * z[k];
+        mv = (double)nv;
+    }
+    uint32_t w[4];
+    rng_block(p, (uint32_t)c, t, sub, P_ROT, 0, w);
+    double sign2d = (w[0] & 1u) ? 1.0 : -1.0;
+    double axis[3] = {0.0, 0.0, 1.0};
+    if (d == 3) {
+        double u0 = orc_u01(w[0], w[1]), u1 = orc_u01(w[2], w[3]);
+        double nz = 2.0 * u0 - 1.0, phi = 6.283185307179586 * u1;
+        double sxy = sqrt(fmax(0.0, 1.0 - nz * nz));
+        axis[0] = sxy * cos(phi);
+        axis[1] = sxy * sin(phi);
+        axis[2] = nz;
+    }
+    /* virtual momentum enters in units of m; the rotation routine uses
+     * unit mass so the momentum is divided by m */
+    double pvu[3] = {pv[0] / p->mass, pv[1] / p->mass, pv[2] / p->mass};
+    double vc[3] = {0.0, 0.0, 0.0};
+    orc_srd_rotate(d, n, v, s->cos_a, s->sin_a, sign2d, axis, pvu, mv, vc);
+    for (int k = 0; k < 3; ++k) vcm_out[k] = vc[k];
+    for (int i = 0; i < d * n; ++i) v[i] = st(s, v[i]);
+}
+
 static void collide_cells(orc_state* s, uint32_t t, uint32_t sub, const double sh[3]) {
     const orc_params* p = &s->p;
     int d = p->dim;
@@ -709,54 +806,31 @@ static void collide_cells(orc_state* s, uint32_t t, uint32_t sub, const double s
         int32_t n = s->count[c];
         for (int k = 0; k < 3; ++k) s->vcm[k * s->ncells + c] = 0.0;
         if (n == 0) continue;
-        int iy = (c / s->Cx) % s->CyB;
-        double pv[3] = {0.0, 0.0, 0.0}, mv = 0.0;
-        int cut = (sh[1] > 0.0) && ((s->bot_wall && iy == 0) || (s->top_wall && iy == s->R));
-        if (cut && n < p->ppc) {
-            double z[3];
-            rng_normals(p, (uint32_t)c, t, sub, P_WALL, z);
-            int nv = p->ppc - n;
-            double sdv = sqrt((double)nv * p->kT / p->mass);
-            for (int k = 0; k < d; ++k) pv[k] = sdv * z[k];
-            mv = (double)nv;
-        }
-        uint32_t w[4];
-        rng_block(p, (uint32_t)c, t, sub, P_ROT, 0, w);
-        double sign2d = (w[0] & 1u) ? 1.0 : -1.0;
-        double axis[3] = {0.0, 0.0, 1.0};
-        if (d == 3) {
-            double u0 = orc_u01(w[0], w[1]), u1 = orc_u01(w[2], w[3]);
-            double nz = 2.0 * u0 - 1.0, phi = 6.283185307179586 * u1;
-            double sxy = sqrt(fmax(0.0, 1.0 - nz * nz));
-            axis[0] = sxy * cos(phi);
-            axis[1] = sxy * sin(phi);
-            axis[2] = nz;
-        }
         double* v = s->scratch;
         if (n > 4096) v = (double*)malloc(sizeof(double) * 3 * (size_t)n);
         for (int i = 0; i < n; ++i) {
             int32_t id = s->order[s->start[c] + i];
             for (int k = 0; k < d; ++k) v[k * n + i] = s->vel[k][id];
         }
-        /* virtual momentum enters in units of m; the rotation routine uses
-         * unit mass so the momentum is divided by m */
-        double pvu[3] = {pv[0] / p->mass, pv[1] / p->mass, pv[2] / p->mass};
         double vc[3];
-        orc_srd_rotate(d, n, v, s->cos_a, s->sin_a, sign2d, axis, pvu, mv, vc);
+        collide_one(s, c, t, sub, sh, n, v, vc);
         for (int k = 0; k < d; ++k) s->vcm[k * s->ncells + c] = vc[k];
         for (int i = 0; i < n; ++i) {
             int32_t id = s->order[s->start[c] + i];
-            for (int k = 0; k < d; ++k) s->vel[k][id] = st(s, v[k * n + i]);
+            for (int k = 0; k < d; ++k) s->vel[k][id] = v[k * n + i];
         }
         if (v != s->scratch) free(v);
     }
 }
 
 static void mpcd_substep(orc_state* s, uint32_t t, uint32_t sub) {
+    /* READING: one sample per LB step, right after the streaming of its last
+     * MPCD step */
+    const int sample = (int)sub == s->p.substeps - 1;
     reinject(s, t, sub);
     for (int64_t k = 0; k < s->Np; ++k) {
         stream_particle(s, k);
-        sample_particle(s, k);
+        if (sample) sample_particle(s, k);
     }
     double sh[3];
     draw_shift(s, t, sub, sh);
@@ -872,4 +946,55 @@ void orc_refresh_ufine(orc_state* s) {
 
 void orc_get_step_acc(const orc_state* s, double* acc) {
     memcpy(acc, s->acc, sizeof(double) * 4 * (size_t)s->p.nx * s->R * s->p.nz);
+}
+
+/* ------------------------------------------------------------------------
+ * Per-element building blocks on caller arrays, for checking sampled outputs
+ * of runs too large for the full oracle.  `s` may come from
+ * orc_create_geometry (no arrays).  Arrays are [dim][n].
+ * ---------------------------------------------------------------------- */
+void orc_grid_shift(const orc_state* s, uint32_t t, uint32_t sub, double sh[3]) { draw_shift(s, t, sub, sh); }
+
+void orc_bin_positions(const orc_state* s, const double sh[3], int64_t n, const double* pos, int32_t* cell) {
+    for (int64_t k = 0; k < n; ++k) {
+        double r[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < s->p.dim; ++d) r[d] = pos[d * n + k];
+        cell[k] = cell_of_pos(s, r, sh);
+    }
+}
+
+/* Exchange step (buffer particles redrawn about u, given per particle) and
+ * streaming of one MPCD step, in place. */
+void orc_exchange_stream(const orc_state* s, uint32_t t, uint32_t sub, int64_t n, const uint32_t* ids,
+                         double* pos, double* vel, const double* u) {
+    for (int64_t k = 0; k < n; ++k) {
+        double r[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0}, uu[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < s->p.dim; ++d) {
+            r[d] = pos[d * n + k];
+            v[d] = vel[d * n + k];
+            uu[d] = u[d * n + k];
+        }
+        if (buffer_cell(s, r) >= 0) reinject_one(s, ids[k], t, sub, uu, v);
+        stream_one(s, r, v);
+        for (int d = 0; d < s->p.dim; ++d) {
+            pos[d * n + k] = r[d];
+            vel[d * n + k] = v[d];
+        }
+    }
+}
+
+/* 1 when the fine cell of the position is a buffer cell */
+int32_t orc_in_buffer(const orc_state* s, const double r[3]) { return buffer_cell(s, r) >= 0; }
+
+/* SRD collision of one cell (index c of the shifted grid of (t, sub)). */
+void orc_collide_cell(const orc_state* s, int32_t c, uint32_t t, uint32_t sub, const double sh[3], int32_t n,
+                      double* vel, double vcm[3]) {
+    collide_one(s, c, t, sub, sh, n, vel, vcm);
+}
+
+/* Buffer fine-cell velocities [3][Cz][R][Cx] (zero outside the buffers) from
+ * given node velocities [3][N] (bi/trilinear interpolation, Alg. 2). */
+void orc_interpolate(const orc_state* s, const double* unode, double* ufine) {
+    memset(ufine, 0, sizeof(double) * 3 * (size_t)s->Cx * s->R * s->Cz);
+    interpolate_from(s, unode, ufine);
 }

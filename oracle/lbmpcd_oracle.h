@@ -91,6 +91,23 @@ void orc_get_shift(const orc_state* s, double sh[3]);
 /* recompute the buffer fine-cell velocities from the current populations */
 void orc_refresh_ufine(orc_state* s);
 
+/* geometry-only state for the per-element functions below (no arrays) */
+int orc_create_geometry(const orc_params* p, orc_state** out);
+/* grid shift of MPCD step (t, sub) */
+void orc_grid_shift(const orc_state* s, uint32_t t, uint32_t sub, double sh[3]);
+/* shifted-grid cell of n positions pos[dim][n] */
+void orc_bin_positions(const orc_state* s, const double sh[3], int64_t n, const double* pos, int32_t* cell);
+/* exchange step + streaming of one MPCD step for n particles in place; u[dim][n]
+ * is the interpolated LB velocity of each particle's fine cell */
+void orc_exchange_stream(const orc_state* s, uint32_t t, uint32_t sub, int64_t n, const uint32_t* ids,
+                         double* pos, double* vel, const double* u);
+int32_t orc_in_buffer(const orc_state* s, const double r[3]);
+/* buffer fine-cell velocities ufine[3][Cz][R][Cx] from node velocities unode[3][N] */
+void orc_interpolate(const orc_state* s, const double* unode, double* ufine);
+/* SRD collision of the n particles (vel[dim][n], in place) of cell c */
+void orc_collide_cell(const orc_state* s, int32_t c, uint32_t t, uint32_t sub, const double sh[3], int32_t n,
+                      double* vel, double vcm[3]);
+
 /* ---- building blocks, exported for the pins ---------------------------- */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_u01(uint32_t lo, uint32_t hi);

@@ -294,3 +294,84 @@ def counting_sort(cell, nc):
     order = np.empty(len(cell), np.int32)
     lib().orc_counting_sort(len(cell), _ptr(cell), nc, _ptr(count), _ptr(start), _ptr(order))
     return count, start, order
+
+
+class Probe:
+    """Geometry-only oracle state: per-particle and per-cell steps of the
+    method on caller arrays, for sampled checks of runs too large to run
+    through the full oracle."""
+
+    def __init__(self, p: dict):
+        self.p = dict(p)
+        L = lib()
+        if not getattr(L, "_probe_types", False):
+            P = C.c_void_p
+            L.orc_create_geometry.argtypes = [C.POINTER(_Params), C.POINTER(C.c_void_p)]
+            L.orc_create_geometry.restype = C.c_int
+            L.orc_grid_shift.argtypes = [P, C.c_uint32, C.c_uint32, P]
+            L.orc_bin_positions.argtypes = [P, P, C.c_int64, P, P]
+            L.orc_exchange_stream.argtypes = [P, C.c_uint32, C.c_uint32, C.c_int64, P, P, P, P]
+            L.orc_in_buffer.argtypes = [P, P]
+            L.orc_in_buffer.restype = C.c_int32
+            L.orc_collide_cell.argtypes = [P, C.c_int32, C.c_uint32, C.c_uint32, P, C.c_int32, P, P]
+            L.orc_interpolate.argtypes = [P, P, P]
+            L._probe_types = True
+        self._L = L
+        self._ps = params_struct(p)
+        h = C.c_void_p()
+        rc = L.orc_create_geometry(C.byref(self._ps), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"orc_create_geometry failed ({rc})")
+        self._h = h
+        self.dim = p["dim"]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._L.orc_destroy(h)
+            self._h = None
+
+    def shift(self, t: int, sub: int) -> np.ndarray:
+        out = np.zeros(3)
+        self._L.orc_grid_shift(self._h, t, sub, _ptr(out))
+        return out
+
+    def bin(self, sh, pos) -> np.ndarray:
+        pos = np.ascontiguousarray(pos, np.float64)
+        sh = np.ascontiguousarray(sh, np.float64)
+        n = pos.shape[1]
+        out = np.empty(n, np.int32)
+        self._L.orc_bin_positions(self._h, _ptr(sh), n, _ptr(pos), _ptr(out))
+        return out
+
+    def exchange_stream(self, t, sub, ids, pos, vel, u):
+        ids = np.ascontiguousarray(ids, np.uint32)
+        pos = np.ascontiguousarray(pos, np.float64).copy()
+        vel = np.ascontiguousarray(vel, np.float64).copy()
+        u = np.ascontiguousarray(u, np.float64)
+        self._L.orc_exchange_stream(self._h, t, sub, len(ids), _ptr(ids), _ptr(pos), _ptr(vel), _ptr(u))
+        return pos, vel
+
+    def in_buffer(self, r) -> bool:
+        rr = np.zeros(3)
+        rr[: len(r)] = r
+        return bool(self._L.orc_in_buffer(self._h, _ptr(rr)))
+
+    def interpolate(self, unode) -> np.ndarray:
+        """Buffer fine-cell velocities [dim][Cz][R][Cx] from node velocities [3][nz][ny][nx]."""
+        p = self.p
+        r = p["refine"]
+        R = (p["yhi"] - p["ylo"]) * r
+        Cx = p["n"][0] * r
+        Cz = p["n"][2] * r if self.dim == 3 else 1
+        u = np.ascontiguousarray(unode, np.float64)
+        out = np.zeros((3, Cz, R, Cx))
+        self._L.orc_interpolate(self._h, _ptr(u), _ptr(out))
+        return out[: self.dim]
+
+    def collide_cell(self, c, t, sub, sh, vel):
+        v = np.ascontiguousarray(vel, np.float64).copy()
+        sh = np.ascontiguousarray(sh, np.float64)
+        vcm = np.zeros(3)
+        self._L.orc_collide_cell(self._h, int(c), t, sub, _ptr(sh), v.shape[1], _ptr(v), _ptr(vcm))
+        return v, vcm[: self.dim]

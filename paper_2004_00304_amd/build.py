@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmpcd.so")
-SOURCES = ["api.hip", "kernels_lb.hip", "kernels_mpcd.hip"]
+SOURCES = ["api.hip", "kernels_lb.hip", "kernels_mpcd.hip", "kernels_util.hip"]
 ARCH = os.environ.get("LBMPCD_ARCH", "gfx950")
 
 FLAGS = [

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -36,6 +37,7 @@ struct lbmpcd_ctx {
     double* uf = nullptr;
     double* acc = nullptr;
     double* prof = nullptr;
+    double* shifts = nullptr;   // [n_inst][2][S][3] grid shifts drawn by the LB kernel
     DevStats* stats = nullptr;
     long long* clock = nullptr;
     void* scratch = nullptr;
@@ -45,6 +47,7 @@ struct lbmpcd_ctx {
               total_particles = 0, total_slab = 0;
     int ppt = 4;
     size_t lds = 0;
+    int staged = 1;               // stage the output tile in LDS before writing it out
     long long t = 0;
     bool pending = false, sampling = false, any_feedback = false;
     long long sampled_steps = 0;
@@ -57,6 +60,11 @@ struct lbmpcd_ctx {
     std::vector<hipEvent_t> pool;
     double timing_ms[4] = {0, 0, 0, 0};
     long long timing_n[4] = {0, 0, 0, 0};
+    // steady-state steps replayed from a captured graph
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_key = -1;
 };
 
 namespace {
@@ -129,7 +137,8 @@ int geometry(const lbmpcd_params& p, Geometry& g, std::string& msg) {
     g.nty = (g.CyB + g.Ty - 1) / g.Ty;
     g.ntz = (g.Cz + g.Tz - 1) / g.Tz;
     g.ntiles = (long long)g.ntx * g.nty * g.ntz;
-    g.init_per = (g.Np + g.ntiles - 1) / g.ntiles;
+    // initial placement: the particles of every slab cell in the tile of that cell
+    g.init_per = (long long)g.nct * p.ppc;
     if (g.init_per > g.cap) { msg = "initial placement exceeds the tile capacity"; return 1; }
     g.by0 = std::max(p.ylo - 1, 0);
     int by1 = std::min(p.yhi + 1, p.n[1]);
@@ -175,7 +184,7 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
 }
 
 struct Layout {
-    size_t desc, tile_inst, f0, f1, ub, uf, acc, prof, fill0, fill1, stats, clock, scratch, end;
+    size_t desc, tile_inst, f0, f1, ub, uf, acc, prof, fill0, fill1, stats, clock, shifts, scratch, end;
     size_t part[2][7];
     size_t acc_bytes, prof_bytes, scratch_bytes;
 };
@@ -216,6 +225,7 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
         d.mass = q.mass; d.kT = q.kT;
         d.key0 = (uint32_t)(q.seed & 0xFFFFFFFFu);
         d.key1 = (uint32_t)(q.seed >> 32) ^ q.instance;
+        d.S = q.mpcd ? q.substeps : 0;
         node += d.N;
         band += g.nband;
         ufine += g.nufine;
@@ -229,7 +239,7 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
         fsz = std::max<size_t>(fsz, (size_t)g.ncells * 8 * q.dim);
         max_field = std::max(max_field, fsz);
     }
-    if (slots >= (1LL << 32) - 1) { msg = "too many particle slots for 32-bit slot indices"; return LBMPCD_E_INVALID; }
+    if (slots >= 0x7FFFFFFFLL) { msg = "too many particle slots for 31-bit slot indices"; return LBMPCD_E_INVALID; }
     tot[0] = node; tot[1] = band; tot[2] = ufine; tot[3] = tiles; tot[4] = slots; tot[5] = parts; tot[6] = slab;
     const int dim = p[0].dim;
     const size_t lbw = p[0].lb_fp == 64 ? 8 : 4, pw = p[0].part_fp == 64 ? 8 : 4;
@@ -253,6 +263,7 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
     }
     L.stats = take(sizeof(DevStats));
     L.clock = take(sizeof(long long));
+    L.shifts = take(sizeof(double) * 6 * (size_t)n * (p[0].mpcd ? p[0].substeps : 1));
     L.scratch_bytes = std::min<size_t>(align_up(max_field, 256), (size_t)64 << 20);
     L.scratch = take(L.scratch_bytes);
     L.end = o;
@@ -322,9 +333,9 @@ int finalize(lbmpcd_ctx* c) {
     L.in = c->part[c->pcur]; L.out = c->part[c->pcur];
     L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
     L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
-    L.stats = c->stats; L.clock = c->clock;
+    L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts;
     L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
-    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds;
+    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.staged = c->staged;
     HIPCHK(c, launch_particles(L, c->stream));
     c->pending = false;
     return 0;
@@ -425,6 +436,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     }
     c->stats = (DevStats*)(c->ws + L.stats);
     c->clock = (long long*)(c->ws + L.clock);
+    c->shifts = (double*)(c->ws + L.shifts);
     c->scratch = c->ws + L.scratch;
     c->scratch_bytes = L.scratch_bytes;
     int cap_max = 64;
@@ -433,7 +445,8 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
         if (d.feedback) c->any_feedback = true;
     }
     c->ppt = cap_max <= 2 * WG ? 2 : (cap_max <= 4 * WG ? 4 : 8);
-    c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max);
+    if (const char* e = std::getenv("LBMPCD_STAGED_WRITES")) c->staged = std::atoi(e) != 0;
+    c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max, c->staged);
 
     // tile -> instance table
     std::vector<int> tinst((size_t)std::max<long long>(c->total_tiles, 1));
@@ -468,15 +481,15 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     return 0;
 }
 
-int lbmpcd_step(lbmpcd_ctx* c, int32_t n_lb_steps) {
-    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
-    if (c->sticky) return c->sticky;
-    if (n_lb_steps < 0) return fail(c, LBMPCD_E_INVALID, "negative step count");
-    hipStream_t s = c->stream;
-    for (int it = 0; it < n_lb_steps; ++it) {
+namespace {
+
+// Enqueue one coupled LB step on stream s (the context's stream, or the
+// capture stream while a graph is recorded).
+int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
+    {
         HIPCHK(c, timed(c, 0, [&] {
                    return launch_lb_step(c->dim, c->lb_fp, c->d_desc, c->n_inst, c->total_nodes, c->f[c->fcur],
-                                         c->f[c->fcur ^ 1], c->clock, s);
+                                         c->f[c->fcur ^ 1], c->clock, c->shifts, c->mpcd ? c->S : 0, s);
                }));
         c->fcur ^= 1;
         if (c->mpcd) {
@@ -495,21 +508,80 @@ int lbmpcd_step(lbmpcd_ctx* c, int32_t n_lb_steps) {
                 L.in = c->part[c->pcur]; L.out = c->part[c->pcur ^ 1];
                 L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
                 L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
-                L.stats = c->stats; L.clock = c->clock;
+                L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts; L.shifts = c->shifts; L.shifts = c->shifts;
                 L.coll_dt = sub > 0 ? 0 : -1;
                 L.coll_s = sub > 0 ? sub - 1 : c->S - 1;
                 L.str_s = sub;
-                L.do_fb = c->any_feedback ? 1 : 0;
-                L.do_prof = c->sampling ? 1 : 0;
-                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds;
+                // samples are taken in the last MPCD step of the LB step
+                L.do_fb = (c->any_feedback && sub == c->S - 1) ? 1 : 0;
+                L.do_prof = (c->sampling && sub == c->S - 1) ? 1 : 0;
+                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.staged = c->staged;
                 HIPCHK(c, timed(c, 3, [&] { return launch_particles(L, s); }));
                 c->pcur ^= 1;
                 c->pending = true;
             }
         }
+    }
+    return 0;
+}
+
+// Record two coupled steps (after which both ping-pong parities are back
+// where they started) into an executable graph.  Kernels read the LB step
+// index from the device clock, so the graph can be replayed indefinitely.
+int build_graph(lbmpcd_ctx* c) {
+    if (c->graph_exec) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+    }
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const int f0 = c->fcur, p0 = c->pcur;
+    const bool pend0 = c->pending, timing0 = c->timing;
+    c->timing = false;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int e = enqueue_one_step(c, c->cap_stream);
+    if (!e) e = enqueue_one_step(c, c->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t he = hipStreamEndCapture(c->cap_stream, &g);
+    c->fcur = f0; c->pcur = p0; c->pending = pend0; c->timing = timing0;
+    if (e) { if (g) (void)hipGraphDestroy(g); return e; }
+    if (he != hipSuccess) return fail(c, LBMPCD_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(he));
+    he = hipGraphInstantiateWithFlags(&c->graph_exec, g, 0);
+    (void)hipGraphDestroy(g);
+    if (he != hipSuccess) return fail(c, LBMPCD_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(he));
+    c->graph_key = (c->fcur << 2) | (c->pcur << 1) | (c->sampling ? 1 : 0);
+    return 0;
+}
+
+}  // namespace
+
+int lbmpcd_step(lbmpcd_ctx* c, int32_t n_lb_steps) {
+    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
+    if (c->sticky) return c->sticky;
+    if (n_lb_steps < 0) return fail(c, LBMPCD_E_INVALID, "negative step count");
+    int it = 0;
+    while (it < n_lb_steps) {
+        const bool steady = !c->mpcd || c->pending;
+        if (c->use_graphs && !c->timing && steady && n_lb_steps - it >= 2) {
+            const int key = (c->fcur << 2) | (c->pcur << 1) | (c->sampling ? 1 : 0);
+            if (!c->graph_exec || c->graph_key != key)
+                if (int e = build_graph(c)) return e;
+            HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+            c->t += 2;
+            if (c->sampling) c->sampled_steps += 2;
+            it += 2;
+            continue;
+        }
+        if (int e = enqueue_one_step(c, c->stream)) return e;
         c->t++;
         if (c->sampling) c->sampled_steps++;
+        ++it;
     }
+    return 0;
+}
+
+int lbmpcd_graphs(lbmpcd_ctx* c, int32_t enable) {
+    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
+    c->use_graphs = enable != 0;
     return 0;
 }
 
@@ -523,7 +595,8 @@ int lbmpcd_field_bytes(const lbmpcd_ctx* c, int32_t field, int32_t inst, size_t*
         case LBMPCD_PI: *bytes = 6 * N * 8; break;
         case LBMPCD_POP: *bytes = (size_t)c->Q * N * (c->lb_fp == 64 ? 8 : 4); break;
         case LBMPCD_PART_POS:
-        case LBMPCD_PART_VEL: *bytes = (size_t)c->dim * d.Np * 8; break;
+        case LBMPCD_PART_VEL:
+        case LBMPCD_PART_VEL_PENDING: *bytes = (size_t)c->dim * d.Np * 8; break;
         case LBMPCD_CELL_ID: *bytes = (size_t)d.Np * 4; break;
         case LBMPCD_CELL_COUNT: *bytes = (size_t)d.ncells * 4; break;
         case LBMPCD_CELL_VCM: *bytes = (size_t)c->dim * d.ncells * 8; break;
@@ -562,10 +635,14 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
         }
         case LBMPCD_PART_POS:
         case LBMPCD_PART_VEL:
-            if (int e = finalize(c)) return e;
+        case LBMPCD_PART_VEL_PENDING:
+            // collisions move no particle; velocities complete the pending collision
+            // unless the pre-collision values are asked for
+            if (field == LBMPCD_PART_VEL)
+                if (int e = finalize(c)) return e;
             HIPCHK(c, launch_gather(c->dim, c->part_fp, c->d_desc, inst, c->part[c->pcur], c->fill[c->pcur],
                                     field == LBMPCD_PART_POS ? (double*)dst : nullptr,
-                                    field == LBMPCD_PART_VEL ? (double*)dst : nullptr, nullptr, slots, tl, sl, s));
+                                    field != LBMPCD_PART_POS ? (double*)dst : nullptr, nullptr, slots, tl, sl, s));
             return 0;
         case LBMPCD_CELL_ID:
             if (c->t == 0) return fail(c, LBMPCD_E_STATE, "no binning before the first step");
@@ -584,14 +661,15 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             ParticleLaunch L{};
             L.dim = c->dim; L.part_fp = c->part_fp; L.ppt = c->ppt; L.mode = 1;
             L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
-            L.in = c->part[c->pcur]; L.out = c->part[c->pcur];
+            // the pending collision is evaluated into the idle particle buffer, so
+            // the state (and the other instances' pending collisions) is untouched
+            L.in = c->part[c->pcur]; L.out = c->part[c->pcur ^ 1];
             L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
             L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
-            L.stats = c->stats; L.clock = c->clock;
+            L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts; L.shifts = c->shifts;
             L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
-            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds;
+            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds; L.staged = c->staged;
             HIPCHK(c, launch_particles(L, s));
-            c->pending = false;
             return 0;
         }
         case LBMPCD_PROFILE:
@@ -646,8 +724,9 @@ int lbmpcd_moments(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t
 }
 
 int lbmpcd_get_state(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t bytes, int32_t on_dev) {
-    if (field != LBMPCD_POP && field != LBMPCD_PART_POS && field != LBMPCD_PART_VEL)
-        return fail(c, LBMPCD_E_INVALID, "get_state handles POP, PART_POS, PART_VEL");
+    if (field != LBMPCD_POP && field != LBMPCD_PART_POS && field != LBMPCD_PART_VEL &&
+        field != LBMPCD_PART_VEL_PENDING)
+        return fail(c, LBMPCD_E_INVALID, "get_state handles POP, PART_POS, PART_VEL, PART_VEL_PENDING");
     return lbmpcd_moments(c, field, inst, dst, bytes, on_dev);
 }
 
@@ -735,6 +814,8 @@ void lbmpcd_destroy(lbmpcd_ctx* c) {
         if (m.b) (void)hipEventDestroy(m.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }
 

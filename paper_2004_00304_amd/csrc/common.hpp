@@ -35,7 +35,7 @@ struct InstDesc {
     int r, R, Cx, Cz, CyB, ywrap, bot_wall, top_wall, ppc, feedback, grid_shift, pad0;
     long long ncells, Np;
     long long part_off;   // first particle of this instance in the init enumeration
-    long long init_per;   // particles per tile in the initial placement
+    long long init_per;   // largest initial tile occupancy (cells per tile x ppc)
     // particle tiles
     int Tx, Ty, Tz, ntx, nty, ntz, cap, nct;
     long long ntiles, tile_off, slot_off;
@@ -49,6 +49,7 @@ struct InstDesc {
     // MPCD constants
     double a, dt, gh[3], gdt[3], sd, cos_a, sin_a, mass, kT;
     uint32_t key0, key1;
+    int S, pad2;          // MPCD steps per LB step
 };
 
 // ---------------------------------------------------------------------------
@@ -175,5 +176,29 @@ struct PartPtrs {
     PT* vel[3];
     uint32_t* id;
 };
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// One coordinate of the shifted-grid cell, floor((x - lo + shift) * r),
+// evaluated in the particle store precision.
+template <typename PT>
+__device__ __forceinline__ int bin_coord(PT x, PT lo, PT sh, PT r) {
+    PT t = x - lo;
+    t = t + sh;
+    t = t * r;
+    return (int)floor(t);
+}
+
+// Random grid shift of MPCD step (t, sub): uniform in [0, a) per axis.
+template <int DIM, typename PT>
+__device__ __forceinline__ void grid_shift_of(const InstDesc& d, uint32_t t, uint32_t sub, PT sh[3]) {
+    double u[4];
+    rng_uniforms4(d, 0u, t, sub, P_SHIFT, u);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double v = (d.grid_shift && k < DIM) ? u[k] * d.a : 0.0;
+        sh[k] = (PT)v;
+    }
+}
 
 }  // namespace lbmpcd

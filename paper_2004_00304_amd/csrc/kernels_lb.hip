@@ -64,10 +64,23 @@ __device__ __forceinline__ void feq_of(double rho, double u0, double u1, double 
 template <int DIM, typename LT>
 __global__ void __launch_bounds__(WG) k_lb_step(const InstDesc* __restrict__ D, int n_inst, long long total,
                                                 const LT* __restrict__ fin, LT* __restrict__ fout,
-                                                long long* __restrict__ clock) {
+                                                long long* __restrict__ clock, double* __restrict__ shifts, int S) {
     using L = Lat<DIM>;
     constexpr int Q = L::Q;
-    if (blockIdx.x == 0 && threadIdx.x == 0) clock[0] = clock[0] + 1;
+    if (blockIdx.x == 0) {
+        // advance the LB step counter and draw the grid shifts of the new step
+        // for every instance and MPCD step (slot = step parity)
+        const long long t_new = clock[0] + 1;
+        __syncthreads();
+        if (threadIdx.x == 0) clock[0] = t_new;
+        for (int i = threadIdx.x; i < n_inst * S; i += WG) {
+            const int inst = i / S, s = i % S;
+            double sh[3];
+            grid_shift_of<DIM, double>(D[inst], (uint32_t)t_new, (uint32_t)s, sh);
+            double* o = shifts + (((long long)inst * 2 + (t_new & 1)) * S + s) * 3;
+            o[0] = sh[0]; o[1] = sh[1]; o[2] = sh[2];
+        }
+    }
     long long gid = (long long)blockIdx.x * WG + threadIdx.x;
     if (gid >= total) return;
     int ii = find_inst(D, n_inst, gid, [](const InstDesc& d) { return d.node_off; });
@@ -321,17 +334,17 @@ __global__ void __launch_bounds__(WG) k_moments(const InstDesc* __restrict__ D, 
 static inline unsigned blocks_for(long long n) { return (unsigned)((n + WG - 1) / WG); }
 
 hipError_t launch_lb_step(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, const void* fin,
-                          void* fout, long long* clock, hipStream_t s) {
+                          void* fout, long long* clock, double* shifts, int S, hipStream_t s) {
     if (total <= 0) return hipSuccess;
     dim3 g(blocks_for(total)), b(WG);
     if (dim == 2 && lb_fp == 64)
-        hipLaunchKernelGGL((k_lb_step<2, double>), g, b, 0, s, D, n_inst, total, (const double*)fin, (double*)fout, clock);
+        hipLaunchKernelGGL((k_lb_step<2, double>), g, b, 0, s, D, n_inst, total, (const double*)fin, (double*)fout, clock, shifts, S);
     else if (dim == 2)
-        hipLaunchKernelGGL((k_lb_step<2, float>), g, b, 0, s, D, n_inst, total, (const float*)fin, (float*)fout, clock);
+        hipLaunchKernelGGL((k_lb_step<2, float>), g, b, 0, s, D, n_inst, total, (const float*)fin, (float*)fout, clock, shifts, S);
     else if (lb_fp == 64)
-        hipLaunchKernelGGL((k_lb_step<3, double>), g, b, 0, s, D, n_inst, total, (const double*)fin, (double*)fout, clock);
+        hipLaunchKernelGGL((k_lb_step<3, double>), g, b, 0, s, D, n_inst, total, (const double*)fin, (double*)fout, clock, shifts, S);
     else
-        hipLaunchKernelGGL((k_lb_step<3, float>), g, b, 0, s, D, n_inst, total, (const float*)fin, (float*)fout, clock);
+        hipLaunchKernelGGL((k_lb_step<3, float>), g, b, 0, s, D, n_inst, total, (const float*)fin, (float*)fout, clock, shifts, S);
     return hipGetLastError();
 }
 

@@ -7,8 +7,10 @@
 
 namespace lbmpcd {
 
+// The LB step also advances the device clock and draws the grid shifts of the
+// new LB step into shifts[n_inst][2][S][3] (slot = step parity) when S > 0.
 hipError_t launch_lb_step(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, const void* fin,
-                          void* fout, long long* clock, hipStream_t s);
+                          void* fout, long long* clock, double* shifts, int S, hipStream_t s);
 hipError_t launch_band(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f, double* acc,
                        double* ub, int do_feedback, hipStream_t s);
 hipError_t launch_interp(int dim, const InstDesc* D, int n_inst, long long total, const double* ub, double* uf,
@@ -25,6 +27,14 @@ struct PartBuf {
     uint32_t* id;
 };
 
+template <typename PT>
+inline PartPtrs<PT> typed(const PartBuf& b) {
+    PartPtrs<PT> p;
+    for (int q = 0; q < 3; ++q) { p.pos[q] = (PT*)b.pos[q]; p.vel[q] = (PT*)b.vel[q]; }
+    p.id = b.id;
+    return p;
+}
+
 struct ParticleLaunch {
     int dim, part_fp, ppt, mode;  // mode bit 0: collide, bit 1: stream
     const InstDesc* D;
@@ -39,15 +49,17 @@ struct ParticleLaunch {
     double* prof;
     DevStats* stats;
     const long long* clock;
+    const double* shifts;         // [n_inst][2][S][3] grid shifts of the current and previous LB step
     int coll_dt, coll_s, str_s;   // collision step = clock + coll_dt, substeps
     int do_fb, do_prof;
     int diag_inst;                // instance whose cell centre-of-mass velocities are written
     double* cell_vcm;             // [dim][ncells] or null
+    int staged;                   // 1: output staged in LDS, 0: direct stores
     size_t lds_bytes;
 };
 
 hipError_t launch_particles(const ParticleLaunch& L, hipStream_t s);
-size_t particle_lds_bytes(int dim, int part_fp, int cap);
+size_t particle_lds_bytes(int dim, int part_fp, int cap, int staged);
 
 hipError_t launch_part_init(int dim, int part_fp, const InstDesc* D, int n_inst, long long total_particles,
                             PartBuf buf, hipStream_t s);

@@ -17,9 +17,11 @@ LIB_PATH = os.path.join(_HERE, "liblbmpcd.so")
 
 ABI_VERSION = 1
 
-RHO, U, PI, POP, PART_POS, PART_VEL, CELL_ID, CELL_COUNT, CELL_VCM, PROFILE, UFINE, STATS = range(12)
+RHO, U, PI, POP, PART_POS, PART_VEL, CELL_ID, CELL_COUNT, CELL_VCM, PROFILE, UFINE, STATS, \
+    PART_VEL_PENDING = range(13)
 FIELD_NAMES = dict(rho=RHO, u=U, pi=PI, pop=POP, pos=PART_POS, vel=PART_VEL, cell_id=CELL_ID,
-                   cell_count=CELL_COUNT, cell_vcm=CELL_VCM, profile=PROFILE, ufine=UFINE, stats=STATS)
+                   cell_count=CELL_COUNT, cell_vcm=CELL_VCM, profile=PROFILE, ufine=UFINE, stats=STATS,
+                   vel_pending=PART_VEL_PENDING)
 ERRORS = {1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_OVERFLOW", 5: "E_STATE", 6: "E_UNSUPPORTED"}
 
 
@@ -65,6 +67,8 @@ def _load():
     L.lbmpcd_timing.restype = C.c_int
     L.lbmpcd_timing_read.argtypes = [P, P, C.c_int32]
     L.lbmpcd_timing_read.restype = C.c_int
+    L.lbmpcd_graphs.argtypes = [P, C.c_int32]
+    L.lbmpcd_graphs.restype = C.c_int
     L.lbmpcd_strerror.argtypes = [C.c_int]
     L.lbmpcd_strerror.restype = C.c_char_p
     L.lbmpcd_last_error.argtypes = [P]
@@ -80,7 +84,7 @@ _lib = _load()
 EXPORTED = ("lbmpcd_workspace_size", "lbmpcd_init", "lbmpcd_step", "lbmpcd_moments",
             "lbmpcd_field_bytes", "lbmpcd_sample", "lbmpcd_get_state", "lbmpcd_set_state",
             "lbmpcd_sync", "lbmpcd_destroy", "lbmpcd_strerror", "lbmpcd_last_error", "lbmpcd_timing",
-            "lbmpcd_timing_read")
+            "lbmpcd_timing_read", "lbmpcd_graphs")
 
 
 def lib():
@@ -166,6 +170,10 @@ class Sim:
 
     def sample(self, mode: int):
         _check(_lib.lbmpcd_sample(self._h, int(mode)), self._h)
+
+    def graphs(self, enable: bool):
+        """Replay steady-state steps from a captured HIP graph (default on)."""
+        _check(_lib.lbmpcd_graphs(self._h, int(bool(enable))), self._h)
 
     # -- fields (device tensors)
     def field_bytes(self, field: int, inst: int = 0) -> int:

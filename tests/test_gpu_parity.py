@@ -132,9 +132,10 @@ def test_batched_instances_match_standalone(env):
     ps = [W.small_2d(n=(24 + 8 * i, 20 + 2 * i, 1), ylo=6, yhi=14, ppc=5 + i, instance=i) for i in range(3)]
     sim = lbmpcd.Sim(ps)
     sim.step(4)
+    bins = [sim.binning(i) for i in range(len(ps))]
     for i, p in enumerate(ps):
         orc = O.Oracle(p)
         orc.step(4)
-        rep = compare_state(sim, orc, p, RTOL64, inst=i)
+        rep = compare_state(sim, orc, p, RTOL64, inst=i, binning=bins[i])
         banner(f"batch inst {i}: {rep}")
         assert_parity(rep, RTOL64)

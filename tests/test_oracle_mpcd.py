@@ -346,9 +346,10 @@ def test_profile_counts(oracle_lib):
     o.sample(1)
     o.step(3)
     acc, nsteps = o.profile()
-    # every particle is sampled once per MPCD step while sampling is on
+    # every particle is sampled once per LB step (after the streaming of its
+    # last MPCD step) while sampling is on
     assert nsteps == 3
-    assert acc[:, 0].sum() == o.Np * p["substeps"] * 3
+    assert acc[:, 0].sum() == o.Np * 3
     o.sample(0)
     o.step(1)
     acc2, nsteps2 = o.profile()
