@@ -152,14 +152,19 @@ class Sim:
         self._h = h
         self.workspace_bytes = nbytes
 
-    def __del__(self):
+    def close(self):
+        """Wait for queued work and release the context (the workspace is torch's)."""
         h = getattr(self, "_h", None)
         if h:
+            self._h = None
             try:
                 _lib.lbmpcd_sync(h)
             finally:
                 _lib.lbmpcd_destroy(h)
-            self._h = None
+
+    def __del__(self):
+        if _lib is not None:  # module globals may already be gone at interpreter exit
+            self.close()
 
     # -- stepping
     def step(self, n: int = 1):
