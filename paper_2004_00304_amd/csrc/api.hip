@@ -45,9 +45,10 @@ struct lbmpcd_ctx {
     size_t prof_bytes = 0, acc_bytes = 0;
     long long total_nodes = 0, total_band = 0, total_ufine = 0, total_tiles = 0, total_slots = 0,
               total_particles = 0, total_slab = 0;
-    int ppt = 4;
     size_t lds = 0;
-    int staged = 1;               // stage the output tile in LDS before writing it out
+    int cap_max = 0;              // largest tile capacity
+    int wg_threads = 0;           // particle kernel workgroup size (0: 256)
+    long long cstride = 0;        // bytes between the component arrays of a particle buffer
     long long t = 0;
     bool pending = false, sampling = false, any_feedback = false;
     long long sampled_steps = 0;
@@ -94,6 +95,12 @@ struct Geometry {
     long long nband = 0, nufine = 0, nslab = 0;
 };
 
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << (l + 1)) <= v) ++l;
+    return l;
+}
+
 int choose_tile(const lbmpcd_params& p, Geometry& g, std::string& msg) {
     int T[3] = {p.tile[0], p.tile[1], p.tile[2]};
     if (T[0] <= 0 || T[1] <= 0 || (p.dim == 3 && T[2] <= 0)) {
@@ -109,6 +116,8 @@ int choose_tile(const lbmpcd_params& p, Geometry& g, std::string& msg) {
         T[0] = opts[pick][0]; T[1] = opts[pick][1]; T[2] = opts[pick][2];
     }
     if (p.dim == 2) T[2] = 1;
+    for (int k = 0; k < 3; ++k)
+        if (T[k] & (T[k] - 1)) { msg = "tile sides must be powers of two"; return 1; }
     g.Tx = T[0]; g.Ty = T[1]; g.Tz = T[2];
     g.nct = g.Tx * g.Ty * g.Tz;
     if (g.nct > MAX_NCT) { msg = "tile has more than 128 cells"; return 1; }
@@ -185,7 +194,8 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
 
 struct Layout {
     size_t desc, tile_inst, f0, f1, ub, uf, acc, prof, fill0, fill1, stats, clock, shifts, scratch, end;
-    size_t part[2][7];
+    size_t part[2];       // particle buffer: 2 dim component arrays of cstride bytes, then ids
+    size_t cstride;
     size_t acc_bytes, prof_bytes, scratch_bytes;
 };
 
@@ -212,6 +222,8 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
         d.grid_shift = q.grid_shift;
         d.ncells = g.ncells; d.Np = g.Np; d.part_off = parts; d.init_per = g.init_per;
         d.Tx = g.Tx; d.Ty = g.Ty; d.Tz = g.Tz; d.ntx = g.ntx; d.nty = g.nty; d.ntz = g.ntz;
+        d.lTx = ilog2(g.Tx); d.lTy = ilog2(g.Ty); d.lTz = ilog2(g.Tz);
+        d.lr = (p[i].refine & (p[i].refine - 1)) == 0 ? ilog2(p[i].refine) : -1;
         d.cap = g.cap; d.nct = g.nct; d.ntiles = g.ntiles; d.tile_off = tiles; d.slot_off = slots;
         d.by0 = g.by0; d.nyb = g.nyb; d.band_off = band; d.NB = g.NB; d.ufine_off = ufine;
         d.nslab = g.nslab; d.acc_off = slab; d.prof_off = prow;
@@ -257,10 +269,8 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
     L.prof = take(L.prof_bytes);
     L.fill0 = take(4 * (size_t)tiles);
     L.fill1 = take(4 * (size_t)tiles);
-    for (int b = 0; b < 2; ++b) {
-        for (int k = 0; k < 6; ++k) L.part[b][k] = (k % 3 < dim) ? take((size_t)slots * pw) : 0;
-        L.part[b][6] = take((size_t)slots * 4);
-    }
+    L.cstride = align_up((size_t)slots * pw, 256);
+    for (int b = 0; b < 2; ++b) L.part[b] = take(2 * (size_t)dim * L.cstride + (size_t)slots * 4);
     L.stats = take(sizeof(DevStats));
     L.clock = take(sizeof(long long));
     L.shifts = take(sizeof(double) * 6 * (size_t)n * (p[0].mpcd ? p[0].substeps : 1));
@@ -328,14 +338,14 @@ hipError_t timed(lbmpcd_ctx* c, int cls, F f) {
 int finalize(lbmpcd_ctx* c) {
     if (!c->pending || !c->mpcd) return 0;
     ParticleLaunch L{};
-    L.dim = c->dim; L.part_fp = c->part_fp; L.ppt = c->ppt; L.mode = 1;
+    L.dim = c->dim; L.part_fp = c->part_fp; L.mode = 1;
     L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
     L.in = c->part[c->pcur]; L.out = c->part[c->pcur];
     L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
     L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
     L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts;
     L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
-    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.staged = c->staged;
+    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride;
     HIPCHK(c, launch_particles(L, c->stream));
     c->pending = false;
     return 0;
@@ -427,12 +437,14 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     c->prof_bytes = L.prof_bytes;
     c->fill[0] = (uint32_t*)(c->ws + L.fill0);
     c->fill[1] = (uint32_t*)(c->ws + L.fill1);
+    c->cstride = (long long)L.cstride;
     for (int b = 0; b < 2; ++b) {
+        unsigned char* pb = (unsigned char*)(c->ws + L.part[b]);
         for (int k = 0; k < 3; ++k) {
-            c->part[b].pos[k] = L.part[b][k] ? c->ws + L.part[b][k] : nullptr;
-            c->part[b].vel[k] = L.part[b][3 + k] ? c->ws + L.part[b][3 + k] : nullptr;
+            c->part[b].pos[k] = k < c->dim ? pb + (size_t)k * L.cstride : nullptr;
+            c->part[b].vel[k] = k < c->dim ? pb + (size_t)(c->dim + k) * L.cstride : nullptr;
         }
-        c->part[b].id = (uint32_t*)(c->ws + L.part[b][6]);
+        c->part[b].id = (uint32_t*)(pb + (size_t)2 * c->dim * L.cstride);
     }
     c->stats = (DevStats*)(c->ws + L.stats);
     c->clock = (long long*)(c->ws + L.clock);
@@ -444,9 +456,10 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
         cap_max = std::max(cap_max, d.cap);
         if (d.feedback) c->any_feedback = true;
     }
-    c->ppt = cap_max <= 2 * WG ? 2 : (cap_max <= 4 * WG ? 4 : 8);
-    if (const char* e = std::getenv("LBMPCD_STAGED_WRITES")) c->staged = std::atoi(e) != 0;
-    c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max, c->staged);
+    c->cap_max = cap_max;
+    // tuning override of the particle kernel's workgroup size
+    if (const char* e = std::getenv("LBMPCD_PARTICLE_WG")) c->wg_threads = std::atoi(e);
+    c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max);
 
     // tile -> instance table
     std::vector<int> tinst((size_t)std::max<long long>(c->total_tiles, 1));
@@ -502,7 +515,7 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
                    }));
             for (int sub = 0; sub < c->S; ++sub) {
                 ParticleLaunch L{};
-                L.dim = c->dim; L.part_fp = c->part_fp; L.ppt = c->ppt;
+                L.dim = c->dim; L.part_fp = c->part_fp;
                 L.mode = (sub == 0 && !c->pending) ? 2 : 3;
                 L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
                 L.in = c->part[c->pcur]; L.out = c->part[c->pcur ^ 1];
@@ -515,7 +528,7 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
                 // samples are taken in the last MPCD step of the LB step
                 L.do_fb = (c->any_feedback && sub == c->S - 1) ? 1 : 0;
                 L.do_prof = (c->sampling && sub == c->S - 1) ? 1 : 0;
-                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.staged = c->staged;
+                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride;
                 HIPCHK(c, timed(c, 3, [&] { return launch_particles(L, s); }));
                 c->pcur ^= 1;
                 c->pending = true;
@@ -659,7 +672,7 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             if (!c->pending) return fail(c, LBMPCD_E_STATE, "cell velocities exist only right after lbmpcd_step");
             HIPCHK(c, launch_zero(dst, nbytes, s));
             ParticleLaunch L{};
-            L.dim = c->dim; L.part_fp = c->part_fp; L.ppt = c->ppt; L.mode = 1;
+            L.dim = c->dim; L.part_fp = c->part_fp; L.mode = 1;
             L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
             // the pending collision is evaluated into the idle particle buffer, so
             // the state (and the other instances' pending collisions) is untouched
@@ -668,7 +681,7 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
             L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts; L.shifts = c->shifts;
             L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
-            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds; L.staged = c->staged;
+            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride;
             HIPCHK(c, launch_particles(L, s));
             return 0;
         }

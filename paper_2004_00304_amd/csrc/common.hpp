@@ -38,6 +38,7 @@ struct InstDesc {
     long long init_per;   // largest initial tile occupancy (cells per tile x ppc)
     // particle tiles
     int Tx, Ty, Tz, ntx, nty, ntz, cap, nct;
+    int lTx, lTy, lTz, lr; // log2 of the tile sides (powers of two) and of r (-1 if r is not one)
     long long ntiles, tile_off, slot_off;
     // band (rows of node velocities used by the interpolation)
     int by0, nyb;
@@ -63,8 +64,11 @@ __device__ __forceinline__ U4 philox(U4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32x32 -> 64 bit product per multiplier (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         U4 n;
         n.x = hi1 ^ c.y ^ k0;
         n.y = lo1;
@@ -80,18 +84,23 @@ __host__ __device__ __forceinline__ double u01(uint32_t lo, uint32_t hi) {
     return (double)(v >> 11) * 0x1.0p-53;
 }
 
-__device__ __forceinline__ U4 rng_block(const InstDesc& d, uint32_t elem, uint32_t t, uint32_t sub,
+// Philox key of one instance: (seed low word, seed high word ^ instance).
+struct Key { uint32_t k0, k1; };
+template <typename Desc>
+__device__ __forceinline__ Key key_of(const Desc& d) { return Key{d.key0, d.key1}; }
+
+__device__ __forceinline__ U4 rng_block(Key k, uint32_t elem, uint32_t t, uint32_t sub,
                                         uint32_t purpose, uint32_t blk) {
-    return philox(U4{elem, t, (sub << 8) | purpose, blk}, d.key0, d.key1);
+    return philox(U4{elem, t, (sub << 8) | purpose, blk}, k.k0, k.k1);
 }
 
 // Four uniforms of one stream element (two Philox blocks, 53 bits each).
-__device__ __forceinline__ void rng_uniforms4(const InstDesc& d, uint32_t elem, uint32_t t,
+__device__ __forceinline__ void rng_uniforms4(Key k, uint32_t elem, uint32_t t,
                                               uint32_t sub, uint32_t purpose, double u[4]) {
-    U4 w = rng_block(d, elem, t, sub, purpose, 0);
+    U4 w = rng_block(k, elem, t, sub, purpose, 0);
     u[0] = u01(w.x, w.y);
     u[1] = u01(w.z, w.w);
-    w = rng_block(d, elem, t, sub, purpose, 1);
+    w = rng_block(k, elem, t, sub, purpose, 1);
     u[2] = u01(w.x, w.y);
     u[3] = u01(w.z, w.w);
 }
@@ -108,15 +117,15 @@ __device__ __forceinline__ void box_muller(double u0, double u1, double& z0, dou
 
 // DIM standard normals of one element; the third comes from a second pair.
 template <int DIM>
-__device__ __forceinline__ void rng_normals(const InstDesc& d, uint32_t elem, uint32_t t, uint32_t sub,
+__device__ __forceinline__ void rng_normals(Key k, uint32_t elem, uint32_t t, uint32_t sub,
                                             uint32_t purpose, double z[3]) {
     if constexpr (DIM == 2) {
-        U4 w = rng_block(d, elem, t, sub, purpose, 0);
+        U4 w = rng_block(k, elem, t, sub, purpose, 0);
         box_muller(u01(w.x, w.y), u01(w.z, w.w), z[0], z[1]);
         z[2] = 0.0;
     } else {
         double u[4], dummy;
-        rng_uniforms4(d, elem, t, sub, purpose, u);
+        rng_uniforms4(k, elem, t, sub, purpose, u);
         box_muller(u[0], u[1], z[0], z[1]);
         box_muller(u[2], u[3], z[2], dummy);
     }
@@ -193,7 +202,7 @@ __device__ __forceinline__ int bin_coord(PT x, PT lo, PT sh, PT r) {
 template <int DIM, typename PT>
 __device__ __forceinline__ void grid_shift_of(const InstDesc& d, uint32_t t, uint32_t sub, PT sh[3]) {
     double u[4];
-    rng_uniforms4(d, 0u, t, sub, P_SHIFT, u);
+    rng_uniforms4(key_of(d), 0u, t, sub, P_SHIFT, u);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         double v = (d.grid_shift && k < DIM) ? u[k] * d.a : 0.0;

@@ -6,33 +6,41 @@
 // particle sits in the slots of the tile that contains its cell, in no
 // particular order inside the tile.
 //
-// k_particles: one workgroup (4 waves) per tile, one launch per MPCD step.
+// k_particles: one workgroup per tile, one launch per MPCD step.
 //   phase 1 (collision of the previous binning, Eq. 4): cell occupancy and
-//     momentum summed in LDS (FP64 atomics), one thread per cell draws the
-//     rotation (2D sign / 3D axis) and, in wall-cut cells, the virtual
-//     particles' momentum; every particle is rotated about its cell's centre
-//     of mass in registers;
+//     momentum summed in LDS (FP64 atomics); the rotation of every cell
+//     (2D sign / 3D axis) is drawn while the tile's particles are loading;
+//     in wall-cut cells the virtual particles' momentum is added; every
+//     particle is rotated about its cell's centre of mass in registers;
 //   phase 2 (next MPCD step): Maxwell-Boltzmann redraw of buffer particles
 //     (exchange step of Alg. 1), streaming with the body force (Eq. 3) and
 //     boundary conditions, samples of the last MPCD step of an LB step,
 //     binning into the new shifted grid;
 //   phase 3 (counting sort into tiles): each wave groups its particles by
-//     destination tile with ballots, one lane per group adds the group to a
-//     small LDS table of destination tiles; one global atomic per destination
-//     reserves a run of slots while the particles are staged in LDS in
-//     destination order; the staged particles are written out in contiguous
-//     runs.
+//     destination tile with ballots; the first lane of a group claims a row
+//     of a small LDS table of destination tiles; one global atomic per
+//     destination reserves a run of slots, and every store writes the lanes
+//     of a group to consecutive slots.
 // Every particle is read once and written once per MPCD step.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace lbmpcd {
 
+// Particle buffers are passed as one base pointer each: component k of
+// x, y, (z), vx, vy, (vz) at base + k * cs bytes, the ids after the last one.
+template <typename PT>
+struct PBuf {
+    unsigned char* b;
+    __device__ __forceinline__ PT* comp(int k, long long cs) const { return (PT*)(b + k * cs); }
+    __device__ __forceinline__ uint32_t* id(int dim, long long cs) const { return (uint32_t*)(b + 2 * dim * cs); }
+};
+
 template <typename PT>
 struct PArgs {
     const InstDesc* D;
-    int n_inst;
-    PartPtrs<PT> in, out;
+    PBuf<PT> in, out;
+    long long cs;
     uint32_t* fill_in;
     uint32_t* fill_out;
     const int* tile_inst;
@@ -42,8 +50,8 @@ struct PArgs {
     DevStats* stats;
     const long long* clock;
     const double* shifts;
-    int coll_dt, coll_s, str_s, do_fb, do_prof, diag_inst, staged;
     double* cell_vcm;
+    int coll_dt, coll_s, str_s, do_fb, do_prof, diag_inst;
 };
 
 template <typename PT>
@@ -71,10 +79,18 @@ __device__ __forceinline__ double prev_below<double>(double v, double toward) { 
 // is unrolled over the particles a thread holds and one shared copy of the
 // FP64 transcendental code keeps the kernel small.
 template <int DIM>
-__device__ __noinline__ void reinject_normals(const InstDesc& d, uint32_t id, uint32_t t, uint32_t sub,
-                                              double* z) {
-    rng_normals<DIM>(d, id, t, sub, P_REINJ, z);
+__device__ __noinline__ void reinject_normals(Key key, uint32_t id, uint32_t t, uint32_t sub, double* z) {
+    rng_normals<DIM>(key, id, t, sub, P_REINJ, z);
 }
+
+// Read-only tables (descriptors, tile owners, grid shifts, fill counts of
+// tiles not yet processed) are read through the constant address space:
+// scalar loads, which the compiler may not use for ordinary global pointers
+// once the loop over tiles has stored anything.
+template <typename T>
+using cst = __attribute__((address_space(4))) const T;
+template <typename T>
+__device__ __forceinline__ cst<T>* cptr(const T* p) { return (cst<T>*)p; }
 
 __device__ __forceinline__ void lds_add(double* p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -82,30 +98,25 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
 __device__ __forceinline__ void gl_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
 // LDS carve-up (bytes): header (counters and the table of destination tiles),
-// sample windows, then a union of the collision arrays and the output
-// staging area.
+// sample windows, collision arrays.
 constexpr int NHASH_BITS = 6;
 constexpr int NHASH = 1 << NHASH_BITS;
-constexpr size_t LDS_HDR = 1088;  // >= 4 * (4 + 4 * NHASH + 3), a multiple of 16
+constexpr size_t LDS_HDR = 1088;  // >= 4 * (4 + 3 * NHASH + 2), a multiple of 16
 constexpr size_t LDS_WIN = (size_t)(MAX_WIN + MAX_WJ) * 4 * sizeof(double);
 constexpr size_t LDS_COLL = (size_t)MAX_NCT * 4 + (size_t)MAX_NCT * 9 * sizeof(double);
-constexpr uint32_t STAGE_LOCAL = 0x80000000u;  // staged entry holds (code, rank), not a slot
-constexpr uint32_t STAGE_DROP = 0x7FFFFFFFu;   // staged entry lost to an overflow
-static_assert(4 * (4 + 4 * NHASH + 3) <= (int)LDS_HDR, "LDS header too small");
+constexpr uint32_t DROP_SLOT = 0x7FFFFFFFu;  // never a slot: the slot total stays below it
+static_assert(4 * (4 + 3 * NHASH + 2) <= (int)LDS_HDR, "LDS header too small");
 
-size_t particle_lds_bytes(int dim, int part_fp, int cap, int staged) {
-    size_t stage = staged ? (size_t)cap * (8 + (size_t)2 * dim * (part_fp == 64 ? 8 : 4)) : 0;
-    return LDS_HDR + LDS_WIN + (stage > LDS_COLL ? stage : LDS_COLL);
-}
+size_t particle_lds_bytes(int, int, int) { return LDS_HDR + LDS_WIN + LDS_COLL; }
 
-// Minimum resident waves per SIMD the register allocation must allow: the
-// kernel is latency bound, so occupancy buys more than registers.
+// Minimum resident waves per SIMD the register allocation must allow.
 #ifndef LBMPCD_PARTICLE_WAVES
 #define LBMPCD_PARTICLE_WAVES 4
 #endif
 
-template <int DIM, typename PT, int PPT, int MODE>
-__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(LBMPCD_PARTICLE_WAVES)))
+// One workgroup per tile.
+template <int DIM, typename PT, int NT, int PPT, int MODE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(LBMPCD_PARTICLE_WAVES)))
 k_particles(PArgs<PT> A) {
     constexpr bool COLL = (MODE & 1) != 0;
     constexpr bool STREAM = (MODE & 2) != 0;
@@ -114,7 +125,6 @@ k_particles(PArgs<PT> A) {
     uint32_t* hkey = wstat + 4;                 // [NHASH] destination tiles (local index)
     uint32_t* hcnt = hkey + NHASH;              // [NHASH + 1] particles per destination
     uint32_t* gbase = hcnt + NHASH + 1;         // [NHASH + 1] reserved run start
-    uint32_t* s_off = gbase + NHASH + 1;        // [NHASH + 1] staging offsets
     double* wacc = (double*)(smem + LDS_HDR);   // [MAX_WIN][4] node sample window
     double* wprof = wacc + MAX_WIN * 4;         // [MAX_WJ][4] profile window
     unsigned char* uni = smem + LDS_HDR + LDS_WIN;
@@ -126,56 +136,78 @@ k_particles(PArgs<PT> A) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const long long T = blockIdx.x;
-    const int ii = A.tile_inst[T];
-    const InstDesc& d = A.D[ii];
+    const long long cs = A.cs;
+    const int ii = cptr(A.tile_inst)[T];
+    cst<InstDesc>& d = cptr(A.D)[ii];
+    const Key key = key_of(d);
     const long long lt = T - d.tile_off;
     const int tx = (int)(lt % d.ntx);
     const int ty = (int)((lt / d.ntx) % d.nty);
     const int tz = (int)(lt / ((long long)d.ntx * d.nty));
     const int cap = d.cap;
     const long long base = d.slot_off + lt * cap;
-    uint32_t n = A.fill_in[T];
+    uint32_t n = cptr(A.fill_in)[T];
     if (n > (uint32_t)cap) n = (uint32_t)cap;
-    if (tid == 0 && n > (uint32_t)(3 * cap / 4)) atomicMax(&A.stats->max_fill, n);
-    if (tid < 4) wstat[tid] = 0u;
-
-    const long long t_now = *A.clock;
+    const long long t_now = *cptr(A.clock);
     const PT rr = (PT)d.r;
-    const double* shtab = A.shifts + (long long)ii * 2 * d.S * 3;
+    cst<double>* shtab = cptr(A.shifts) + (long long)ii * 2 * d.S * 3;
+    const long long tcl = t_now + A.coll_dt;
+    const uint32_t tc = (uint32_t)tcl;
+    const uint32_t sc = (uint32_t)A.coll_s;
 
-    // ---- load
+    // ---- load (the rotations below are drawn while the loads are in flight)
     uint32_t pid[PPT];
     PT px[PPT][3], pv[PPT][3];
     bool valid[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int s = tid + k * WG;
+        const int s = tid + k * NT;
         valid[k] = s < (int)n;
-        px[k][2] = (PT)0;
-        pv[k][2] = (PT)0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { px[k][c] = (PT)0; pv[k][c] = (PT)0; }
         pid[k] = 0;
         if (valid[k]) {
-            pid[k] = A.in.id[base + s];
+            pid[k] = A.in.id(DIM, cs)[base + s];
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
-                px[k][c] = A.in.pos[c][base + s];
-                pv[k][c] = A.in.vel[c][base + s];
+                px[k][c] = A.in.comp(c, cs)[base + s];
+                pv[k][c] = A.in.comp(DIM + c, cs)[base + s];
             }
         }
+    }
+    if (tid == 0 && n > (uint32_t)(3 * cap / 4)) atomicMax(&A.stats->max_fill, n);
+    if (tid < 4) wstat[tid] = 0u;
+
+    // rotation of every cell of the tile (2D sign / 3D axis): independent of
+    // the particles
+    if constexpr (COLL) {
+        for (int j = tid; j < d.nct; j += NT) {
+            const int lx = j & (d.Tx - 1), ly = (j >> d.lTx) & (d.Ty - 1), lz = j >> (d.lTx + d.lTy);
+            const int ix = (tx << d.lTx) + lx, iy = (ty << d.lTy) + ly, iz = (tz << d.lTz) + lz;
+            const uint32_t cg = (uint32_t)(ix + d.Cx * (iy + d.CyB * iz));
+            const U4 w = rng_block(key, cg, tc, sc, P_ROT, 0);
+            if constexpr (DIM == 2) {
+                crot[3 * j] = (w.x & 1u) ? 1.0 : -1.0;
+            } else {
+                const double u0 = u01(w.x, w.y), u1 = u01(w.z, w.w);
+                const double nz = 2.0 * u0 - 1.0, phi = 6.283185307179586 * u1;
+                const double sxy = sqrt(fmax(0.0, 1.0 - nz * nz));
+                double sp, cp;
+                sincos(phi, &sp, &cp);
+                crot[3 * j] = sxy * cp;
+                crot[3 * j + 1] = sxy * sp;
+                crot[3 * j + 2] = nz;
+            }
+            ccnt[j] = 0u;
+            csv[3 * j] = 0.0; csv[3 * j + 1] = 0.0; csv[3 * j + 2] = 0.0;
+        }
+        __syncthreads();
     }
 
     // ---- phase 1: SRD collision of the binning these particles sit in
     if constexpr (COLL) {
-        const long long tcl = t_now + A.coll_dt;
-        const uint32_t tc = (uint32_t)tcl;
-        const uint32_t sc = (uint32_t)A.coll_s;
-        const double* shc = shtab + ((tcl & 1) * d.S + sc) * 3;
+        cst<double>* shc = shtab + ((tcl & 1) * d.S + sc) * 3;
         const PT sh[3] = {(PT)shc[0], (PT)shc[1], (PT)shc[2]};
-        for (int i = tid; i < MAX_NCT; i += WG) {
-            ccnt[i] = 0u;
-            csv[3 * i] = 0.0; csv[3 * i + 1] = 0.0; csv[3 * i + 2] = 0.0;
-        }
-        __syncthreads();
         int lc[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -190,21 +222,22 @@ k_particles(PArgs<PT> A) {
                 iz = bin_coord<PT>(px[k][2], (PT)0, sh[2], rr);
                 if (iz >= d.Cz) iz -= d.Cz;
             }
-            const int lx = ix - tx * d.Tx, ly = iy - ty * d.Ty, lz = iz - tz * d.Tz;
-            if (lx < 0 || lx >= d.Tx || ly < 0 || ly >= d.Ty || lz < 0 || lz >= d.Tz) {
+            const int lx = ix - (tx << d.lTx), ly = iy - (ty << d.lTy), lz = iz - (tz << d.lTz);
+            if ((unsigned)lx >= (unsigned)d.Tx || (unsigned)ly >= (unsigned)d.Ty ||
+                (unsigned)lz >= (unsigned)d.Tz) {
                 atomicAdd(&wstat[1], 1u);
                 continue;
             }
-            const int c = lx + d.Tx * (ly + d.Ty * lz);
+            const int c = lx + ((ly + (lz << d.lTy)) << d.lTx);
             lc[k] = c;
             atomicAdd(&ccnt[c], 1u);
 #pragma unroll
             for (int q = 0; q < DIM; ++q) lds_add(&csv[3 * c + q], (double)pv[k][q]);
         }
         __syncthreads();
-        for (int j = tid; j < d.nct; j += WG) {
-            const int lx = j % d.Tx, ly = (j / d.Tx) % d.Ty, lz = j / (d.Tx * d.Ty);
-            const int ix = tx * d.Tx + lx, iy = ty * d.Ty + ly, iz = tz * d.Tz + lz;
+        for (int j = tid; j < d.nct; j += NT) {
+            const int lx = j & (d.Tx - 1), ly = (j >> d.lTx) & (d.Ty - 1), lz = j >> (d.lTx + d.lTy);
+            const int ix = (tx << d.lTx) + lx, iy = (ty << d.lTy) + ly, iz = (tz << d.lTz) + lz;
             const uint32_t nc = ccnt[j];
             if (nc == 0u || ix >= d.Cx || iy >= d.CyB || iz >= d.Cz) continue;
             const uint32_t cg = (uint32_t)(ix + d.Cx * (iy + d.CyB * iz));
@@ -212,7 +245,7 @@ k_particles(PArgs<PT> A) {
             const bool cut = ((double)sh[1] > 0.0) && ((d.bot_wall && iy == 0) || (d.top_wall && iy == d.R));
             if (cut && (int)nc < d.ppc) {
                 double z[3];
-                rng_normals<DIM>(d, cg, tc, sc, P_WALL, z);
+                rng_normals<DIM>(key, cg, tc, sc, P_WALL, z);
                 const int nv = d.ppc - (int)nc;
                 const double sdv = sqrt((double)nv * d.kT / d.mass);
 #pragma unroll
@@ -223,19 +256,6 @@ k_particles(PArgs<PT> A) {
             for (int q = 0; q < 3; ++q) cvcm[3 * j + q] = 0.0;
 #pragma unroll
             for (int q = 0; q < DIM; ++q) cvcm[3 * j + q] = (csv[3 * j + q] + pvv[q]) / ((double)nc + mv);
-            const U4 w = rng_block(d, cg, tc, sc, P_ROT, 0);
-            if constexpr (DIM == 2) {
-                crot[3 * j] = (w.x & 1u) ? 1.0 : -1.0;
-            } else {
-                const double u0 = u01(w.x, w.y), u1 = u01(w.z, w.w);
-                const double nz = 2.0 * u0 - 1.0, phi = 6.283185307179586 * u1;
-                const double sxy = sqrt(fmax(0.0, 1.0 - nz * nz));
-                double sp, cp;
-                sincos(phi, &sp, &cp);
-                crot[3 * j] = sxy * cp;
-                crot[3 * j + 1] = sxy * sp;
-                crot[3 * j + 2] = nz;
-            }
             if (A.cell_vcm && ii == A.diag_inst) {
 #pragma unroll
                 for (int q = 0; q < DIM; ++q) A.cell_vcm[(long long)q * d.ncells + cg] = cvcm[3 * j + q];
@@ -274,37 +294,36 @@ k_particles(PArgs<PT> A) {
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (!valid[k]) continue;
-                const int s = tid + k * WG;
+                const int s = tid + k * NT;
 #pragma unroll
-                for (int q = 0; q < DIM; ++q) A.out.vel[q][base + s] = pv[k][q];
+                for (int q = 0; q < DIM; ++q) A.out.comp(DIM + q, cs)[base + s] = pv[k][q];
             }
             if (tid == 0 && wstat[1]) atomicAdd(&A.stats->misplaced, (unsigned long long)wstat[1]);
             return;
         }
-        __syncthreads();  // the collision arrays are reused below
     }
 
     if constexpr (STREAM) {
         const uint32_t ts = (uint32_t)t_now;
         const uint32_t ss = (uint32_t)A.str_s;
-        const double* shs = shtab + ((t_now & 1) * d.S + ss) * 3;
+        cst<double>* shs = shtab + ((t_now & 1) * d.S + ss) * 3;
         const PT sh[3] = {(PT)shs[0], (PT)shs[1], (PT)shs[2]};
         // sample windows (node sums for the feedback, fine rows for profiles)
         const int nslab_y = d.yhi - d.ylo;
         const int wnx = (d.Tx + d.r - 1) / d.r + 2, wny = (d.Ty + d.r - 1) / d.r + 2;
         const int wnz = (DIM == 3) ? (d.Tz + d.r - 1) / d.r + 2 : 1;
-        const int wx0 = (tx * d.Tx) / d.r - 1, wy0 = (ty * d.Ty) / d.r - 1;
-        const int wz0 = (DIM == 3) ? (tz * d.Tz) / d.r - 1 : 0;
+        const int wx0 = (tx << d.lTx) / d.r - 1, wy0 = (ty << d.lTy) / d.r - 1;
+        const int wz0 = (DIM == 3) ? (tz << d.lTz) / d.r - 1 : 0;
         const bool win_ok = wnx * wny * wnz <= MAX_WIN;
-        const int wj0 = ty * d.Ty - 2, wnj = d.Ty + 4;
+        const int wj0 = (ty << d.lTy) - 2, wnj = d.Ty + 4;
         const bool wj_ok = wnj <= MAX_WJ;
         const int copy = (int)(lt % NCOPY);
         if (A.do_fb)
-            for (int i = tid; i < MAX_WIN * 4; i += WG) wacc[i] = 0.0;
+            for (int i = tid; i < MAX_WIN * 4; i += NT) wacc[i] = 0.0;
         if (A.do_prof)
-            for (int i = tid; i < MAX_WJ * 4; i += WG) wprof[i] = 0.0;
-        for (int i = tid; i < NHASH; i += WG) hkey[i] = BAD_SLOT;
-        for (int i = tid; i <= NHASH; i += WG) hcnt[i] = 0u;
+            for (int i = tid; i < MAX_WJ * 4; i += NT) wprof[i] = 0.0;
+        for (int i = tid; i < NHASH; i += NT) hkey[i] = BAD_SLOT;
+        for (int i = tid; i <= NHASH; i += NT) hcnt[i] = 0u;
         __syncthreads();
 
         const double ylo_d = (double)d.ylo, yhi_d = (double)d.yhi;
@@ -325,7 +344,7 @@ k_particles(PArgs<PT> A) {
                 const int Jb = (J0 < rb_lo) ? J0 : J0 - (d.R - d.NB);
                 const long long fc = ((long long)K * d.NB + Jb) * d.Cx + I;
                 double z[3];
-                reinject_normals<DIM>(d, pid[k], ts, ss, z);
+                reinject_normals<DIM>(key, pid[k], ts, ss, z);
 #pragma unroll
                 for (int q = 0; q < DIM; ++q) pv[k][q] = (PT)(uf[q * NF + fc] + d.sd * z[q]);
             }
@@ -380,7 +399,7 @@ k_particles(PArgs<PT> A) {
                 double vals[4] = {1.0, (double)pv[k][0], (double)pv[k][1], DIM == 3 ? (double)pv[k][2] : 0.0};
                 if (A.do_fb) {
                     const int ixn = clampi((int)floor((double)px[k][0]), 0, d.nx - 1);
-                    const int iyn = J / d.r;
+                    const int iyn = d.lr >= 0 ? (J >> d.lr) : J / d.r;
                     const int izn = (DIM == 3) ? clampi((int)floor((double)px[k][2]), 0, d.nz - 1) : 0;
                     int ax = ixn - wx0; if (ax < 0) ax += d.nx; else if (ax >= d.nx) ax -= d.nx;
                     const int ay = iyn - wy0;
@@ -420,7 +439,7 @@ k_particles(PArgs<PT> A) {
                 iz = bin_coord<PT>(px[k][2], (PT)0, sh[2], rr);
                 if (iz >= d.Cz) iz -= d.Cz;
             }
-            const int ntx = ix / d.Tx, nty = iy / d.Ty, ntz = iz / d.Tz;
+            const int ntx = ix >> d.lTx, nty = iy >> d.lTy, ntz = iz >> d.lTz;
             dest[k] = (uint32_t)(ntx + d.ntx * (nty + d.nty * ntz));
             int dx = ntx - tx, dy = nty - ty, dz = ntz - tz;
             if (d.ntx > 2) { if (dx == d.ntx - 1) dx = -1; else if (dx == 1 - d.ntx) dx = 1; }
@@ -428,10 +447,12 @@ k_particles(PArgs<PT> A) {
             if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) atomicAdd(&wstat[0], 1u);
         }
 
-        // ---- phase 3a: group each wave's particles by destination tile
+        // ---- phase 3a: group each wave's particles by destination tile.
+        // Lanes with equal destinations get consecutive ranks; the group's
+        // first lane claims a row of the LDS destination table and the
+        // group's offset in it, and hands both back with one permute.
         const unsigned long long below_me = (1ull << lane) - 1ull;
-        int code[PPT];
-        uint32_t lrank[PPT], odst[PPT];
+        uint32_t pk[PPT];  // bit 31: direct slot; else (table row + 1) << 24 | rank
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const uint32_t key = dest[k];
@@ -441,7 +462,7 @@ k_particles(PArgs<PT> A) {
             bool is_lead = false;
             while (todo) {
                 const int leader = __ffsll((unsigned long long)todo) - 1;
-                const uint32_t kv = __shfl(key, leader);
+                const uint32_t kv = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
                 const unsigned long long m = __ballot(key == kv);
                 if (key == kv) {
                     my_leader = leader;
@@ -453,9 +474,9 @@ k_particles(PArgs<PT> A) {
                 }
                 todo &= ~m;
             }
-            int h = -1;
-            uint32_t b = 0u, ob = 0u;
+            uint32_t packed = 0u;
             if (is_lead) {
+                int h = -1;
                 uint32_t hh = (key * 2654435761u) >> (32 - NHASH_BITS);
 #pragma unroll 1
                 for (int probe = 0; probe < NHASH; ++probe) {
@@ -464,125 +485,61 @@ k_particles(PArgs<PT> A) {
                     hh = (hh + 1) & (NHASH - 1);
                 }
                 if (h >= 0) {
-                    b = atomicAdd(&hcnt[h], lead_cnt);
+                    packed = ((uint32_t)(h + 1) << 24) | atomicAdd(&hcnt[h], lead_cnt);
                 } else {
-                    // more destinations than table slots: reserve directly
-                    b = atomicAdd(&hcnt[NHASH], lead_cnt);
-                    ob = atomicAdd(&A.fill_out[d.tile_off + key], lead_cnt);
+                    // more destinations than table rows: reserve directly
+                    const uint32_t ob = atomicAdd(&A.fill_out[d.tile_off + key], lead_cnt);
+                    packed = ob < 0xFFFFFFu ? ob : 0xFFFFFFu;
                 }
             }
-            const int hb = __shfl(h, my_leader);
-            const uint32_t bb = __shfl(b, my_leader);
-            const uint32_t obb = __shfl(ob, my_leader);
-            code[k] = -1;
+            packed = (uint32_t)__shfl((int)packed, my_leader);
+            pk[k] = BAD_SLOT;
             if (key != BAD_SLOT) {
-                lrank[k] = bb + my_rank;
-                if (hb >= 0) {
-                    code[k] = hb;
+                const uint32_t row = packed >> 24;
+                const uint32_t r_ = (packed & 0xFFFFFFu) + my_rank;
+                if (row) {
+                    pk[k] = (row << 24) | r_;
                 } else {
-                    code[k] = NHASH;
-                    const uint32_t g = obb + my_rank;
-                    odst[k] = g < (uint32_t)cap ? (uint32_t)(d.slot_off + (long long)key * cap + g) : STAGE_DROP;
+                    pk[k] = r_ < (uint32_t)cap ? (0x80000000u | (uint32_t)(key * cap + r_)) : DROP_SLOT;
                 }
             }
         }
         __syncthreads();
-        if (!A.staged) {
-            // ---- phase 3b': reserve runs, then every thread stores its
-            // particles; the lanes of a wave that share a destination hold
-            // consecutive ranks, so each store writes contiguous runs
-            if (tid < NHASH) {
-                const uint32_t c = hcnt[tid];
-                gbase[tid] = c > 0u ? atomicAdd(&A.fill_out[d.tile_off + hkey[tid]], c) : 0u;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (code[k] < 0) continue;
-                const int c = code[k];
-                uint32_t g;
-                if (c < NHASH) {
-                    const uint32_t r_ = gbase[c] + lrank[k];
-                    g = r_ < (uint32_t)cap ? (uint32_t)(d.slot_off + (long long)hkey[c] * cap + r_) : STAGE_DROP;
-                } else {
-                    g = odst[k];
-                }
-                if (g == STAGE_DROP) {
-                    atomicAdd(&A.stats->dropped, 1ull);
-                    continue;
-                }
-                A.out.id[g] = pid[k];
-#pragma unroll
-                for (int q = 0; q < DIM; ++q) {
-                    A.out.pos[q][g] = px[k][q];
-                    A.out.vel[q][g] = pv[k][q];
-                }
-            }
-        } else {
-        // ---- phase 3b: staging offsets (wave-parallel exclusive scan)
-        if (tid < 64) {
-            const uint32_t v = hcnt[tid];
-            uint32_t incl = v;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(incl, off);
-                if (lane >= off) incl += y;
-            }
-            s_off[tid] = incl - v;
-            if (tid == 63) s_off[NHASH] = incl;
-        }
-        __syncthreads();
-        // ---- phase 3c: reserve runs (wave 0) while every wave stages
-        uint32_t resv = 0u;
+        // ---- phase 3b: one global atomic per destination reserves a run of
+        // slots; each store writes the lanes of a group to consecutive slots
         if (tid < NHASH) {
             const uint32_t c = hcnt[tid];
-            if (c > 0u) resv = atomicAdd(&A.fill_out[d.tile_off + hkey[tid]], c);
+            gbase[tid] = c > 0u ? atomicAdd(&A.fill_out[d.tile_off + hkey[tid]], c) : 0u;
         }
-        uint32_t* sdst = (uint32_t*)uni;
-        uint32_t* sid = sdst + cap;
-        PT* spos = (PT*)(sid + cap);
-        PT* svel = spos + (size_t)DIM * cap;
+        __syncthreads();
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            if (code[k] < 0) continue;
-            const int c = code[k];
-            const uint32_t at = s_off[c] + lrank[k];
-            sdst[at] = (c < NHASH) ? (STAGE_LOCAL | ((uint32_t)c << 16) | lrank[k]) : odst[k];
-            sid[at] = pid[k];
-#pragma unroll
-            for (int q = 0; q < DIM; ++q) {
-                spos[(size_t)q * cap + at] = px[k][q];
-                svel[(size_t)q * cap + at] = pv[k][q];
-            }
-        }
-        if (tid < NHASH) gbase[tid] = resv;
-        __syncthreads();
-        // ---- phase 3d: contiguous write-out
-        for (int i = tid; i < (int)n; i += WG) {
-            const uint32_t e = sdst[i];
-            uint32_t g;
-            if (e & STAGE_LOCAL) {
-                const int c = (int)((e >> 16) & 0x7FFFu);
-                const uint32_t r_ = gbase[c] + (e & 0xFFFFu);
-                g = r_ < (uint32_t)cap ? (uint32_t)(d.slot_off + (long long)hkey[c] * cap + r_) : STAGE_DROP;
+            const uint32_t e = pk[k];
+            if (e == BAD_SLOT) continue;
+            long long g;
+            if (e == DROP_SLOT) {
+                g = -1;
+            } else if (e & 0x80000000u) {
+                g = d.slot_off + (long long)(e & 0x7FFFFFFFu);
             } else {
-                g = e;
+                const int row = (int)(e >> 24) - 1;
+                const uint32_t r_ = gbase[row] + (e & 0xFFFFFFu);
+                g = r_ < (uint32_t)cap ? d.slot_off + (long long)hkey[row] * cap + r_ : -1;
             }
-            if (g == STAGE_DROP) {
+            if (g < 0) {
                 atomicAdd(&A.stats->dropped, 1ull);
                 continue;
             }
-            A.out.id[g] = sid[i];
+            A.out.id(DIM, cs)[g] = pid[k];
 #pragma unroll
             for (int q = 0; q < DIM; ++q) {
-                A.out.pos[q][g] = spos[(size_t)q * cap + i];
-                A.out.vel[q][g] = svel[(size_t)q * cap + i];
+                A.out.comp(q, cs)[g] = px[k][q];
+                A.out.comp(DIM + q, cs)[g] = pv[k][q];
             }
         }
-        }  // staged
-        // ---- sample windows to global memory (no barrier follows)
+        // ---- sample windows to global memory
         if (A.do_fb && win_ok) {
-            for (int i = tid; i < wnx * wny * wnz; i += WG) {
+            for (int i = tid; i < wnx * wny * wnz; i += NT) {
                 const double cnt = wacc[4 * i];
                 if (cnt == 0.0) continue;
                 const int ax = i % wnx, ay = (i / wnx) % wny, az = i / (wnx * wny);
@@ -598,7 +555,7 @@ k_particles(PArgs<PT> A) {
             }
         }
         if (A.do_prof && wj_ok) {
-            for (int i = tid; i < wnj; i += WG) {
+            for (int i = tid; i < wnj; i += NT) {
                 const double cnt = wprof[4 * i];
                 if (cnt == 0.0) continue;
                 const int J = wj0 + i;
@@ -618,36 +575,43 @@ k_particles(PArgs<PT> A) {
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
-template <int DIM, typename PT, int PPT, int MODE>
+template <int DIM, typename PT, int NT, int PPT, int MODE>
 static hipError_t launch_p4(const ParticleLaunch& L, hipStream_t s) {
     PArgs<PT> a;
-    a.D = L.D; a.n_inst = L.n_inst;
-    a.in = typed<PT>(L.in); a.out = typed<PT>(L.out);
+    a.D = L.D;
+    a.in.b = (unsigned char*)L.in.pos[0]; a.out.b = (unsigned char*)L.out.pos[0]; a.cs = L.cstride;
     a.fill_in = L.fill_in; a.fill_out = L.fill_out; a.tile_inst = L.tile_inst;
     a.ufine = L.ufine; a.acc = L.acc; a.prof = L.prof; a.stats = L.stats; a.clock = L.clock;
     a.shifts = L.shifts;
     a.coll_dt = L.coll_dt; a.coll_s = L.coll_s; a.str_s = L.str_s;
     a.do_fb = L.do_fb; a.do_prof = L.do_prof; a.diag_inst = L.diag_inst; a.cell_vcm = L.cell_vcm;
-    a.staged = L.staged;
-    hipLaunchKernelGGL((k_particles<DIM, PT, PPT, MODE>), dim3((unsigned)L.tiles), dim3(WG), L.lds_bytes, s, a);
+    auto kern = k_particles<DIM, PT, NT, PPT, MODE>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)L.tiles), dim3(NT), L.lds_bytes, s, a);
     return hipGetLastError();
 }
 
-template <int DIM, typename PT, int PPT>
+template <int DIM, typename PT, int NT, int PPT>
 static hipError_t launch_p3(const ParticleLaunch& L, hipStream_t s) {
     switch (L.mode) {
-        case 1: return launch_p4<DIM, PT, PPT, 1>(L, s);
-        case 2: return launch_p4<DIM, PT, PPT, 2>(L, s);
-        case 3: return launch_p4<DIM, PT, PPT, 3>(L, s);
+        case 1: return launch_p4<DIM, PT, NT, PPT, 1>(L, s);
+        case 2: return launch_p4<DIM, PT, NT, PPT, 2>(L, s);
+        case 3: return launch_p4<DIM, PT, NT, PPT, 3>(L, s);
         default: return hipErrorInvalidValue;
     }
 }
 
+// Workgroup shape: threads x particles per thread must cover the largest
+// tile capacity.  256 threads unless the caller asks for 512.
 template <int DIM, typename PT>
 static hipError_t launch_p2(const ParticleLaunch& L, hipStream_t s) {
-    if (L.ppt <= 2) return launch_p3<DIM, PT, 2>(L, s);
-    if (L.ppt <= 4) return launch_p3<DIM, PT, 4>(L, s);
-    if (L.ppt <= 8) return launch_p3<DIM, PT, 8>(L, s);
+    if (L.wg_threads == 512) {
+        if (L.cap_max <= 2 * 512) return launch_p3<DIM, PT, 512, 2>(L, s);
+        if (L.cap_max <= 4 * 512) return launch_p3<DIM, PT, 512, 4>(L, s);
+        return hipErrorInvalidValue;
+    }
+    if (L.cap_max <= 2 * 256) return launch_p3<DIM, PT, 256, 2>(L, s);
+    if (L.cap_max <= 4 * 256) return launch_p3<DIM, PT, 256, 4>(L, s);
+    if (L.cap_max <= 8 * 256) return launch_p3<DIM, PT, 256, 8>(L, s);
     return hipErrorInvalidValue;
 }
 

@@ -29,12 +29,12 @@ __global__ void __launch_bounds__(WG) k_part_init(const InstDesc* __restrict__ D
     const int J = (int)((cl / d.Cx) % d.R);
     const int K = (int)(cl / ((long long)d.Cx * d.R));
     double u[4], z[3];
-    rng_uniforms4(d, (uint32_t)id, 0u, 0u, P_INIT_POS, u);
+    rng_uniforms4(key_of(d), (uint32_t)id, 0u, 0u, P_INIT_POS, u);
     const double r = (double)d.r;
     const double x = ((double)I + u[0]) / r;
     const double y = (double)d.ylo + ((double)J + u[1]) / r;
     const double zz = (DIM == 3) ? ((double)K + u[2]) / r : 0.0;
-    rng_normals<DIM>(d, (uint32_t)id, 0u, 0u, P_INIT_VEL, z);
+    rng_normals<DIM>(key_of(d), (uint32_t)id, 0u, 0u, P_INIT_VEL, z);
     // the tile of the unshifted cell; slots ranked over the tile's slab cells
     const int tx = I / d.Tx, ty = J / d.Ty, tz = K / d.Tz;
     const int cx = min(d.Tx, d.Cx - tx * d.Tx), cy = min(d.Ty, d.R - ty * d.Ty), cz = min(d.Tz, d.Cz - tz * d.Tz);

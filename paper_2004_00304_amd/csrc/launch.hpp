@@ -36,7 +36,7 @@ inline PartPtrs<PT> typed(const PartBuf& b) {
 }
 
 struct ParticleLaunch {
-    int dim, part_fp, ppt, mode;  // mode bit 0: collide, bit 1: stream
+    int dim, part_fp, mode;       // mode bit 0: collide, bit 1: stream
     const InstDesc* D;
     int n_inst;
     long long tiles;              // workgroups (tiles of all instances)
@@ -54,12 +54,14 @@ struct ParticleLaunch {
     int do_fb, do_prof;
     int diag_inst;                // instance whose cell centre-of-mass velocities are written
     double* cell_vcm;             // [dim][ncells] or null
-    int staged;                   // 1: output staged in LDS, 0: direct stores
+    int cap_max;                  // largest tile capacity
+    int wg_threads;               // 256 or 512 threads per workgroup (0: 256)
+    long long cstride;            // bytes between component arrays (pos[k] = pos[0] + k cstride, vel[k] = pos[0] + (dim + k) cstride, id after vel)
     size_t lds_bytes;
 };
 
 hipError_t launch_particles(const ParticleLaunch& L, hipStream_t s);
-size_t particle_lds_bytes(int dim, int part_fp, int cap, int staged);
+size_t particle_lds_bytes(int dim, int part_fp, int cap);
 
 hipError_t launch_part_init(int dim, int part_fp, const InstDesc* D, int n_inst, long long total_particles,
                             PartBuf buf, hipStream_t s);
