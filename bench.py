@@ -54,7 +54,7 @@ def measured_traffic(per_launch_particles: int):
     return pmc.get("bytes_per_launch")
 
 
-def cpu_baseline(p: dict, seconds_cap: float = 25.0) -> dict:
+def cpu_baseline(p: dict, seconds_cap: float = 15.0) -> dict:
     """The oracle, as it stands, on a bounded sample of the same workload:
     x and z cut by 8 (same per-node and per-particle work), single thread."""
     from oracle import oracle as O
@@ -71,7 +71,7 @@ def cpu_baseline(p: dict, seconds_cap: float = 25.0) -> dict:
     while True:
         o.step(1)
         steps += 1
-        if time.perf_counter() - t0 > seconds_cap / 3 or steps >= 3:
+        if time.perf_counter() - t0 > seconds_cap or steps >= 200:
             break
     dt = time.perf_counter() - t0
     sample_sps = steps / dt
@@ -96,6 +96,55 @@ def calib_copy():
     print(json.dumps({"calib_copy_bytes": n}), flush=True)
 
 
+def pmc_summary(fetch_csv: str, write_csv: str, command: str) -> None:
+    """Writes the committed PMC summary of the particle kernel from two
+    rocprofv3 --pmc runs of `bench.py --calib-copy` (FETCH_SIZE, WRITE_SIZE;
+    KiB per dispatch).  Each counter is scaled by what it reads for the plain
+    1 GiB device copy in the same run."""
+    import csv
+    from paper_2004_00304_amd import workloads as W
+
+    def per_kernel(path, counter):
+        out = {}
+        for row in csv.DictReader(open(path)):
+            if row["Counter_Name"] != counter:
+                continue
+            out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+        return out
+
+    f = per_kernel(fetch_csv, "FETCH_SIZE")
+    w = per_kernel(write_csv, "WRITE_SIZE")
+    copy_f = [v for k, vs in f.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in vs]
+    copy_w = [v for k, vs in w.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in vs]
+    gib_kib = float(1 << 20)
+    fscale = gib_kib / max(copy_f)  # the copy reads 1 GiB
+    wscale = gib_kib / max(copy_w)  # and writes 1 GiB
+    fused = lambda d: [v for k, vs in d.items() if "k_particles" in k and k.rstrip(")").rstrip().endswith(
+        "3>(lbmpcd::PArgs<float>") or ("k_particles" in k and ", 3>" in k) for v in vs]
+    pf, pw = fused(f), fused(w)
+    fetch_b = sum(pf) / len(pf) * 1024 * fscale
+    write_b = sum(pw) / len(pw) * 1024 * wscale
+    p = W.channel_3d()
+    alg = W.algorithmic_bytes_per_lb_step(p)["per_particle_update"] * W.sizes(p)["particles"]
+    out = {
+        "kernel": "k_particles<3, float, 256, 4, 3> (fused MPCD step), channel_3d",
+        "kernel_hash": kernel_hash(),
+        "command": command,
+        "dispatches": len(pf),
+        "fetch_kib_per_dispatch": sum(pf) / len(pf),
+        "write_kib_per_dispatch": sum(pw) / len(pw),
+        "copy_fetch_kib": max(copy_f), "copy_write_kib": max(copy_w),
+        "fetch_scale": fscale, "write_scale": wscale,
+        "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+        "bytes_per_launch": fetch_b + write_b,
+        "algorithmic_bytes_per_launch": alg,
+        "traffic_over_algorithmic": (fetch_b + write_b) / alg,
+    }
+    with open(PMC_FILE, "w") as fo:
+        json.dump(out, fo, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,7 +153,12 @@ def main():
     ap.add_argument("--workload", default="channel_3d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="write the particle kernel's PMC summary from two rocprofv3 runs and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU "
               "sharding of the coupled step is a design note, not built)", file=sys.stderr)
