@@ -36,9 +36,27 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def workload(name: str) -> dict:
+def workload(name: str) -> list:
+    """Parameter dicts of the named workload (one per channel)."""
     from paper_2004_00304_amd import workloads as W
-    return {"channel_3d": W.channel_3d, "channel_2d": W.channel_2d, "thin_film_3d": W.thin_film_3d}[name]()
+    if name == "ensemble":
+        return W.ensemble(256)
+    return [{"channel_3d": W.channel_3d, "channel_2d": W.channel_2d, "thin_film_3d": W.thin_film_3d}[name]()]
+
+
+def totals(plist: list) -> dict:
+    """Summed sizes and algorithmic bytes of a list of channels."""
+    from paper_2004_00304_amd import workloads as W
+    out = dict(nodes=0, particles=0, lb_bytes=0, mpcd_bytes=0, launch_bytes=0)
+    for p in plist:
+        sz, ab = W.sizes(p), W.algorithmic_bytes_per_lb_step(p)
+        out["nodes"] += sz["nodes"]
+        out["particles"] += sz["particles"]
+        out["lb_bytes"] += ab["lb"]
+        out["mpcd_bytes"] += ab["mpcd"]
+        out["launch_bytes"] += ab["per_particle_update"] * sz["particles"]
+    out["total_bytes"] = out["lb_bytes"] + out["mpcd_bytes"]
+    return out
 
 
 def measured_traffic(per_launch_particles: int):
@@ -54,6 +72,32 @@ def measured_traffic(per_launch_particles: int):
     return pmc.get("bytes_per_launch")
 
 
+def cpu_baseline_ensemble(plist: list, seconds_cap: float = 15.0) -> dict:
+    """The oracle on the first channels of the ensemble, one LB step each in
+    turn, single thread, scaled to the whole ensemble by the particle ratio."""
+    from oracle import oracle as O
+    from paper_2004_00304_amd import workloads as W
+
+    if not os.path.exists(O.LIB_PATH):
+        O.build()
+    total = sum(W.sizes(p)["particles"] for p in plist)
+    done_particles, k, steps = 0, 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds_cap and k < len(plist):
+        o = O.Oracle(plist[k])
+        o.step(1)
+        done_particles += W.sizes(plist[k])["particles"]
+        k += 1
+        steps += 1
+    dt = time.perf_counter() - t0
+    rate = done_particles / dt  # particle-LB-steps per second
+    return dict(value=rate / total, unit="coupled LB steps/s", cores=1, kind="oracle",
+                sample=(f"channels 0..{k - 1} of {len(plist)} ({done_particles} particles), one LB step "
+                        f"each in {dt:.1f} s (including set-up), scaled by the particle ratio "
+                        f"{done_particles / total:.5f}"),
+                particle_updates_per_s=rate * plist[0]["substeps"])
+
+
 def cpu_baseline(p: dict, seconds_cap: float = 15.0) -> dict:
     """The oracle, as it stands, on a bounded sample of the same workload:
     x and z cut by 8 (same per-node and per-particle work), single thread."""
@@ -62,7 +106,10 @@ def cpu_baseline(p: dict, seconds_cap: float = 15.0) -> dict:
 
     if not os.path.exists(O.LIB_PATH):
         O.build()
-    q = W.make(**{**p, "n": (p["n"][0] // 8, p["n"][1], p["n"][2] // 8)})
+    if p["dim"] == 2:
+        q = W.make(**{**p, "n": (max(p["n"][0] // 8, 8), p["n"][1], 1)})
+    else:
+        q = W.make(**{**p, "n": (p["n"][0] // 8, p["n"][1], p["n"][2] // 8)})
     o = O.Oracle(q)
     full = W.sizes(p)
     samp = W.sizes(q)
@@ -82,6 +129,27 @@ def cpu_baseline(p: dict, seconds_cap: float = 15.0) -> dict:
                         f"ratio {scale:.5f}"),
                 particle_updates_per_s=samp["particles"] * p["substeps"] * sample_sps,
                 lb_mlups=samp["nodes"] * sample_sps / 1e6)
+
+
+def one_by_one(lbmpcd, plist: list, batched_ms: float, sample: int = 16, steps: int = 8) -> dict:
+    """The same channels advanced one context at a time (each alone on the
+    GPU), for every len(plist)/sample-th channel; the summed time per coupled
+    step is scaled to all channels and compared with the batched step."""
+    import torch
+    idx = list(range(0, len(plist), max(1, len(plist) // sample)))[:sample]
+    total_ms = 0.0
+    for i in idx:
+        sim = lbmpcd.Sim(plist[i], device="cuda:0")
+        sim.step(4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        total_ms += 1e3 * (time.perf_counter() - t0) / steps
+        sim.close()
+    est = total_ms * len(plist) / len(idx)
+    return dict(channels_measured=len(idx), one_by_one_ms_per_step=est, batched_ms_per_step=batched_ms,
+                speedup=est / batched_ms)
 
 
 def calib_copy():
@@ -150,7 +218,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="channel_3d")
+    ap.add_argument("--workload", default="channel_3d",
+                    choices=["channel_3d", "channel_2d", "thin_film_3d", "ensemble"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shape with lbmpcd_autotune first (always on for the ensemble)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -170,16 +241,20 @@ def main():
 
     if args.calib_copy:
         calib_copy()
-    p = workload(args.workload)
-    sz = W.sizes(p)
-    ab = W.algorithmic_bytes_per_lb_step(p)
+    plist = workload(args.workload)
+    p = plist[0]
+    tot = totals(plist)
     torch.cuda.set_device(0)
-    sim = lbmpcd.Sim(p, device="cuda:0")
-    print(f"[bench] {args.workload}: {sz['nodes']} nodes, {sz['particles']} particles, "
-          f"workspace {sim.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    tuning = None
+    if args.autotune or args.workload == "ensemble":
+        tuning = lbmpcd.autotune(plist, lb_steps=5)
+        plist = lbmpcd.with_tuning(plist, tuning)
+        print(f"[bench] autotune: {tuning}", file=sys.stderr, flush=True)
+    sim = lbmpcd.Sim(plist, device="cuda:0")
+    print(f"[bench] {args.workload}: {len(plist)} channel(s), {tot['nodes']} nodes, {tot['particles']} "
+          f"particles, workspace {sim.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     sim.step(args.warmup)
     sim.sync()
-    st0 = sim.stats()
     sim.timing(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -189,7 +264,7 @@ def main():
     sim.timing(0)
     kt = sim.timing_read()
     sim.sync()
-    st = sim.stats()
+    st = sim.stats()  # device counters shared by all channels of the context
     if st["dropped"] or st["misplaced"]:
         raise SystemExit(f"invalid run: {st}")
     dt = t1 - t0
@@ -197,9 +272,19 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     kp = kt["particles"]
     part_ms = kp["ms"] / max(kp["launches"], 1)
-    per_launch = ab["per_particle_update"] * sz["particles"]
+    per_launch = tot["launch_bytes"]
     achieved = per_launch / (part_ms * 1e-3) / 1e9
-    traffic = measured_traffic(sz["particles"])
+    traffic = measured_traffic(tot["particles"]) if args.workload == "channel_3d" else None
+    if args.workload == "ensemble":
+        wl = (f"ensemble: 256 2D channels (D2Q9, widths 16-128, lengths 32-256, strip W/4 with 1-row "
+              f"buffers, r 4, 5-20 ppc, FP64), {tot['nodes']} nodes, {tot['particles']} particles, "
+              f"S {p['substeps']}, SRD {p['alpha_deg']} deg")
+    else:
+        lat = "D2Q9" if p["dim"] == 2 else "D3Q19"
+        wl = (f"{args.workload}: {lat} {p['n'][0]}x{p['n'][1]}x{p['n'][2]} tau {p['tau']}, "
+              f"slab y[{p['ylo']},{p['yhi']}) buffers {p['buf_lo']}/{p['buf_hi']}, r {p['refine']}, "
+              f"{p['ppc']} ppc ({tot['particles']} particles), S {p['substeps']}, "
+              f"SRD {p['alpha_deg']} deg, feedback {p['feedback']}")
     out = {
         "metric": "coupled steps/s: LB MLUPS + MPCD particle-updates/s, % HBM roofline",
         "value": sps,
@@ -214,15 +299,13 @@ def main():
         "dtype": "f32 particles / f64 LB and cell sums" if p["part_fp"] == 32 else "f64",
         "data": "synthetic (seeded Poiseuille channel; uniform-in-cell positions, Maxwellian velocities)",
         "config": {
-            "workload": (f"{args.workload}: D3Q19 {p['n'][0]}x{p['n'][1]}x{p['n'][2]} tau {p['tau']}, "
-                         f"slab y[{p['ylo']},{p['yhi']}) buffers {p['buf_lo']}/{p['buf_hi']}, r {p['refine']}, "
-                         f"{p['ppc']} ppc ({sz['particles']} particles), S {p['substeps']}, "
-                         f"SRD {p['alpha_deg']} deg, feedback {p['feedback']}"),
-            "lb_nodes": sz["nodes"], "particles": sz["particles"], "substeps": p["substeps"],
+            "workload": wl, "channels": len(plist),
+            "lb_nodes": tot["nodes"], "particles": tot["particles"], "substeps": p["substeps"],
+            "launch_shape": tuning if tuning else "default (tile_target 640, 256 threads)",
         },
-        "lb_mlups": sz["nodes"] * sps / 1e6,
-        "mpcd_particle_updates_per_s": sz["particles"] * p["substeps"] * sps,
-        "coupled_hbm_frac": ab["total"] * sps / 1e9 / HBM_PEAK_GBS,
+        "lb_mlups": tot["nodes"] * sps / 1e6,
+        "mpcd_particle_updates_per_s": tot["particles"] * p["substeps"] * sps,
+        "coupled_hbm_frac": tot["total_bytes"] * sps / 1e9 / HBM_PEAK_GBS,
         "kernels_ms_per_launch": {k: v["ms"] / max(v["launches"], 1) for k, v in kt.items()},
         "roofline": {
             "bound": "hbm",
@@ -236,8 +319,12 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if len(plist) > 1:
+        del sim
+        torch.cuda.empty_cache()
+        out["batched_vs_one_by_one"] = one_by_one(lbmpcd, plist, ms_per_step)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
+        out["cpu_baseline"] = cpu_baseline_ensemble(plist) if len(plist) > 1 else cpu_baseline(p)
     print(json.dumps(out), flush=True)
 
 

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define LBMPCD_ABI_VERSION 1u
+#define LBMPCD_ABI_VERSION 2u
 
 enum lbmpcd_status {
     LBMPCD_OK = 0,
@@ -106,8 +106,11 @@ typedef struct lbmpcd_params {
     int32_t init_flow;     /* 0: rest, 1: discrete Poiseuille profile (needs walls) */
     uint64_t seed;         /* Philox key (low, high ^ instance) */
     uint32_t instance;     /* instance number inside the key */
-    int32_t tile[3];       /* particle tile in cells per axis; 0 = default */
+    int32_t tile[3];       /* particle tile in cells per axis (powers of two); 0 = from tile_target */
     double capacity_factor;/* tile capacity / expected occupancy; 0 = default 1.3 */
+    int32_t tile_target;   /* expected particles per tile when tile[] is 0; 0 = default 640 */
+    int32_t wg_threads;    /* particle kernel workgroup: 256 or 512 threads; 0 = 256.
+                              All instances of a context must agree. */
 } lbmpcd_params;
 
 /*
@@ -154,7 +157,8 @@ int lbmpcd_field_bytes(const struct lbmpcd_ctx* c, int32_t field, int32_t inst, 
 /*
  * Time averaging of the MPCD velocity profile (Sec. 3.1: averaging over
  * samples suppresses the particle noise).  mode 1: zero the accumulators and
- * start sampling every MPCD step; 0: stop.
+ * start sampling, once per LB step after the streaming of its last MPCD
+ * step; 0: stop.
  */
 int lbmpcd_sample(struct lbmpcd_ctx* c, int32_t mode);
 
@@ -192,6 +196,31 @@ int lbmpcd_graphs(struct lbmpcd_ctx* c, int32_t enable);
 
 /* Free the host context; never frees caller memory. */
 void lbmpcd_destroy(struct lbmpcd_ctx* c);
+
+/*
+ * Launch-shape autotuner (not part of the method: it picks how the particle
+ * step is cut into work, never what it computes).  Candidates are the tile
+ * sizes tile_target in {160, 320, 640, 1280} expected particles per tile
+ * (each instance's tile then follows from its own particles per cell) times
+ * the particle kernel's workgroup size wg_threads in {256, 512}.  Each
+ * candidate is initialised in dev_workspace (candidates that need more than
+ * `bytes`, or are invalid for the parameters, are skipped), run for
+ * 2 * lb_steps coupled steps and timed over the last lb_steps with HIP events
+ * on hip_stream; the workspace contents are overwritten.  p[i].tile must be
+ * zero.  *out receives the fastest candidate; the results of the method do
+ * not depend on the choice.  Synchronises the stream.
+ */
+typedef struct lbmpcd_tuning {
+    uint32_t struct_size;  /* sizeof(lbmpcd_tuning), set by the caller */
+    int32_t tile_target;   /* chosen expected particles per tile */
+    int32_t wg_threads;    /* chosen workgroup size */
+    int32_t tried;         /* candidates measured */
+    double ms_per_step;    /* ms per coupled LB step of the chosen candidate */
+    double ms_default;     /* ms per coupled LB step of (640, 256), -1 if not measured */
+} lbmpcd_tuning;
+
+int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, size_t bytes,
+                    void* hip_stream, int32_t lb_steps, lbmpcd_tuning* out);
 
 const char* lbmpcd_strerror(int code);
 const char* lbmpcd_last_error(const struct lbmpcd_ctx* c);

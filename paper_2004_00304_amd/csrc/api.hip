@@ -105,7 +105,8 @@ int choose_tile(const lbmpcd_params& p, Geometry& g, std::string& msg) {
     int T[3] = {p.tile[0], p.tile[1], p.tile[2]};
     if (T[0] <= 0 || T[1] <= 0 || (p.dim == 3 && T[2] <= 0)) {
         // aim at ~640 expected particles per tile
-        int target = std::max(8, std::min(MAX_NCT, 640 / std::max(1, p.ppc)));
+        const int per_tile = p.tile_target > 0 ? p.tile_target : 640;
+        int target = std::max(8, std::min(MAX_NCT, per_tile / std::max(1, p.ppc)));
         static const int opts3[][3] = {{2, 2, 2}, {4, 2, 2}, {4, 4, 2}, {4, 4, 4}, {4, 4, 8}};
         static const int opts2[][3] = {{4, 2, 1}, {4, 4, 1}, {8, 4, 1}, {8, 8, 1}, {16, 8, 1}};
         const int(*opts)[3] = p.dim == 3 ? opts3 : opts2;
@@ -172,6 +173,8 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     if ((long long)p.n[0] * p.n[1] * p.n[2] > (1LL << 40)) { msg = "domain too large"; return LBMPCD_E_INVALID; }
     if (!p.mpcd) return 0;
     if (p.collision != 0) { msg = "only the SRD collision (0) is implemented"; return LBMPCD_E_UNSUPPORTED; }
+    if (p.wg_threads != 0 && p.wg_threads != 256 && p.wg_threads != 512) { msg = "wg_threads must be 0, 256 or 512"; return LBMPCD_E_INVALID; }
+    if (p.tile_target < 0 || p.tile_target > 8 * WG) { msg = "tile_target out of range"; return LBMPCD_E_INVALID; }
     if (p.part_fp != 32 && p.part_fp != 64) { msg = "part_fp must be 32 or 64"; return LBMPCD_E_INVALID; }
     if (p.ylo < 0 || p.yhi > p.n[1] || p.ylo >= p.yhi) { msg = "slab outside the domain"; return LBMPCD_E_INVALID; }
     if (p.refine < 1 || p.substeps < 1 || p.ppc < 1) { msg = "refine, substeps, ppc must be >= 1"; return LBMPCD_E_INVALID; }
@@ -288,6 +291,10 @@ int validate_all(const lbmpcd_params* p, int n, std::string& msg) {
         if (p[i].dim != p[0].dim || p[i].lb_fp != p[0].lb_fp || p[i].mpcd != p[0].mpcd ||
             (p[0].mpcd && (p[i].part_fp != p[0].part_fp || p[i].substeps != p[0].substeps))) {
             msg = "all instances must share dim, lb_fp, mpcd, part_fp and substeps";
+            return LBMPCD_E_INVALID;
+        }
+        if (p[i].wg_threads != p[0].wg_threads) {
+            msg = "all instances must share wg_threads";
             return LBMPCD_E_INVALID;
         }
     }
@@ -457,8 +464,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
         if (d.feedback) c->any_feedback = true;
     }
     c->cap_max = cap_max;
-    // tuning override of the particle kernel's workgroup size
-    if (const char* e = std::getenv("LBMPCD_PARTICLE_WG")) c->wg_threads = std::atoi(e);
+    c->wg_threads = p[0].wg_threads;
     c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max);
 
     // tile -> instance table
@@ -817,6 +823,73 @@ int lbmpcd_timing_read(lbmpcd_ctx* c, double* out, int32_t n_classes) {
         out[2 * k] = k < 4 ? c->timing_ms[k] : 0.0;
         out[2 * k + 1] = k < 4 ? (double)c->timing_n[k] : 0.0;
     }
+    return 0;
+}
+
+int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, size_t bytes,
+                    void* hip_stream, int32_t lb_steps, lbmpcd_tuning* out) {
+    if (!out || out->struct_size != sizeof(lbmpcd_tuning))
+        return fail(nullptr, LBMPCD_E_INVALID, "out is null or its struct_size is wrong");
+    if (lb_steps < 1) return fail(nullptr, LBMPCD_E_INVALID, "lb_steps must be >= 1");
+    std::string msg;
+    if (int e = validate_all(p, n_inst, msg)) return fail(nullptr, e, msg);
+    for (int i = 0; i < n_inst; ++i)
+        if (p[i].tile[0] || p[i].tile[1] || p[i].tile[2])
+            return fail(nullptr, LBMPCD_E_INVALID, "autotune needs tile = 0 (the tile follows tile_target)");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        return fail(nullptr, LBMPCD_E_DEVICE, "event creation failed");
+    }
+    static const int targets[] = {160, 320, 640, 1280};
+    static const int wgs[] = {256, 512};
+    std::vector<lbmpcd_params> q(p, p + n_inst);
+    double best = -1.0;
+    int rc = 0;
+    out->tried = 0;
+    out->ms_default = -1.0;
+    for (int tt : targets) {
+        for (int wg : wgs) {
+            for (auto& x : q) { x.tile_target = tt; x.wg_threads = wg; }
+            size_t need = 0;
+            if (lbmpcd_workspace_size(q.data(), n_inst, &need) != LBMPCD_OK || need > bytes) continue;
+            lbmpcd_ctx* c = nullptr;
+            if (lbmpcd_init(q.data(), n_inst, dev_workspace, bytes, hip_stream, &c) != LBMPCD_OK) {
+                if (c) lbmpcd_destroy(c);
+                continue;  // e.g. a tile whose capacity exceeds the kernel's limit
+            }
+            float ms = 0.f;
+            int e = lbmpcd_step(c, lb_steps);
+            if (!e && hipEventRecord(ev[0], s) != hipSuccess) e = LBMPCD_E_DEVICE;
+            if (!e) e = lbmpcd_step(c, lb_steps);
+            if (!e && hipEventRecord(ev[1], s) != hipSuccess) e = LBMPCD_E_DEVICE;
+            if (!e) e = lbmpcd_sync(c);
+            if (!e && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) e = LBMPCD_E_DEVICE;
+            if (e) {
+                g_err = "autotune candidate (" + std::to_string(tt) + ", " + std::to_string(wg) + "): " +
+                        c->err;
+                lbmpcd_destroy(c);
+                rc = e;
+                break;
+            }
+            lbmpcd_destroy(c);
+            const double per = (double)ms / lb_steps;
+            ++out->tried;
+            if (tt == 640 && wg == 256) out->ms_default = per;
+            if (best < 0 || per < best) {
+                best = per;
+                out->tile_target = tt;
+                out->wg_threads = wg;
+                out->ms_per_step = per;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rc) return rc;
+    if (best < 0) return fail(nullptr, LBMPCD_E_NOMEM, "no candidate fits the workspace");
     return 0;
 }
 

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmpcd.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 RHO, U, PI, POP, PART_POS, PART_VEL, CELL_ID, CELL_COUNT, CELL_VCM, PROFILE, UFINE, STATS, \
     PART_VEL_PENDING = range(13)
@@ -43,7 +43,13 @@ class Params(C.Structure):
         ("collision", C.c_int32), ("grid_shift", C.c_int32), ("feedback", C.c_int32),
         ("init_flow", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint32),
         ("tile", C.c_int32 * 3), ("capacity_factor", C.c_double),
+        ("tile_target", C.c_int32), ("wg_threads", C.c_int32),
     ]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("tile_target", C.c_int32), ("wg_threads", C.c_int32),
+                ("tried", C.c_int32), ("ms_per_step", C.c_double), ("ms_default", C.c_double)]
 
 
 def _load():
@@ -71,6 +77,8 @@ def _load():
     L.lbmpcd_graphs.restype = C.c_int
     L.lbmpcd_strerror.argtypes = [C.c_int]
     L.lbmpcd_strerror.restype = C.c_char_p
+    L.lbmpcd_autotune.argtypes = [P, C.c_int32, P, C.c_size_t, P, C.c_int32, C.POINTER(Tuning)]
+    L.lbmpcd_autotune.restype = C.c_int
     L.lbmpcd_last_error.argtypes = [P]
     L.lbmpcd_last_error.restype = C.c_char_p
     for name in ("lbmpcd_workspace_size", "lbmpcd_init", "lbmpcd_step", "lbmpcd_moments",
@@ -84,7 +92,10 @@ _lib = _load()
 EXPORTED = ("lbmpcd_workspace_size", "lbmpcd_init", "lbmpcd_step", "lbmpcd_moments",
             "lbmpcd_field_bytes", "lbmpcd_sample", "lbmpcd_get_state", "lbmpcd_set_state",
             "lbmpcd_sync", "lbmpcd_destroy", "lbmpcd_strerror", "lbmpcd_last_error", "lbmpcd_timing",
-            "lbmpcd_timing_read", "lbmpcd_graphs")
+            "lbmpcd_timing_read", "lbmpcd_graphs", "lbmpcd_autotune")
+
+# candidate tile sizes of lbmpcd_autotune (expected particles per tile)
+TUNE_TILE_TARGETS = (160, 320, 640, 1280)
 
 
 def lib():
@@ -110,6 +121,8 @@ def params_struct(p: dict) -> Params:
                                                           p["feedback"], p["init_flow"])
     s.seed, s.instance = p["seed"], p["instance"]
     s.capacity_factor = p.get("capacity_factor", 0.0)
+    s.tile_target = p.get("tile_target", 0)
+    s.wg_threads = p.get("wg_threads", 0)
     return s
 
 
@@ -124,6 +137,44 @@ def workspace_size(params) -> int:
     n = C.c_size_t()
     _check(_lib.lbmpcd_workspace_size(C.cast(arr, C.c_void_p), len(plist), C.byref(n)))
     return int(n.value)
+
+
+def autotune(params, lb_steps: int = 5, device="cuda", stream=None) -> dict:
+    """Runs lbmpcd_autotune on a scratch workspace large enough for every
+    candidate and returns the chosen launch shape (tile_target, wg_threads)
+    with the timings."""
+    import torch
+
+    plist = list(params) if isinstance(params, (list, tuple)) else [params]
+    need = 0
+    for tt in TUNE_TILE_TARGETS:
+        try:
+            need = max(need, workspace_size([{**p, "tile_target": tt} for p in plist]))
+        except LbmpcdError:
+            pass
+    arr = (Params * len(plist))(*[params_struct(p) for p in plist])
+    dev = torch.device(device)
+    if dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    out = Tuning()
+    out.struct_size = C.sizeof(Tuning)
+    with torch.cuda.device(dev):
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        rc = _lib.lbmpcd_autotune(C.cast(arr, C.c_void_p), len(plist), C.c_void_p(ws.data_ptr()), need,
+                                  C.c_void_p(st.cuda_stream), int(lb_steps), C.byref(out))
+        _check(rc, None)
+        del ws
+    return dict(tile_target=out.tile_target, wg_threads=out.wg_threads, tried=out.tried,
+                ms_per_step=out.ms_per_step, ms_default=out.ms_default)
+
+
+def with_tuning(params, tuning: dict):
+    """The parameter dict(s) with the launch shape chosen by autotune."""
+    upd = {"tile_target": tuning["tile_target"], "wg_threads": tuning["wg_threads"]}
+    if isinstance(params, (list, tuple)):
+        return [{**p, **upd} for p in params]
+    return {**params, **upd}
 
 
 class Sim:

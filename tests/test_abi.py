@@ -91,3 +91,40 @@ def test_null_context_calls_fail_cleanly(binding):
     assert L.lbmpcd_step(None, 1) == 1
     assert L.lbmpcd_sync(None) == 1
     L.lbmpcd_destroy(None)
+
+
+@pytest.mark.parametrize("kw", [dict(wg_threads=128), dict(tile_target=-1), dict(tile_target=1 << 20),
+                                dict(tile=(3, 2, 1))])
+def test_invalid_launch_shape(binding, kw):
+    with pytest.raises(binding.LbmpcdError) as e:
+        binding.workspace_size(W.make(**kw))
+    assert e.value.code == 1
+
+
+def test_mixed_workgroup_sizes_rejected(binding):
+    with pytest.raises(binding.LbmpcdError):
+        binding.workspace_size([W.channel_2d(), W.make(wg_threads=512)])
+
+
+def test_tile_target_sets_the_tile(binding):
+    """A smaller tile target gives smaller tiles, hence more tile metadata
+    and a different workspace size; the same target reproduces the size."""
+    a = binding.workspace_size(W.make(tile_target=160))
+    b = binding.workspace_size(W.make(tile_target=1280))
+    assert a != b
+    assert a == binding.workspace_size(W.make(tile_target=160))
+
+
+def test_autotune_argument_checks(binding):
+    """Argument errors are reported before any device work."""
+    lib = binding.lib()
+    arr = (binding.Params * 1)(binding.params_struct(W.channel_2d()))
+    out = binding.Tuning()
+    out.struct_size = 3  # wrong
+    rc = lib.lbmpcd_autotune(ctypes.cast(arr, ctypes.c_void_p), 1, None, 0, None, 1, ctypes.byref(out))
+    assert rc == 1
+    out.struct_size = ctypes.sizeof(binding.Tuning)
+    arr[0].tile[0] = 4
+    rc = lib.lbmpcd_autotune(ctypes.cast(arr, ctypes.c_void_p), 1, None, 0, None, 1, ctypes.byref(out))
+    assert rc == 1
+    assert b"tile" in lib.lbmpcd_last_error(None)

@@ -33,6 +33,10 @@ CASES = {
     "periodic_2d": (W.periodic_2d(), 6, RTOL64),
     "no_shift": (W.small_2d(grid_shift=0), 4, RTOL64),
     "poiseuille_init": (W.small_2d(init_flow=1, g=(2e-5, 0, 0)), 4, RTOL64),
+    # launch shapes: the results do not depend on how the step is cut into work
+    "shape_small_tiles_wg512": (W.small_3d(tile_target=160, wg_threads=512), 4, RTOL64),
+    "shape_large_tiles": (W.small_2d(tile_target=1280), 4, RTOL64),
+    "shape_wg512_fp32": (W.small_3d(part_fp=32, wg_threads=512), 4, RTOL32),
 }
 
 
