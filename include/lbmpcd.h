@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define LBMPCD_ABI_VERSION 2u
+#define LBMPCD_ABI_VERSION 3u
 
 enum lbmpcd_status {
     LBMPCD_OK = 0,
@@ -111,6 +111,8 @@ typedef struct lbmpcd_params {
     int32_t tile_target;   /* expected particles per tile when tile[] is 0; 0 = default 640 */
     int32_t wg_threads;    /* particle kernel workgroup: 256 or 512 threads; 0 = 256.
                               All instances of a context must agree. */
+    int32_t closure;       /* 1: reserve the learned closure (lbmpcd_closure_*); needs
+                              dim 3, mpcd and a single channel */
 } lbmpcd_params;
 
 /*
@@ -221,6 +223,107 @@ typedef struct lbmpcd_tuning {
 
 int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, size_t bytes,
                     void* hip_stream, int32_t lb_steps, lbmpcd_tuning* out);
+
+/*
+ * Learned closure.  Not part of the method of the paper: a surrogate that,
+ * where thermal fluctuations are not needed, stands in for the MPCD slab.
+ * With one-way coupling (feedback 0, as in the paper's Alg. 1/2) it supplies
+ * the MPCD averages (the time-averaged profile) from the LB state without
+ * advancing particles; with feedback 1 its velocity also replaces the
+ * particle averages in the projection onto the LB equilibria, where any
+ * bias of the prediction acts like an extra body force (the periodic check
+ * below guards against that).  A network (MLP 271 -> 128 -> 128 -> 128 -> 9,
+ * GELU, BF16 weights and activations, FP32 accumulation on the matrix
+ * cores) maps the LB moments around a slab node -- rho, u and Pi (Sec. 2.1,
+ * the moments of the populations) of the 3x3x3 neighbourhood, x and z
+ * periodic, y clamped -- and the node's shear rate sqrt(2 S:S), S = -(Pi -
+ * rho u u) / (2 rho c_s^2 tau), to the node's MPCD mean velocity (3) and
+ * kinetic stress sum m (v - u)(v - u) per unit volume (xx yy zz xy xz yz).
+ * The network's velocity outputs are relative to the node's own LB velocity
+ * (features 131..133, the centre of the stencil); targets Y and the outputs
+ * of lbmpcd_closure_forward are absolute.
+ * Features are standardised and targets too (mean and standard deviation of
+ * the training set), the loss is the mean squared error in standardised
+ * units, training is Adam on FP32 parameters with a BF16 copy for the
+ * products.  Contexts must be created with closure = 1 (dim 3, one channel).  The parameter block (lbmpcd_closure_weights) is FP32:
+ * W1[128][288] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] W4[9][128]
+ * b4[9] (weights [out][in]; W1's inputs 271..287 are zero), then the
+ * statistics mean_x[271] std_x[271] mean_y[9] std_y[9]: 71737 floats.
+ * Device pointers X, Y hold rows of 271 raw features and 9 raw targets.
+ */
+typedef struct lbmpcd_train_opts {
+    uint32_t struct_size;  /* sizeof(lbmpcd_train_opts) */
+    int32_t epochs;        /* passes of ceil(n / batch) Adam steps */
+    int32_t batch;         /* rows per step, drawn uniformly with Philox; >= n: all rows in order */
+    float lr, beta1, beta2, eps;  /* Adam */
+    uint64_t seed;         /* initial weights (Glorot uniform) when none are set */
+} lbmpcd_train_opts;
+
+/* Scratch bytes of lbmpcd_closure_train / loss_grad / forward for n rows. */
+int lbmpcd_closure_scratch_size(int64_t n, int32_t batch, size_t* bytes);
+
+/*
+ * Training data from the plain coupled step: advances lb_steps LB steps and
+ * writes, per slab node (x fastest, then y - ylo, then z), the features
+ * averaged over the window (after every LB collide-stream) into X and the
+ * targets (post-collision particle moments after every LB step) into Y.
+ * Asynchronous; the closure must be disabled.
+ */
+int lbmpcd_closure_collect(struct lbmpcd_ctx* c, int32_t lb_steps, float* X, float* Y);
+
+/*
+ * Train on n rows: statistics and initial weights are set on the first call
+ * (or by lbmpcd_closure_weights), later calls continue.  loss_per_epoch
+ * (host, epochs entries, may be NULL) receives the mean batch loss of each
+ * epoch; the call then synchronises once per epoch.
+ */
+int lbmpcd_closure_train(struct lbmpcd_ctx* c, const float* X, const float* Y, int64_t n,
+                         const lbmpcd_train_opts* opts, void* scratch, size_t scratch_bytes,
+                         float* loss_per_epoch);
+
+/* Loss and parameter gradient (host, NPARAM = 71177 floats, may be NULL) on n rows; synchronises. */
+int lbmpcd_closure_loss_grad(struct lbmpcd_ctx* c, const float* X, const float* Y, int64_t n, void* scratch,
+                             size_t scratch_bytes, double* loss, float* grad);
+
+/* Raw features of every slab node of the current populations (device X, nslab x 271). */
+int lbmpcd_closure_features(struct lbmpcd_ctx* c, float* X);
+
+/* Network output in physical units for n rows of raw features (device Y, n x 9). */
+int lbmpcd_closure_forward(struct lbmpcd_ctx* c, const float* X, int64_t n, float* Y, void* scratch,
+                           size_t scratch_bytes);
+
+/* get_or_set 0: copy the parameter block out (host); 1: load it (resets Adam). Synchronises. */
+int lbmpcd_closure_weights(struct lbmpcd_ctx* c, int32_t get_or_set, float* buf, size_t bytes);
+
+/*
+ * on 1: lbmpcd_step runs LB collide-stream and the network on every slab
+ * node (profile samples; with feedback, the projection with the predicted
+ * velocity); no particle step.
+ * Every check_every LB steps (0: never) a check with check_steps plain
+ * steps (lbmpcd_closure_check) runs, synchronously, and falls back to the
+ * plain MPCD step for good when the error exceeds fallback_tol (0: 0.02).
+ */
+int lbmpcd_closure_enable(struct lbmpcd_ctx* c, int32_t on, double fallback_tol, int32_t check_every,
+                          int32_t check_steps);
+
+/*
+ * Plain coupled burst of burst_steps LB steps (the particles resume from
+ * their last state; the profile of the second half is kept) against the
+ * network's profile of the final LB state: relative L2 error of the
+ * streamwise velocity averaged over each LB node row between the buffers
+ * (the network predicts node averages).  Disables
+ * the closure when above the tolerance.  Resets the profile accumulators.
+ */
+int lbmpcd_closure_check(struct lbmpcd_ctx* c, int32_t burst_steps, double* rel_err);
+
+int lbmpcd_closure_status(const struct lbmpcd_ctx* c, int32_t* on, int32_t* fell_back, double* last_err);
+
+/*
+ * The matrix-core product of the closure on its own: C[M][N] = A[M][K] B[N][K]^T,
+ * BF16 row-major operands, FP32 result, on hip_stream.  Asynchronous.
+ */
+int lbmpcd_closure_gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t* A, const uint16_t* B, float* C,
+                             void* hip_stream);
 
 const char* lbmpcd_strerror(int code);
 const char* lbmpcd_last_error(const struct lbmpcd_ctx* c);

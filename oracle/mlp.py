@@ -87,12 +87,14 @@ def gelu_grad(x):
 # ---- standardisation -------------------------------------------------------------
 
 def stats_of(X, Y):
-    """mean and population standard deviation per column (1 where it vanishes)."""
+    """Mean and population standard deviation per column, the latter floored
+    at 1e-3 of the mean's magnitude and at 1e-12 (the targets Y here are the
+    network's, see network_targets)."""
     def ms(A):
         A = np.asarray(A, np.float64)
         m = A.mean(axis=0)
         s = np.sqrt(np.maximum((A * A).mean(axis=0) - m * m, 0.0))
-        s = np.where(s > 0.0, s, 1.0)
+        s = np.maximum(np.maximum(s, 1e-3 * np.abs(m)), 1e-12)
         return m, s
     mx, sx = ms(X)
     my, sy = ms(Y)
@@ -102,6 +104,24 @@ def stats_of(X, Y):
 def split_stats(st):
     st = np.asarray(st, np.float64)
     return st[:NF], st[NF:2 * NF], st[2 * NF:2 * NF + NOUT], st[2 * NF + NOUT:]
+
+
+UC = 13 * 10 + 1  # u_x of the stencil's centre node among the features
+
+
+def network_targets(X, Y):
+    """What the network fits: the velocity relative to the node's own LB
+    velocity (the centre stencil entry), the stress as is."""
+    T = np.asarray(Y, np.float64).copy()
+    T[:, :3] -= np.asarray(X, np.float64)[:, UC:UC + 3]
+    return T
+
+
+def physical_outputs(X, T):
+    """Inverse of network_targets."""
+    Y = np.asarray(T, np.float64).copy()
+    Y[:, :3] += np.asarray(X, np.float64)[:, UC:UC + 3]
+    return Y
 
 
 def standardise(X, st, rnd=bf16):

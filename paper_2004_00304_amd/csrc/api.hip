@@ -14,6 +14,7 @@
 
 #include "../../include/lbmpcd.h"
 #include "common.hpp"
+#include "mlp.hpp"
 #include "launch.hpp"
 
 using namespace lbmpcd;
@@ -59,13 +60,35 @@ struct lbmpcd_ctx {
     struct Mark { int cls; hipEvent_t a, b; };
     std::vector<Mark> marks;
     std::vector<hipEvent_t> pool;
-    double timing_ms[4] = {0, 0, 0, 0};
-    long long timing_n[4] = {0, 0, 0, 0};
+    double timing_ms[5] = {0, 0, 0, 0, 0};
+    long long timing_n[5] = {0, 0, 0, 0, 0};
     // steady-state steps replayed from a captured graph
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_key = -1;
+    // learned closure (channel 0)
+    bool closure = false;          // region reserved
+    float* cl_P = nullptr;         // [NPARAM] FP32 parameters
+    uint16_t* cl_Pb = nullptr;     // [NPARAM] BF16 copy
+    float* cl_G = nullptr;         // [NPARAM] gradient
+    float* cl_m = nullptr;         // [NPARAM] Adam first moment
+    float* cl_v = nullptr;         // [NPARAM] Adam second moment
+    float* cl_stats = nullptr;     // [NSTATS] standardisation
+    double* cl_sums = nullptr;     // [2 (NF + NOUT)] column sums
+    double* cl_loss = nullptr;     // [1]
+    double* cl_facc = nullptr;     // [nslab][NF] feature sums of a collection window
+    double* cl_nm = nullptr;       // [nslab][10] particle moment sums
+    float* cl_uc = nullptr;        // [nslab][3] LB velocity of each slab node (surrogate step)
+    ClosureBufs cl_inf;            // inference activations, one row per slab node
+    long long cl_nslab = 0;
+    bool cl_ready = false;         // parameters and statistics set
+    bool cl_collect = false;       // collection window: features after every LB collide-stream
+    bool cl_on = false;            // surrogate replaces the MPCD steps
+    bool cl_fell_back = false;     // a check found the surrogate off by more than cl_tol
+    double cl_tol = 0.02, cl_last_err = -1.0;
+    int cl_every = 0, cl_burst = 40;
+    long long cl_since = 0, cl_adam_t = 0;
 };
 
 namespace {
@@ -171,10 +194,12 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     if (!(p.rho0 > 0.0)) { msg = "rho0 must be positive"; return LBMPCD_E_INVALID; }
     if (p.init_flow && !p.walls_y) { msg = "init_flow needs walls"; return LBMPCD_E_INVALID; }
     if ((long long)p.n[0] * p.n[1] * p.n[2] > (1LL << 40)) { msg = "domain too large"; return LBMPCD_E_INVALID; }
+    if (p.closure && !p.mpcd) { msg = "the closure needs the MPCD slab"; return LBMPCD_E_INVALID; }
     if (!p.mpcd) return 0;
     if (p.collision != 0) { msg = "only the SRD collision (0) is implemented"; return LBMPCD_E_UNSUPPORTED; }
     if (p.wg_threads != 0 && p.wg_threads != 256 && p.wg_threads != 512) { msg = "wg_threads must be 0, 256 or 512"; return LBMPCD_E_INVALID; }
     if (p.tile_target < 0 || p.tile_target > 8 * WG) { msg = "tile_target out of range"; return LBMPCD_E_INVALID; }
+    if (p.closure && p.dim != 3) { msg = "the closure needs dim 3"; return LBMPCD_E_INVALID; }
     if (p.part_fp != 32 && p.part_fp != 64) { msg = "part_fp must be 32 or 64"; return LBMPCD_E_INVALID; }
     if (p.ylo < 0 || p.yhi > p.n[1] || p.ylo >= p.yhi) { msg = "slab outside the domain"; return LBMPCD_E_INVALID; }
     if (p.refine < 1 || p.substeps < 1 || p.ppc < 1) { msg = "refine, substeps, ppc must be >= 1"; return LBMPCD_E_INVALID; }
@@ -197,6 +222,7 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
 
 struct Layout {
     size_t desc, tile_inst, f0, f1, ub, uf, acc, prof, fill0, fill1, stats, clock, shifts, scratch, end;
+    size_t cl_P, cl_Pb, cl_G, cl_m, cl_v, cl_stats, cl_sums, cl_loss, cl_facc, cl_nm, cl_uc, cl_inf;
     size_t part[2];       // particle buffer: 2 dim component arrays of cstride bytes, then ids
     size_t cstride;
     size_t acc_bytes, prof_bytes, scratch_bytes;
@@ -279,6 +305,20 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
     L.shifts = take(sizeof(double) * 6 * (size_t)n * (p[0].mpcd ? p[0].substeps : 1));
     L.scratch_bytes = std::min<size_t>(align_up(max_field, 256), (size_t)64 << 20);
     L.scratch = take(L.scratch_bytes);
+    if (p[0].closure) {
+        L.cl_P = take(4 * (size_t)NPARAM);
+        L.cl_Pb = take(2 * (size_t)NPARAM);
+        L.cl_G = take(4 * (size_t)NPARAM);
+        L.cl_m = take(4 * (size_t)NPARAM);
+        L.cl_v = take(4 * (size_t)NPARAM);
+        L.cl_stats = take(4 * (size_t)NSTATS);
+        L.cl_sums = take(8 * 2 * (size_t)(NF + NOUT));
+        L.cl_loss = take(8);
+        L.cl_facc = take(8 * (size_t)slab * NF);
+        L.cl_nm = take(8 * (size_t)slab * 10);
+        L.cl_uc = take(4 * (size_t)slab * 3);
+        L.cl_inf = take(closure_bufs_bytes(slab, false));
+    }
     L.end = o;
     return 0;
 }
@@ -296,6 +336,10 @@ int validate_all(const lbmpcd_params* p, int n, std::string& msg) {
         if (p[i].wg_threads != p[0].wg_threads) {
             msg = "all instances must share wg_threads";
             return LBMPCD_E_INVALID;
+        }
+        if (p[i].closure && n != 1) {
+            msg = "the learned closure serves a context of one channel";
+            return LBMPCD_E_UNSUPPORTED;
         }
     }
     return 0;
@@ -456,6 +500,22 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     c->stats = (DevStats*)(c->ws + L.stats);
     c->clock = (long long*)(c->ws + L.clock);
     c->shifts = (double*)(c->ws + L.shifts);
+    if (p[0].closure) {
+        c->closure = true;
+        c->cl_P = (float*)(c->ws + L.cl_P);
+        c->cl_Pb = (uint16_t*)(c->ws + L.cl_Pb);
+        c->cl_G = (float*)(c->ws + L.cl_G);
+        c->cl_m = (float*)(c->ws + L.cl_m);
+        c->cl_v = (float*)(c->ws + L.cl_v);
+        c->cl_stats = (float*)(c->ws + L.cl_stats);
+        c->cl_sums = (double*)(c->ws + L.cl_sums);
+        c->cl_loss = (double*)(c->ws + L.cl_loss);
+        c->cl_facc = (double*)(c->ws + L.cl_facc);
+        c->cl_nm = (double*)(c->ws + L.cl_nm);
+        c->cl_uc = (float*)(c->ws + L.cl_uc);
+        c->cl_nslab = c->desc[0].nslab;
+        closure_bufs_carve((unsigned char*)(c->ws + L.cl_inf), c->cl_nslab, false, c->cl_inf);
+    }
     c->scratch = c->ws + L.scratch;
     c->scratch_bytes = L.scratch_bytes;
     int cap_max = 64;
@@ -511,6 +571,29 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
                                          c->f[c->fcur ^ 1], c->clock, c->shifts, c->mpcd ? c->S : 0, s);
                }));
         c->fcur ^= 1;
+        if (c->cl_on) {
+            // surrogate: the network's velocity of every slab node stands in
+            // for the MPCD samples -- in the profile, and with feedback in
+            // the projection onto the LB equilibria
+            HIPCHK(c, timed(c, 4, [&] {
+                       hipError_t e = closure_features(c->lb_fp, c->d_desc, 0, c->cl_nslab, c->f[c->fcur], nullptr,
+                                                       c->cl_stats, c->cl_inf.X, c->cl_uc, s);
+                       if (e == hipSuccess) e = mlp_forward(c->cl_P, c->cl_Pb, c->cl_inf, s);
+                       if (e == hipSuccess)
+                           e = closure_to_acc(c->d_desc, 0, c->cl_nslab, c->cl_inf.Y, c->cl_stats, c->cl_uc, c->acc,
+                                              c->prof, c->sampling ? 1 : 0, s);
+                       return e;
+                   }));
+            if (c->any_feedback)
+                HIPCHK(c, timed(c, 1, [&] {
+                           return launch_band(c->dim, c->lb_fp, c->d_desc, c->n_inst, c->total_band,
+                                              c->f[c->fcur], c->acc, c->ub, 1, s);
+                       }));
+            return 0;
+        }
+        if (c->cl_collect)
+            HIPCHK(c, closure_features(c->lb_fp, c->d_desc, 0, c->cl_nslab, c->f[c->fcur], c->cl_facc, nullptr,
+                                       nullptr, nullptr, s));
         if (c->mpcd) {
             HIPCHK(c, timed(c, 1, [&] {
                        return launch_band(c->dim, c->lb_fp, c->d_desc, c->n_inst, c->total_band, c->f[c->fcur],
@@ -527,7 +610,7 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
                 L.in = c->part[c->pcur]; L.out = c->part[c->pcur ^ 1];
                 L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
                 L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
-                L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts; L.shifts = c->shifts; L.shifts = c->shifts;
+                L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts;
                 L.coll_dt = sub > 0 ? 0 : -1;
                 L.coll_s = sub > 0 ? sub - 1 : c->S - 1;
                 L.str_s = sub;
@@ -567,7 +650,7 @@ int build_graph(lbmpcd_ctx* c) {
     he = hipGraphInstantiateWithFlags(&c->graph_exec, g, 0);
     (void)hipGraphDestroy(g);
     if (he != hipSuccess) return fail(c, LBMPCD_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(he));
-    c->graph_key = (c->fcur << 2) | (c->pcur << 1) | (c->sampling ? 1 : 0);
+    c->graph_key = (c->cl_on ? 8 : 0) | (c->fcur << 2) | (c->pcur << 1) | (c->sampling ? 1 : 0);
     return 0;
 }
 
@@ -579,18 +662,25 @@ int lbmpcd_step(lbmpcd_ctx* c, int32_t n_lb_steps) {
     if (n_lb_steps < 0) return fail(c, LBMPCD_E_INVALID, "negative step count");
     int it = 0;
     while (it < n_lb_steps) {
-        const bool steady = !c->mpcd || c->pending;
+        if (c->cl_on && c->cl_every > 0 && c->cl_since >= c->cl_every) {
+            // periodic check of the surrogate against a burst of plain MPCD steps
+            double err = 0.0;
+            if (int e = lbmpcd_closure_check(c, c->cl_burst, &err)) return e;
+        }
+        const bool steady = !c->mpcd || c->pending || c->cl_on;
         if (c->use_graphs && !c->timing && steady && n_lb_steps - it >= 2) {
-            const int key = (c->fcur << 2) | (c->pcur << 1) | (c->sampling ? 1 : 0);
+            const int key = (c->cl_on ? 8 : 0) | (c->fcur << 2) | (c->pcur << 1) | (c->sampling ? 1 : 0);
             if (!c->graph_exec || c->graph_key != key)
                 if (int e = build_graph(c)) return e;
             HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+            if (c->cl_on) c->cl_since += 2;
             c->t += 2;
             if (c->sampling) c->sampled_steps += 2;
             it += 2;
             continue;
         }
         if (int e = enqueue_one_step(c, c->stream)) return e;
+        if (c->cl_on) c->cl_since += 1;
         c->t++;
         if (c->sampling) c->sampled_steps++;
         ++it;
@@ -806,7 +896,7 @@ int lbmpcd_timing(lbmpcd_ctx* c, int32_t mode) {
     if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
     if (mode == 1) {
         if (int e = drain_marks(c)) return e;
-        for (int k = 0; k < 4; ++k) { c->timing_ms[k] = 0; c->timing_n[k] = 0; }
+        for (int k = 0; k < 5; ++k) { c->timing_ms[k] = 0; c->timing_n[k] = 0; }
         c->timing = true;
     } else if (mode == 0) {
         c->timing = false;
@@ -820,8 +910,8 @@ int lbmpcd_timing_read(lbmpcd_ctx* c, double* out, int32_t n_classes) {
     if (!c || !out || n_classes < 0) return fail(c, LBMPCD_E_INVALID, "bad arguments");
     if (int e = drain_marks(c)) return e;
     for (int k = 0; k < n_classes; ++k) {
-        out[2 * k] = k < 4 ? c->timing_ms[k] : 0.0;
-        out[2 * k + 1] = k < 4 ? (double)c->timing_n[k] : 0.0;
+        out[2 * k] = k < 5 ? c->timing_ms[k] : 0.0;
+        out[2 * k + 1] = k < 5 ? (double)c->timing_n[k] : 0.0;
     }
     return 0;
 }
@@ -890,6 +980,267 @@ int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace,
     (void)hipEventDestroy(ev[1]);
     if (rc) return rc;
     if (best < 0) return fail(nullptr, LBMPCD_E_NOMEM, "no candidate fits the workspace");
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// learned closure
+// ---------------------------------------------------------------------------
+namespace {
+
+int need_closure(lbmpcd_ctx* c) {
+    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
+    if (c->sticky) return c->sticky;
+    if (!c->closure) return fail(c, LBMPCD_E_STATE, "the context was created without closure = 1");
+    return 0;
+}
+
+size_t train_scratch_bytes(long long rows) {
+    return closure_bufs_bytes(rows, true) + align_up((size_t)rows * NOUT * 4, 256);
+}
+
+// One standardised batch of `rows` rows (drawn, or the first rows of X, Y).
+int closure_batch(lbmpcd_ctx* c, const float* X, const float* Y, long long n, long long rows, bool draw,
+                  uint32_t step, void* scratch, ClosureBufs& b, float*& Yb) {
+    closure_bufs_carve((unsigned char*)scratch, rows, true, b);
+    Yb = (float*)((unsigned char*)scratch + closure_bufs_bytes(rows, true));
+    const InstDesc& d = c->desc[0];
+    HIPCHK(c, mlp_gather(X, Y, n, c->cl_stats, rows, draw, d.key0, d.key1, step, b.X, Yb, c->stream));
+    return 0;
+}
+
+}  // namespace
+
+int lbmpcd_closure_scratch_size(int64_t n, int32_t batch, size_t* bytes) {
+    if (!bytes || n < 1) return fail(nullptr, LBMPCD_E_INVALID, "bad arguments");
+    const long long rows = batch > 0 && batch < n ? batch : n;
+    *bytes = train_scratch_bytes(rows);
+    return 0;
+}
+
+int lbmpcd_closure_collect(lbmpcd_ctx* c, int32_t lb_steps, float* X, float* Y) {
+    if (int e = need_closure(c)) return e;
+    if (lb_steps < 1 || !X || !Y) return fail(c, LBMPCD_E_INVALID, "need lb_steps >= 1 and device X, Y");
+    if (c->cl_on) return fail(c, LBMPCD_E_STATE, "collection runs the plain coupled step; disable the closure");
+    const InstDesc& d = c->desc[0];
+    HIPCHK(c, hipMemsetAsync(c->cl_facc, 0, sizeof(double) * c->cl_nslab * NF, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->cl_nm, 0, sizeof(double) * c->cl_nslab * 10, c->stream));
+    for (int k = 0; k < lb_steps; ++k) {
+        c->cl_collect = true;
+        int e = enqueue_one_step(c, c->stream);
+        c->cl_collect = false;
+        if (e) return e;
+        c->t++;
+        if (c->sampling) c->sampled_steps++;
+        // the samples are taken from the collided state
+        if (int e2 = finalize(c)) return e2;
+        HIPCHK(c, closure_node_moments(c->part_fp, c->d_desc, 0, d.ntiles * (long long)d.cap, c->part[c->pcur].pos[0],
+                                       c->cstride, c->fill[c->pcur], c->cl_nm, c->stream));
+    }
+    HIPCHK(c, closure_collect_finish(c->cl_nslab, lb_steps, d.mass, c->cl_facc, c->cl_nm, X, Y, c->stream));
+    return 0;
+}
+
+int lbmpcd_closure_features(lbmpcd_ctx* c, float* X) {
+    if (int e = need_closure(c)) return e;
+    if (!X) return fail(c, LBMPCD_E_INVALID, "X is null");
+    HIPCHK(c, hipMemsetAsync(c->cl_facc, 0, sizeof(double) * c->cl_nslab * NF, c->stream));
+    HIPCHK(c, closure_features(c->lb_fp, c->d_desc, 0, c->cl_nslab, c->f[c->fcur], c->cl_facc, nullptr, nullptr,
+                               nullptr, c->stream));
+    // one window of one step: the feature sums are the features
+    HIPCHK(c, closure_collect_finish(c->cl_nslab, 1, 1.0, c->cl_facc, nullptr, X, nullptr, c->stream));
+    return 0;
+}
+
+int lbmpcd_closure_train(lbmpcd_ctx* c, const float* X, const float* Y, int64_t n, const lbmpcd_train_opts* o,
+                         void* scratch, size_t scratch_bytes, float* loss_per_epoch) {
+    if (int e = need_closure(c)) return e;
+    if (!o || o->struct_size != sizeof(lbmpcd_train_opts)) return fail(c, LBMPCD_E_INVALID, "bad train options");
+    if (!X || !Y || n < 1 || o->epochs < 1 || !(o->lr > 0.0f)) return fail(c, LBMPCD_E_INVALID, "bad arguments");
+    const long long rows = o->batch > 0 && o->batch < n ? o->batch : n;
+    if (!scratch || scratch_bytes < train_scratch_bytes(rows))
+        return fail(c, LBMPCD_E_NOMEM, "scratch smaller than lbmpcd_closure_scratch_size");
+    hipStream_t s = c->stream;
+    if (!c->cl_ready) {
+        HIPCHK(c, mlp_stats(X, Y, n, c->cl_sums, c->cl_stats, s));
+        const uint32_t k0 = (uint32_t)(o->seed & 0xFFFFFFFFu), k1 = (uint32_t)(o->seed >> 32);
+        HIPCHK(c, mlp_init(c->cl_P, c->cl_Pb, c->cl_m, c->cl_v, k0, k1, s));
+        c->cl_adam_t = 0;
+        c->cl_ready = true;
+    }
+    const long long steps = (n + rows - 1) / rows;
+    for (int ep = 0; ep < o->epochs; ++ep) {
+        HIPCHK(c, hipMemsetAsync(c->cl_loss, 0, sizeof(double), s));
+        for (long long st = 0; st < steps; ++st) {
+            ClosureBufs b;
+            float* Yb = nullptr;
+            if (int e = closure_batch(c, X, Y, n, rows, rows < n, (uint32_t)(c->cl_adam_t + 1), scratch, b, Yb))
+                return e;
+            HIPCHK(c, mlp_forward(c->cl_P, c->cl_Pb, b, s));
+            HIPCHK(c, mlp_backward(c->cl_Pb, Yb, b, c->cl_G, c->cl_loss, s));
+            ++c->cl_adam_t;
+            HIPCHK(c, mlp_adam(c->cl_P, c->cl_Pb, c->cl_G, c->cl_m, c->cl_v, c->cl_adam_t, o->lr, o->beta1,
+                               o->beta2, o->eps, s));
+        }
+        if (loss_per_epoch) {
+            double l = 0.0;
+            HIPCHK(c, hipMemcpyAsync(&l, c->cl_loss, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            loss_per_epoch[ep] = (float)(l / (double)steps);
+        }
+    }
+    return 0;
+}
+
+int lbmpcd_closure_loss_grad(lbmpcd_ctx* c, const float* X, const float* Y, int64_t n, void* scratch,
+                             size_t scratch_bytes, double* loss, float* grad) {
+    if (int e = need_closure(c)) return e;
+    if (!c->cl_ready) return fail(c, LBMPCD_E_STATE, "closure parameters are not set");
+    if (!X || !Y || n < 1) return fail(c, LBMPCD_E_INVALID, "bad arguments");
+    if (!scratch || scratch_bytes < train_scratch_bytes(n))
+        return fail(c, LBMPCD_E_NOMEM, "scratch smaller than lbmpcd_closure_scratch_size(n, n)");
+    hipStream_t s = c->stream;
+    ClosureBufs b;
+    float* Yb = nullptr;
+    if (int e = closure_batch(c, X, Y, n, n, false, 0u, scratch, b, Yb)) return e;
+    HIPCHK(c, hipMemsetAsync(c->cl_loss, 0, sizeof(double), s));
+    HIPCHK(c, mlp_forward(c->cl_P, c->cl_Pb, b, s));
+    HIPCHK(c, mlp_backward(c->cl_Pb, Yb, b, c->cl_G, c->cl_loss, s));
+    if (loss) HIPCHK(c, hipMemcpyAsync(loss, c->cl_loss, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (grad) HIPCHK(c, hipMemcpyAsync(grad, c->cl_G, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return 0;
+}
+
+int lbmpcd_closure_forward(lbmpcd_ctx* c, const float* X, int64_t n, float* Y, void* scratch, size_t scratch_bytes) {
+    if (int e = need_closure(c)) return e;
+    if (!c->cl_ready) return fail(c, LBMPCD_E_STATE, "closure parameters are not set");
+    if (!X || !Y || n < 1) return fail(c, LBMPCD_E_INVALID, "bad arguments");
+    if (!scratch || scratch_bytes < train_scratch_bytes(n))
+        return fail(c, LBMPCD_E_NOMEM, "scratch smaller than lbmpcd_closure_scratch_size(n, n)");
+    ClosureBufs b;
+    float* Yb = nullptr;
+    if (int e = closure_batch(c, X, nullptr, n, n, false, 0u, scratch, b, Yb)) return e;
+    HIPCHK(c, mlp_forward(c->cl_P, c->cl_Pb, b, c->stream));
+    HIPCHK(c, mlp_destandardize(b.Y, c->cl_stats, X, n, Y, c->stream));
+    return 0;
+}
+
+int lbmpcd_closure_weights(lbmpcd_ctx* c, int32_t get_or_set, float* buf, size_t bytes) {
+    if (int e = need_closure(c)) return e;
+    const size_t need = sizeof(float) * (size_t)(NPARAM + NSTATS);
+    if (!buf || bytes < need) return fail(c, LBMPCD_E_INVALID, "buffer smaller than the parameter block");
+    hipStream_t s = c->stream;
+    if (get_or_set == 0) {
+        if (!c->cl_ready) return fail(c, LBMPCD_E_STATE, "closure parameters are not set");
+        HIPCHK(c, hipMemcpyAsync(buf, c->cl_P, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(buf + NPARAM, c->cl_stats, sizeof(float) * NSTATS, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    } else if (get_or_set == 1) {
+        HIPCHK(c, hipMemcpyAsync(c->cl_P, buf, sizeof(float) * NPARAM, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(c->cl_stats, buf + NPARAM, sizeof(float) * NSTATS, hipMemcpyHostToDevice, s));
+        HIPCHK(c, mlp_refresh_bf16(c->cl_P, c->cl_Pb, s));
+        HIPCHK(c, hipMemsetAsync(c->cl_m, 0, sizeof(float) * NPARAM, s));
+        HIPCHK(c, hipMemsetAsync(c->cl_v, 0, sizeof(float) * NPARAM, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        c->cl_adam_t = 0;
+        c->cl_ready = true;
+    } else {
+        return fail(c, LBMPCD_E_INVALID, "get_or_set must be 0 or 1");
+    }
+    return 0;
+}
+
+int lbmpcd_closure_enable(lbmpcd_ctx* c, int32_t on, double fallback_tol, int32_t check_every, int32_t check_steps) {
+    if (int e = need_closure(c)) return e;
+    if (on && !c->cl_ready) return fail(c, LBMPCD_E_STATE, "closure parameters are not set");
+    if (fallback_tol < 0.0 || check_every < 0 || check_steps < 0)
+        return fail(c, LBMPCD_E_INVALID, "negative tolerance or check interval");
+    // the particles rest while the surrogate runs: complete their pending
+    // collision now, in the grid shift it was binned with
+    if (on && !c->cl_on)
+        if (int e = finalize(c)) return e;
+    c->cl_on = on != 0;
+    c->cl_tol = fallback_tol > 0.0 ? fallback_tol : 0.02;
+    c->cl_every = check_every;
+    c->cl_burst = check_steps > 0 ? check_steps : 40;
+    c->cl_since = 0;
+    c->cl_fell_back = false;
+    return 0;
+}
+
+int lbmpcd_closure_check(lbmpcd_ctx* c, int32_t burst_steps, double* rel_err) {
+    if (int e = need_closure(c)) return e;
+    if (!c->cl_ready) return fail(c, LBMPCD_E_STATE, "closure parameters are not set");
+    if (burst_steps < 2 || !rel_err) return fail(c, LBMPCD_E_INVALID, "need burst_steps >= 2 and rel_err");
+    const InstDesc& d = c->desc[0];
+    const bool was_on = c->cl_on, was_sampling = c->sampling;
+    c->cl_on = false;
+    // plain MPCD burst; its second half is averaged
+    if (int e = lbmpcd_step(c, burst_steps - burst_steps / 2)) return e;
+    if (int e = lbmpcd_sample(c, 1)) return e;
+    if (int e = lbmpcd_step(c, burst_steps / 2)) return e;
+    std::vector<double> pm((size_t)d.R * 4), pp((size_t)d.R * 4);
+    if (int e = lbmpcd_moments(c, LBMPCD_PROFILE, 0, pm.data(), pm.size() * 8, 0)) return e;
+    // the surrogate's profile of the current state
+    HIPCHK(c, launch_zero(c->prof, c->prof_bytes, c->stream));
+    HIPCHK(c, closure_features(c->lb_fp, c->d_desc, 0, c->cl_nslab, c->f[c->fcur], nullptr, c->cl_stats,
+                               c->cl_inf.X, c->cl_uc, c->stream));
+    HIPCHK(c, mlp_forward(c->cl_P, c->cl_Pb, c->cl_inf, c->stream));
+    // written into the sample sums and profile; the sums are cleared again below
+    HIPCHK(c, closure_to_acc(c->d_desc, 0, c->cl_nslab, c->cl_inf.Y, c->cl_stats, c->cl_uc, c->acc, c->prof, 1,
+                             c->stream));
+    if (int e = lbmpcd_moments(c, LBMPCD_PROFILE, 0, pp.data(), pp.size() * 8, 0)) return e;
+    HIPCHK(c, launch_zero(c->acc, c->acc_bytes, c->stream));
+    HIPCHK(c, launch_zero(c->prof, c->prof_bytes, c->stream));
+    c->sampling = was_sampling;
+    c->sampled_steps = 0;
+    // relative L2 error of the streamwise profile over the LB node rows
+    // between the buffers (the network predicts node averages)
+    double num = 0.0, den = 0.0;
+    for (int y = d.buf_lo; y < (d.yhi - d.ylo) - d.buf_hi; ++y) {
+        double cm = 0, sm = 0, cp = 0, sp = 0;
+        for (int J = y * d.r; J < (y + 1) * d.r; ++J) {
+            cm += pm[4 * J]; sm += pm[4 * J + 1];
+            cp += pp[4 * J]; sp += pp[4 * J + 1];
+        }
+        if (cm <= 0.0 || cp <= 0.0) continue;
+        const double um = sm / cm, up = sp / cp;
+        num += (up - um) * (up - um);
+        den += um * um;
+    }
+    const double err = den > 0.0 ? std::sqrt(num / den) : 0.0;
+    *rel_err = err;
+    c->cl_last_err = err;
+    c->cl_since = 0;
+    if (err > c->cl_tol) {
+        c->cl_fell_back = true;
+        c->cl_on = false;
+    } else {
+        c->cl_on = was_on;
+    }
+    return 0;
+}
+
+int lbmpcd_closure_status(const lbmpcd_ctx* c, int32_t* on, int32_t* fell_back, double* last_err) {
+    if (!c) return fail(nullptr, LBMPCD_E_INVALID, "null context");
+    if (on) *on = c->cl_on ? 1 : 0;
+    if (fell_back) *fell_back = c->cl_fell_back ? 1 : 0;
+    if (last_err) *last_err = c->cl_last_err;
+    return 0;
+}
+
+int lbmpcd_closure_gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t* A, const uint16_t* B, float* C,
+                             void* hip_stream) {
+    if (M < 0 || N < 0 || K < 1 || !A || !B || !C) return fail(nullptr, LBMPCD_E_INVALID, "bad arguments");
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.sam = K; g.sak = 1;
+    g.B = B; g.sbk = 1; g.sbn = K;
+    g.C = C; g.ldc = N;
+    g.epi = EPI_NONE;
+    const hipError_t e = launch_gemm(g, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(nullptr, LBMPCD_E_DEVICE, hipGetErrorString(e));
     return 0;
 }
 

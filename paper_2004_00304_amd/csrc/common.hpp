@@ -16,7 +16,11 @@ constexpr uint32_t BAD_SLOT = 0xFFFFFFFFu;
 
 // Purposes of the random streams: the counter of every draw is
 // (element, LB step, substep << 8 | purpose, block).
-enum Purpose : uint32_t { P_INIT_POS = 1, P_INIT_VEL = 2, P_REINJ = 3, P_SHIFT = 4, P_ROT = 5, P_WALL = 6 };
+enum Purpose : uint32_t {
+    P_INIT_POS = 1, P_INIT_VEL = 2, P_REINJ = 3, P_SHIFT = 4, P_ROT = 5, P_WALL = 6,
+    P_MLP_INIT = 7,   // closure network initial weights
+    P_MLP_BATCH = 8,  // closure training batch draws
+};
 
 // Everything a kernel needs to know about one channel.  One array of these
 // lives in the workspace; kernels find their instance from a global index by

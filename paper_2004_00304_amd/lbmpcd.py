@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmpcd.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 RHO, U, PI, POP, PART_POS, PART_VEL, CELL_ID, CELL_COUNT, CELL_VCM, PROFILE, UFINE, STATS, \
     PART_VEL_PENDING = range(13)
@@ -43,8 +43,17 @@ class Params(C.Structure):
         ("collision", C.c_int32), ("grid_shift", C.c_int32), ("feedback", C.c_int32),
         ("init_flow", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint32),
         ("tile", C.c_int32 * 3), ("capacity_factor", C.c_double),
-        ("tile_target", C.c_int32), ("wg_threads", C.c_int32),
+        ("tile_target", C.c_int32), ("wg_threads", C.c_int32), ("closure", C.c_int32),
     ]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
+
+
+# the closure network's sizes (see include/lbmpcd.h)
+CLOSURE_NF, CLOSURE_NOUT, CLOSURE_NPARAM, CLOSURE_NSTATS = 271, 9, 71177, 560
 
 
 class Tuning(C.Structure):
@@ -79,6 +88,22 @@ def _load():
     L.lbmpcd_strerror.restype = C.c_char_p
     L.lbmpcd_autotune.argtypes = [P, C.c_int32, P, C.c_size_t, P, C.c_int32, C.POINTER(Tuning)]
     L.lbmpcd_autotune.restype = C.c_int
+    L.lbmpcd_closure_scratch_size.argtypes = [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
+    L.lbmpcd_closure_collect.argtypes = [P, C.c_int32, P, P]
+    L.lbmpcd_closure_train.argtypes = [P, P, P, C.c_int64, C.POINTER(TrainOpts), P, C.c_size_t, P]
+    L.lbmpcd_closure_loss_grad.argtypes = [P, P, P, C.c_int64, P, C.c_size_t, P, P]
+    L.lbmpcd_closure_forward.argtypes = [P, P, C.c_int64, P, P, C.c_size_t]
+    L.lbmpcd_closure_features.argtypes = [P, P]
+    L.lbmpcd_closure_weights.argtypes = [P, C.c_int32, P, C.c_size_t]
+    L.lbmpcd_closure_enable.argtypes = [P, C.c_int32, C.c_double, C.c_int32, C.c_int32]
+    L.lbmpcd_closure_check.argtypes = [P, C.c_int32, C.POINTER(C.c_double)]
+    L.lbmpcd_closure_status.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.lbmpcd_closure_gemm_bf16.argtypes = [C.c_int64, C.c_int64, C.c_int64, P, P, P, P]
+    for name in ("lbmpcd_closure_scratch_size", "lbmpcd_closure_collect", "lbmpcd_closure_train",
+                 "lbmpcd_closure_loss_grad", "lbmpcd_closure_forward", "lbmpcd_closure_weights",
+                 "lbmpcd_closure_enable", "lbmpcd_closure_check", "lbmpcd_closure_status",
+                 "lbmpcd_closure_gemm_bf16", "lbmpcd_closure_features"):
+        getattr(L, name).restype = C.c_int
     L.lbmpcd_last_error.argtypes = [P]
     L.lbmpcd_last_error.restype = C.c_char_p
     for name in ("lbmpcd_workspace_size", "lbmpcd_init", "lbmpcd_step", "lbmpcd_moments",
@@ -92,7 +117,11 @@ _lib = _load()
 EXPORTED = ("lbmpcd_workspace_size", "lbmpcd_init", "lbmpcd_step", "lbmpcd_moments",
             "lbmpcd_field_bytes", "lbmpcd_sample", "lbmpcd_get_state", "lbmpcd_set_state",
             "lbmpcd_sync", "lbmpcd_destroy", "lbmpcd_strerror", "lbmpcd_last_error", "lbmpcd_timing",
-            "lbmpcd_timing_read", "lbmpcd_graphs", "lbmpcd_autotune")
+            "lbmpcd_timing_read", "lbmpcd_graphs", "lbmpcd_autotune", "lbmpcd_closure_scratch_size",
+            "lbmpcd_closure_collect", "lbmpcd_closure_train", "lbmpcd_closure_loss_grad",
+            "lbmpcd_closure_forward", "lbmpcd_closure_weights", "lbmpcd_closure_enable",
+            "lbmpcd_closure_check", "lbmpcd_closure_status", "lbmpcd_closure_gemm_bf16",
+            "lbmpcd_closure_features")
 
 # candidate tile sizes of lbmpcd_autotune (expected particles per tile)
 TUNE_TILE_TARGETS = (160, 320, 640, 1280)
@@ -123,6 +152,7 @@ def params_struct(p: dict) -> Params:
     s.capacity_factor = p.get("capacity_factor", 0.0)
     s.tile_target = p.get("tile_target", 0)
     s.wg_threads = p.get("wg_threads", 0)
+    s.closure = p.get("closure", 0)
     return s
 
 
@@ -167,6 +197,27 @@ def autotune(params, lb_steps: int = 5, device="cuda", stream=None) -> dict:
         del ws
     return dict(tile_target=out.tile_target, wg_threads=out.wg_threads, tried=out.tried,
                 ms_per_step=out.ms_per_step, ms_default=out.ms_default)
+
+
+def gemm_bf16(A, B):
+    """C = A B^T on the matrix cores (A: M x K, B: N x K, torch bfloat16 on
+    the GPU, row-major) -> float32 M x N."""
+    import torch
+    A = A.contiguous()
+    B = B.contiguous()
+    M, K = A.shape
+    N = B.shape[0]
+    out = torch.empty(M, N, dtype=torch.float32, device=A.device)
+    st = torch.cuda.current_stream(A.device)
+    _check(_lib.lbmpcd_closure_gemm_bf16(M, N, K, C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()),
+                                         C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
+    return out
+
+
+def scratch_size(n: int, batch: int = 0) -> int:
+    b = C.c_size_t()
+    _check(_lib.lbmpcd_closure_scratch_size(int(n), int(batch), C.byref(b)))
+    return int(b.value)
 
 
 def with_tuning(params, tuning: dict):
@@ -322,14 +373,97 @@ class Sim:
     def stats(self, inst=0) -> dict:
         return self.moments(STATS, inst)
 
+    # -- learned closure
+    def _scratch(self, n, batch=0):
+        return self.torch.empty(scratch_size(n, batch), dtype=self.torch.uint8, device=self.device)
+
+    def closure_collect(self, lb_steps: int):
+        """(X, Y) device tensors: features and targets of every slab node
+        averaged over lb_steps plain coupled steps."""
+        t = self.torch
+        p = self.plist[0]
+        nslab = p["n"][0] * (p["yhi"] - p["ylo"]) * p["n"][2]
+        X = t.empty(nslab, CLOSURE_NF, dtype=t.float32, device=self.device)
+        Y = t.empty(nslab, CLOSURE_NOUT, dtype=t.float32, device=self.device)
+        _check(_lib.lbmpcd_closure_collect(self._h, int(lb_steps), C.c_void_p(X.data_ptr()),
+                                           C.c_void_p(Y.data_ptr())), self._h)
+        return X, Y
+
+    def closure_features(self):
+        """Raw features of every slab node of the current populations."""
+        t = self.torch
+        p = self.plist[0]
+        nslab = p["n"][0] * (p["yhi"] - p["ylo"]) * p["n"][2]
+        X = t.empty(nslab, CLOSURE_NF, dtype=t.float32, device=self.device)
+        _check(_lib.lbmpcd_closure_features(self._h, C.c_void_p(X.data_ptr())), self._h)
+        return X
+
+    def closure_train(self, X, Y, epochs=1, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=1):
+        o = TrainOpts()
+        o.struct_size = C.sizeof(TrainOpts)
+        o.epochs, o.batch, o.lr, o.beta1, o.beta2, o.eps, o.seed = epochs, batch, lr, beta1, beta2, eps, seed
+        X = X.contiguous()
+        Y = Y.contiguous()
+        n = X.shape[0]
+        scr = self._scratch(n, batch)
+        losses = np.zeros(epochs, np.float32)
+        _check(_lib.lbmpcd_closure_train(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), n,
+                                         C.byref(o), C.c_void_p(scr.data_ptr()), scr.numel(),
+                                         losses.ctypes.data_as(C.c_void_p)), self._h)
+        return losses
+
+    def closure_loss_grad(self, X, Y):
+        X = X.contiguous()
+        Y = Y.contiguous()
+        n = X.shape[0]
+        scr = self._scratch(n, n)
+        loss = C.c_double()
+        g = np.zeros(CLOSURE_NPARAM, np.float32)
+        _check(_lib.lbmpcd_closure_loss_grad(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), n,
+                                             C.c_void_p(scr.data_ptr()), scr.numel(), C.byref(loss),
+                                             g.ctypes.data_as(C.c_void_p)), self._h)
+        return float(loss.value), g
+
+    def closure_forward(self, X):
+        X = X.contiguous()
+        n = X.shape[0]
+        scr = self._scratch(n, n)
+        Y = self.torch.empty(n, CLOSURE_NOUT, dtype=self.torch.float32, device=self.device)
+        _check(_lib.lbmpcd_closure_forward(self._h, C.c_void_p(X.data_ptr()), n, C.c_void_p(Y.data_ptr()),
+                                           C.c_void_p(scr.data_ptr()), scr.numel()), self._h)
+        return Y
+
+    def closure_weights(self, block=None):
+        """Without argument: the FP32 parameter block (numpy); with one: load it."""
+        if block is None:
+            out = np.zeros(CLOSURE_NPARAM + CLOSURE_NSTATS, np.float32)
+            _check(_lib.lbmpcd_closure_weights(self._h, 0, out.ctypes.data_as(C.c_void_p), out.nbytes), self._h)
+            return out
+        blk = np.ascontiguousarray(block, np.float32)
+        _check(_lib.lbmpcd_closure_weights(self._h, 1, blk.ctypes.data_as(C.c_void_p), blk.nbytes), self._h)
+
+    def closure_enable(self, on=True, tol=0.02, check_every=0, check_steps=40):
+        _check(_lib.lbmpcd_closure_enable(self._h, int(on), float(tol), int(check_every), int(check_steps)),
+               self._h)
+
+    def closure_check(self, burst_steps=40) -> float:
+        e = C.c_double()
+        _check(_lib.lbmpcd_closure_check(self._h, int(burst_steps), C.byref(e)), self._h)
+        return float(e.value)
+
+    def closure_status(self) -> dict:
+        on, fb, err = C.c_int32(), C.c_int32(), C.c_double()
+        _check(_lib.lbmpcd_closure_status(self._h, C.byref(on), C.byref(fb), C.byref(err)), self._h)
+        return dict(on=bool(on.value), fell_back=bool(fb.value), last_err=float(err.value))
+
     # -- kernel timing (HIP events on the context's stream)
-    KERNEL_CLASSES = ("lb_step", "band", "interp", "particles")
+    KERNEL_CLASSES = ("lb_step", "band", "interp", "particles", "closure")
 
     def timing(self, mode: int):
         _check(_lib.lbmpcd_timing(self._h, int(mode)), self._h)
 
     def timing_read(self) -> dict:
-        out = np.zeros(8, np.float64)
-        _check(_lib.lbmpcd_timing_read(self._h, out.ctypes.data_as(C.c_void_p), 4), self._h)
+        out = np.zeros(10, np.float64)
+        _check(_lib.lbmpcd_timing_read(self._h, out.ctypes.data_as(C.c_void_p), 5), self._h)
         return {k: dict(ms=float(out[2 * i]), launches=int(out[2 * i + 1]))
                 for i, k in enumerate(self.KERNEL_CLASSES)}

@@ -22,7 +22,7 @@ _BASE = dict(
     feedback=1, init_flow=0, seed=1, instance=0,
     # launch configuration of the HIP path (tile shape in cells, tile slot
     # capacity over expected occupancy); 0 = library default
-    tile=(0, 0, 0), capacity_factor=0.0, tile_target=0, wg_threads=0,
+    tile=(0, 0, 0), capacity_factor=0.0, tile_target=0, wg_threads=0, closure=0,
 )
 
 

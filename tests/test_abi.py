@@ -21,7 +21,7 @@ def binding():
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "lbmpcd.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbmpcd_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(lbmpcd_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_every_declared_symbol_is_exported(binding):

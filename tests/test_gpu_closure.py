@@ -1,0 +1,269 @@
+"""The learned closure on the GPU, through the C ABI, against the FP64 oracle
+of oracle/mlp.py on identical BF16 operands: the matrix-core product, the
+forward pass (1e-2 elementwise, 1e-3 in norm), loss and gradients (1e-2
+relative L2 per layer), one Adam step on the FP32 parameters (1e-5 of the
+step), the features of the LB state and the particle targets; then that a
+trained surrogate reproduces the plain MPCD profile within 2%, is faster
+than the plain step, and falls back when it is wrong."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2004_00304_amd import workloads as W
+from tests.gpu_util import banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import mlp as M
+    from paper_2004_00304_amd import lbmpcd
+    return torch, M, lbmpcd
+
+
+def channel(**kw):
+    """A small 3D channel with the closure reserved (D3Q19, walls, Poiseuille
+    start, slab with 1-row buffers, FP64)."""
+    base = dict(dim=3, n=(16, 16, 8), tau=0.8, g=(1e-4, 0.0, 0.0), walls_y=1, init_flow=1, ylo=4, yhi=12,
+                buf_lo=1, buf_hi=1, ppc=5, part_fp=64, lb_fp=64, alpha_deg=120.0, feedback=1, closure=1)
+    base.update(kw)
+    return W.make(**base)
+
+
+def random_block(M, rng, scale=0.5):
+    P = np.zeros(M.NPARAM)
+    for (fo, fi), (ow, ob) in zip(M.LAYERS, M.OFFS):
+        Wt = rng.normal(0, scale / np.sqrt(min(fi, M.NF)), (fo, fi))
+        if fi == M.NFP:
+            Wt[:, M.NF:] = 0.0
+        P[ow:ow + fo * fi] = Wt.reshape(-1)
+        P[ob:ob + fo] = rng.normal(0, 0.1, fo)
+    st = np.concatenate([rng.normal(0, 1, M.NF), rng.uniform(0.5, 2, M.NF), rng.normal(0, 1, 9),
+                         rng.uniform(0.5, 2, 9)])
+    return np.concatenate([P, st]).astype(np.float32)
+
+
+def raw_data(M, rng, block, n):
+    st = block[M.NPARAM:].astype(np.float64)
+    mx, sx, my, sy = M.split_stats(st)
+    X = (mx + sx * rng.normal(size=(n, M.NF))).astype(np.float32)
+    Y = (my + sy * rng.normal(size=(n, 9))).astype(np.float32)
+    return X, Y
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("M_,N_,K_", [(100, 70, 300), (64, 64, 32), (1, 9, 128), (257, 128, 288)])
+def test_gemm_bf16_matches_exact_product(env, M_, N_, K_):
+    """C = A B^T with BF16 inputs: every product of two BF16 numbers is exact
+    in FP32, so the only error is FP32 accumulation (~K 2^-24)."""
+    torch, M, lbmpcd = env
+    rng = np.random.default_rng(M_ + N_ + K_)
+    A = torch.tensor(rng.normal(size=(M_, K_)), dtype=torch.bfloat16, device="cuda")
+    B = torch.tensor(rng.normal(size=(N_, K_)), dtype=torch.bfloat16, device="cuda")
+    Cg = lbmpcd.gemm_bf16(A, B).cpu().numpy().astype(np.float64)
+    Ce = A.float().cpu().numpy().astype(np.float64) @ B.float().cpu().numpy().astype(np.float64).T
+    err = np.abs(Cg - Ce).max() / np.abs(Ce).max()
+    banner(f"gemm {M_}x{N_}x{K_}: max rel err {err:.2e}")
+    assert err < 1e-5
+
+
+def test_forward_and_gradient_match_oracle(env):
+    torch, M, lbmpcd = env
+    rng = np.random.default_rng(11)
+    sim = lbmpcd.Sim(channel())
+    block = random_block(M, rng)
+    sim.closure_weights(block)
+    assert np.array_equal(sim.closure_weights(), block)
+    X, Y = raw_data(M, rng, block, 700)
+    Xt, Yt = torch.tensor(X, device="cuda"), torch.tensor(Y, device="cuda")
+    P32 = block[:M.NPARAM].astype(np.float64)
+    st = block[M.NPARAM:].astype(np.float64)
+    mx, sx, my, sy = M.split_stats(st)
+    Xs = M.standardise(X, st)
+    Ys = (M.network_targets(X, Y) - my) / sy
+
+    out = sim.closure_forward(Xt).cpu().numpy().astype(np.float64)
+    yo, _ = M.forward(P32, Xs)
+    want = M.physical_outputs(X, yo * sy + my)
+    scale = np.abs(want).max()
+    el = np.abs(out - want).max() / scale
+    nr = rel_l2(out, want)
+    banner(f"forward: max {el:.2e}, norm {nr:.2e}")
+    assert el <= 1e-2 and nr <= 1e-3
+
+    loss, G = sim.closure_loss_grad(Xt, Yt)
+    lo, Go = M.loss_grad(P32, Xs, Ys)
+    banner(f"loss gpu {loss:.6g} oracle {lo:.6g}")
+    assert abs(loss - lo) <= 1e-3 * lo
+    for (fo, fi), (ow, ob) in zip(M.LAYERS, M.OFFS):
+        ew = rel_l2(G[ow:ow + fo * fi], Go[ow:ow + fo * fi])
+        eb = rel_l2(G[ob:ob + fo], Go[ob:ob + fo])
+        banner(f"grad layer {fo}x{fi}: W {ew:.2e} b {eb:.2e}")
+        assert ew <= 1e-2 and eb <= 1e-2
+
+
+def test_adam_step_matches_oracle(env):
+    """One training step over all rows in order: the GPU's own gradient goes
+    through Adam on the FP32 parameters exactly as in the oracle."""
+    torch, M, lbmpcd = env
+    rng = np.random.default_rng(12)
+    sim = lbmpcd.Sim(channel())
+    block = random_block(M, rng)
+    sim.closure_weights(block)
+    X, Y = raw_data(M, rng, block, 300)
+    Xt, Yt = torch.tensor(X, device="cuda"), torch.tensor(Y, device="cuda")
+    _, G = sim.closure_loss_grad(Xt, Yt)
+    lr = 1e-3
+    sim.closure_train(Xt, Yt, epochs=1, batch=1 << 20, lr=lr)
+    after = sim.closure_weights()[:M.NPARAM].astype(np.float64)
+    P0 = block[:M.NPARAM].astype(np.float64)
+    want, _, _ = M.adam(P0, G.astype(np.float64), np.zeros(M.NPARAM), np.zeros(M.NPARAM), 1, lr)
+    err = np.abs(after - want).max()
+    banner(f"adam step: max abs err {err:.2e} (step {lr})")
+    assert err <= 1e-5 * lr + 1e-7 * np.abs(P0).max()
+
+
+def test_features_and_targets_match_oracle(env):
+    torch, M, lbmpcd = env
+    p = channel()
+    sim = lbmpcd.Sim(p)
+    sim.step(3)
+    X = sim.closure_features().cpu().numpy().astype(np.float64)
+    Xo = M.features(sim.f(), p)
+    colscale = np.maximum(np.abs(Xo).max(axis=0), 1e-12)
+    err = (np.abs(X - Xo) / colscale).max()
+    banner(f"features: max rel err {err:.2e}")
+    assert err <= 2e-6
+
+    Xc, Yc = sim.closure_collect(1)
+    pos, vel = sim.particles()  # [3][N] each, the collided state the targets were taken from
+    To = M.targets(pos.T, vel.T, p)
+    Yg = Yc.cpu().numpy().astype(np.float64)
+    sc = np.maximum(np.abs(To).max(axis=0), 1e-12)
+    err = (np.abs(Yg - To) / sc).max()
+    banner(f"targets: max rel err {err:.2e}")
+    assert err <= 2e-6
+
+
+def oneway(**kw):
+    """The paper's one-way coupling (feedback 0) on a wider channel: the LB
+    does not see the particles, so the surrogate and the plain run share the
+    LB state and their MPCD profiles compare directly."""
+    base = dict(n=(32, 16, 16), feedback=0)
+    base.update(kw)
+    return channel(**base)
+
+
+def _train_closure(lbmpcd, torch, configs, warm=300, windows=2, window=320):
+    X, Y = [], []
+    for p in configs:
+        s = lbmpcd.Sim(p)
+        s.step(warm)  # past the MPCD transient from the Poiseuille start
+        for _ in range(windows):
+            # long windows: the particle noise of the targets averages down
+            x, y = s.closure_collect(window)
+            X.append(x)
+            Y.append(y)
+        s.close()
+    X = torch.cat(X)
+    Y = torch.cat(Y)
+    trainer = lbmpcd.Sim(configs[0])
+    # the loss of the freshly initialised network (a pass with a vanishing step)
+    first = trainer.closure_train(X, Y, epochs=1, batch=1024, lr=1e-30, seed=7)
+    losses = np.concatenate([trainer.closure_train(X, Y, epochs=60, batch=1024, lr=2e-3),
+                             trainer.closure_train(X, Y, epochs=60, batch=1024, lr=3e-4)])
+    return trainer.closure_weights(), np.concatenate([first, losses]), X.shape[0]
+
+
+@pytest.fixture(scope="module")
+def trained(env):
+    torch, M, lbmpcd = env
+    cfgs = [oneway(g=(g, 0.0, 0.0), tau=tau) for g in (6e-5, 8e-5, 1e-4, 1.2e-4) for tau in (0.7, 0.8, 0.9)]
+    t0 = time.perf_counter()
+    block, losses, n = _train_closure(lbmpcd, torch, cfgs)
+    banner(f"trained on {n} samples in {time.perf_counter() - t0:.1f} s: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    return block, losses
+
+
+def test_training_reduces_the_loss(trained):
+    """Against the freshly initialised network the loss falls well down; what
+    remains is mostly particle noise of the standardised targets (transverse
+    velocities, most stress components), which no network can predict."""
+    _, losses = trained
+    banner(f"loss: initial {losses[0]:.4f}, epochs {np.round(losses[1:], 4)}")
+    assert losses[-1] < losses[0] - 0.05
+    assert losses[-1] <= losses[1]
+
+
+def _profile_u(prof, p):
+    """Streamwise velocity of each LB node row between the buffers (the fine
+    rows of a node pooled): the resolution the network predicts."""
+    r = p["refine"]
+    nsy = p["yhi"] - p["ylo"]
+    prof = np.asarray(prof).reshape(nsy, r, 4).sum(axis=1)
+    rows = range(p["buf_lo"], nsy - p["buf_hi"])
+    return np.array([prof[y, 1] / prof[y, 0] for y in rows])
+
+
+def test_surrogate_matches_plain_mpcd_and_is_faster(env, trained):
+    """Same channel, same LB (one-way coupling): the time-averaged MPCD
+    profile of 2000 plain steps against the surrogate's, within 2% (relative
+    L2 over the LB node rows between the buffers), at a force not trained
+    on; and the surrogate step is faster than the plain one."""
+    torch, M, lbmpcd = env
+    block, _ = trained
+    p = oneway(g=(9e-5, 0.0, 0.0), tau=0.8)
+
+    def run(surrogate, steps):
+        sim = lbmpcd.Sim(p)
+        if surrogate:
+            sim.closure_weights(block)
+            sim.closure_enable(True, tol=0.02, check_every=0)
+        sim.step(300)
+        sim.sample(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        u = _profile_u(sim.profile(), p)
+        if surrogate:
+            assert sim.closure_status()["on"]
+        return u, dt
+
+    up, t_plain = run(False, 2000)
+    us, t_sur = run(True, 400)
+    err = rel_l2(us, up)
+    banner(f"surrogate vs plain profile: rel L2 {err:.4f}; ms/step plain {1e3 * t_plain:.3f} "
+           f"surrogate {1e3 * t_sur:.3f}")
+    assert np.all(np.isfinite(us))
+    assert err <= 0.02
+    assert t_sur < t_plain
+
+
+def test_wrong_surrogate_falls_back(env, trained):
+    """A network whose streamwise output is 3 standard deviations off: the
+    periodic check measures it against plain MPCD and falls back."""
+    torch, M, lbmpcd = env
+    block, _ = trained
+    bad = block.copy()
+    bad[:M.NPARAM] = 0.0
+    bad[M.OFFS[3][1]] = 3.0  # streamwise velocity 3 standard deviations off
+    p = oneway(g=(9e-5, 0.0, 0.0))
+    sim = lbmpcd.Sim(p)
+    sim.step(300)
+    sim.closure_weights(bad)
+    sim.closure_enable(True, tol=0.02, check_every=10, check_steps=40)
+    sim.step(30)
+    st = sim.closure_status()
+    banner(f"fallback: {st}")
+    assert st["fell_back"] and not st["on"]
+    assert st["last_err"] > 0.02
