@@ -152,6 +152,72 @@ def one_by_one(lbmpcd, plist: list, batched_ms: float, sample: int = 16, steps: 
                 speedup=est / batched_ms)
 
 
+def closure_bench(lbmpcd, W, args):
+    """The learned closure against the plain coupled step on the same channel
+    (256x128x128 D3Q19, 16-row slab, 335.5M particles, one-way coupling).
+    Training data come from eight 64x32x32 channels (g log-uniform in
+    [1e-7, 1e-5], tau in [0.6, 1.2]), 2M samples; training runs on the GPU
+    with the library's kernels before the timed region."""
+    import torch
+    t0 = time.perf_counter()
+    X, Y = [], []
+    for q in W.closure_training_channels(8):
+        s = lbmpcd.Sim(q)
+        s.step(100)
+        for _ in range(16):
+            x, y = s.closure_collect(10)
+            X.append(x)
+            Y.append(y)
+        s.close()
+    X = torch.cat(X)
+    Y = torch.cat(Y)
+    n_samples = X.shape[0]
+    t_data = time.perf_counter() - t0
+    trainer = lbmpcd.Sim(W.closure_training_channels(1)[0])
+    t0 = time.perf_counter()
+    losses = trainer.closure_train(X, Y, epochs=2, batch=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    block = trainer.closure_weights()
+    trainer.close()
+    del X, Y
+    torch.cuda.empty_cache()
+
+    p = W.closure_target()
+    sz = W.sizes(p)
+    sim = lbmpcd.Sim(p, device="cuda:0")
+
+    def timed(n):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sim.step(n)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / n
+
+    sim.step(args.warmup)
+    plain = timed(args.steps)
+    sim.closure_weights(block)
+    sim.closure_enable(True, tol=0.02, check_every=0)
+    sim.step(args.warmup)
+    sur = timed(args.steps)
+    out = {
+        "metric": "coupled steps/s: LB MLUPS + MPCD particle-updates/s, % HBM roofline",
+        "value": 1.0 / sur, "unit": "coupled LB steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * sur, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 network (fp32 accumulate) / f32 LB",
+        "data": "synthetic (seeded Poiseuille channels; training data from the coupled method itself)",
+        "config": {"workload": (f"closure: D3Q19 {p['n'][0]}x{p['n'][1]}x{p['n'][2]} FP32, slab "
+                                f"y[{p['ylo']},{p['yhi']}), {sz['particles']} particles replaced by the MLP "
+                                f"271-128-128-128-9"), "lb_nodes": sz["nodes"], "particles": sz["particles"]},
+        "plain_steps_per_s": 1.0 / plain, "plain_ms_per_step": 1e3 * plain,
+        "surrogate_speedup": plain / sur,
+        "lb_mlups": sz["nodes"] / sur / 1e6,
+        "training": {"samples": int(n_samples), "data_s": t_data, "train_s": t_train,
+                     "epoch_loss": [float(x) for x in losses]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def calib_copy():
     """Plain device copy of known size, for scaling the PMC byte counters."""
     import torch
@@ -219,7 +285,7 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="channel_3d",
-                    choices=["channel_3d", "channel_2d", "thin_film_3d", "ensemble"])
+                    choices=["channel_3d", "channel_2d", "thin_film_3d", "ensemble", "closure"])
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with lbmpcd_autotune first (always on for the ensemble)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -239,6 +305,9 @@ def main():
     from paper_2004_00304_amd import lbmpcd
     from paper_2004_00304_amd import workloads as W
 
+    if args.workload == "closure":
+        closure_bench(lbmpcd, W, args)
+        return
     if args.calib_copy:
         calib_copy()
     plist = workload(args.workload)

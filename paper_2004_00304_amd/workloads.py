@@ -142,6 +142,33 @@ def algorithmic_bytes_per_lb_step(p: dict) -> dict:
                 per_node=2 * s["Q"] * lbw, per_particle_update=2 * 2 * p["dim"] * pw)
 
 
+def closure_target(**kw) -> dict:
+    """Channel the learned closure stands in for the MPCD slab of: D3Q19
+    256x128x128 FP32 populations, walls at y = 0 and 128, slab of 16 rows
+    y in [56, 72) with 1-row buffers, r 4, 10 particles per cell
+    (335,544,320 FP32 particles), one-way coupling, exact Poiseuille start."""
+    base = dict(dim=3, n=(256, 128, 128), tau=0.8, g=(1e-6, 0.0, 0.0), ylo=56, yhi=72, buf_lo=1, buf_hi=1,
+                ppc=10, part_fp=32, lb_fp=32, alpha_deg=120.0, feedback=0, init_flow=1, closure=1)
+    base.update(kw)
+    return make(**base)
+
+
+def closure_training_channels(n: int = 8, seed: int = 1) -> list[dict]:
+    """Training channels for the closure: 3D channels 64x32x32 (slab y in
+    [12, 20), r 4, 10 particles per cell, one-way coupling, exact Poiseuille
+    start) with body force log-uniform in [1e-7, 1e-5] and tau uniform in
+    [0.6, 1.2]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        g = float(10.0 ** rng.uniform(-7.0, -5.0))
+        tau = float(rng.uniform(0.6, 1.2))
+        out.append(make(dim=3, n=(64, 32, 32), tau=tau, g=(g, 0.0, 0.0), ylo=12, yhi=20, buf_lo=1, buf_hi=1,
+                        ppc=10, part_fp=32, lb_fp=64, alpha_deg=120.0, feedback=0, init_flow=1, closure=1,
+                        instance=i))
+    return out
+
+
 def ensemble(n_inst: int = 256, seed: int = 1) -> list[dict]:
     """Batched ensemble of independent 2D channels of uneven sizes: width
     W ~ U{16..128}, length L ~ U{32..256}, particles per cell U{5..20}; the
