@@ -49,6 +49,7 @@ struct lbmpcd_ctx {
     size_t lds = 0;
     int cap_max = 0;              // largest tile capacity
     int wg_threads = 0;           // particle kernel workgroup size (0: 256)
+    int xcd_blocked = 1;          // XCD-blocked tile order of the particle kernel
     long long cstride = 0;        // bytes between the component arrays of a particle buffer
     long long t = 0;
     bool pending = false, sampling = false, any_feedback = false;
@@ -197,7 +198,7 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     if (p.closure && !p.mpcd) { msg = "the closure needs the MPCD slab"; return LBMPCD_E_INVALID; }
     if (!p.mpcd) return 0;
     if (p.collision != 0) { msg = "only the SRD collision (0) is implemented"; return LBMPCD_E_UNSUPPORTED; }
-    if (p.wg_threads != 0 && p.wg_threads != 256 && p.wg_threads != 512) { msg = "wg_threads must be 0, 256 or 512"; return LBMPCD_E_INVALID; }
+    if (p.wg_threads != 0 && p.wg_threads != 128 && p.wg_threads != 256 && p.wg_threads != 512) { msg = "wg_threads must be 0, 128, 256 or 512"; return LBMPCD_E_INVALID; }
     if (p.tile_target < 0 || p.tile_target > 8 * WG) { msg = "tile_target out of range"; return LBMPCD_E_INVALID; }
     if (p.closure && p.dim != 3) { msg = "the closure needs dim 3"; return LBMPCD_E_INVALID; }
     if (p.part_fp != 32 && p.part_fp != 64) { msg = "part_fp must be 32 or 64"; return LBMPCD_E_INVALID; }
@@ -396,7 +397,7 @@ int finalize(lbmpcd_ctx* c) {
     L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
     L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts;
     L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
-    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride;
+    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
     HIPCHK(c, launch_particles(L, c->stream));
     c->pending = false;
     return 0;
@@ -617,7 +618,7 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
                 // samples are taken in the last MPCD step of the LB step
                 L.do_fb = (c->any_feedback && sub == c->S - 1) ? 1 : 0;
                 L.do_prof = (c->sampling && sub == c->S - 1) ? 1 : 0;
-                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride;
+                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
                 HIPCHK(c, timed(c, 3, [&] { return launch_particles(L, s); }));
                 c->pcur ^= 1;
                 c->pending = true;
@@ -777,7 +778,7 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
             L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts; L.shifts = c->shifts;
             L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
-            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride;
+            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
             HIPCHK(c, launch_particles(L, s));
             return 0;
         }

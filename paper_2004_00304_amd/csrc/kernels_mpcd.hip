@@ -52,6 +52,8 @@ struct PArgs {
     const double* shifts;
     double* cell_vcm;
     int coll_dt, coll_s, str_s, do_fb, do_prof, diag_inst;
+    long long ntiles;  // tiles of all instances
+    long long xcd_per; // > 0: tiles per XCD of the XCD-blocked order, 0: workgroup b takes tile b
 };
 
 template <typename PT>
@@ -135,7 +137,15 @@ k_particles(PArgs<PT> A) {
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const long long T = blockIdx.x;
+    // Workgroups are dealt to the eight XCDs in turn.  In the XCD-blocked
+    // order the workgroups of one XCD take one contiguous range of tiles, so
+    // the tiles that trade particles are mostly served by one L2, where the
+    // partial lines of their destination runs merge.
+    long long T = blockIdx.x;
+    if (A.xcd_per > 0) {
+        T = (long long)(blockIdx.x % 8) * A.xcd_per + blockIdx.x / 8;
+        if (T >= A.ntiles) return;
+    }
     const long long cs = A.cs;
     const int ii = cptr(A.tile_inst)[T];
     cst<InstDesc>& d = cptr(A.D)[ii];
@@ -327,6 +337,10 @@ k_particles(PArgs<PT> A) {
         __syncthreads();
 
         const double ylo_d = (double)d.ylo, yhi_d = (double)d.yhi;
+        // the slab faces are integers, exact in either precision, so the
+        // face tests compare in the particle precision
+        const PT ylo_p = (PT)d.ylo, yhi_p = (PT)d.yhi;
+        const int bw = d.bot_wall, tw = d.top_wall, ywrap = d.ywrap;
         const int rb_lo = d.buf_lo * d.r, rb_hi = d.R - d.buf_hi * d.r;
         const long long NF = (long long)d.Cx * d.NB * d.Cz;
         const double* uf = A.ufine + d.ufine_off * DIM;
@@ -357,9 +371,9 @@ k_particles(PArgs<PT> A) {
                 r1[q] = fma_t<PT>(vh, dtp, r0[q]);
                 v1[q] = v0[q] + (PT)d.gdt[q];
             }
-            const bool below = (double)r1[1] < ylo_d, above = (double)r1[1] >= yhi_d;
-            if (!d.ywrap && (below || above)) {
-                const int wall = below ? d.bot_wall : d.top_wall;
+            const bool below = r1[1] < ylo_p, above = r1[1] >= yhi_p;
+            if (!ywrap && (below || above)) {
+                const int wall = below ? bw : tw;
                 const double Yw = below ? ylo_d : yhi_d;
                 double q1[3] = {(double)r1[0], (double)r1[1], (double)r1[2]};
                 double w1[3] = {(double)v1[0], (double)v1[1], (double)v1[2]};
@@ -375,7 +389,7 @@ k_particles(PArgs<PT> A) {
                         q1[q] = rc + (vr + 0.5 * d.g[q] * tr) * tr;
                         w1[q] = vr + d.g[q] * tr;
                     }
-                } else if (d.bot_wall || d.top_wall) {
+                } else if (bw || tw) {
                     q1[1] = 2.0 * Yw - q1[1];
                     w1[1] = -w1[1];
                 } else {
@@ -383,9 +397,9 @@ k_particles(PArgs<PT> A) {
                 }
 #pragma unroll
                 for (int q = 0; q < DIM; ++q) { r1[q] = (PT)q1[q]; v1[q] = (PT)w1[q]; }
-                if ((double)r1[1] < ylo_d) r1[1] = (PT)d.ylo;
-                if ((double)r1[1] >= yhi_d) r1[1] = prev_below<PT>((PT)d.yhi, (PT)d.ylo);
-            } else if (d.ywrap) {
+                if (r1[1] < ylo_p) r1[1] = ylo_p;
+                if (r1[1] >= yhi_p) r1[1] = prev_below<PT>(yhi_p, ylo_p);
+            } else if (ywrap) {
                 r1[1] = wrap_periodic<PT>(r1[1], (PT)0, (PT)d.ny);
             }
             r1[0] = wrap_periodic<PT>(r1[0], (PT)0, (PT)d.nx);
@@ -585,8 +599,11 @@ static hipError_t launch_p4(const ParticleLaunch& L, hipStream_t s) {
     a.shifts = L.shifts;
     a.coll_dt = L.coll_dt; a.coll_s = L.coll_s; a.str_s = L.str_s;
     a.do_fb = L.do_fb; a.do_prof = L.do_prof; a.diag_inst = L.diag_inst; a.cell_vcm = L.cell_vcm;
+    a.ntiles = L.tiles;
+    a.xcd_per = L.xcd_blocked ? (L.tiles + 7) / 8 : 0;
+    const long long grid = L.xcd_blocked ? 8 * a.xcd_per : L.tiles;
     auto kern = k_particles<DIM, PT, NT, PPT, MODE>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)L.tiles), dim3(NT), L.lds_bytes, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), L.lds_bytes, s, a);
     return hipGetLastError();
 }
 
@@ -604,6 +621,11 @@ static hipError_t launch_p3(const ParticleLaunch& L, hipStream_t s) {
 // tile capacity.  256 threads unless the caller asks for 512.
 template <int DIM, typename PT>
 static hipError_t launch_p2(const ParticleLaunch& L, hipStream_t s) {
+    if (L.wg_threads == 128) {
+        if (L.cap_max <= 4 * 128) return launch_p3<DIM, PT, 128, 4>(L, s);
+        if (L.cap_max <= 8 * 128) return launch_p3<DIM, PT, 128, 8>(L, s);
+        return hipErrorInvalidValue;
+    }
     if (L.wg_threads == 512) {
         if (L.cap_max <= 2 * 512) return launch_p3<DIM, PT, 512, 2>(L, s);
         if (L.cap_max <= 4 * 512) return launch_p3<DIM, PT, 512, 4>(L, s);

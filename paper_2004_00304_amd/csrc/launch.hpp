@@ -56,6 +56,7 @@ struct ParticleLaunch {
     double* cell_vcm;             // [dim][ncells] or null
     int cap_max;                  // largest tile capacity
     int wg_threads;               // 256 or 512 threads per workgroup (0: 256)
+    int xcd_blocked;              // 1: each XCD's workgroups take a contiguous range of tiles
     long long cstride;            // bytes between component arrays (pos[k] = pos[0] + k cstride, vel[k] = pos[0] + (dim + k) cstride, id after vel)
     size_t lds_bytes;
 };

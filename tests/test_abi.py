@@ -93,7 +93,7 @@ def test_null_context_calls_fail_cleanly(binding):
     L.lbmpcd_destroy(None)
 
 
-@pytest.mark.parametrize("kw", [dict(wg_threads=128), dict(tile_target=-1), dict(tile_target=1 << 20),
+@pytest.mark.parametrize("kw", [dict(wg_threads=64), dict(tile_target=-1), dict(tile_target=1 << 20),
                                 dict(tile=(3, 2, 1))])
 def test_invalid_launch_shape(binding, kw):
     with pytest.raises(binding.LbmpcdError) as e:
