@@ -260,6 +260,8 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
         d.a = q.mpcd ? 1.0 / q.refine : 0.0;
         d.dt = q.mpcd ? 1.0 / q.substeps : 0.0;
         for (int k = 0; k < 3; ++k) { d.gh[k] = 0.5 * q.g[k] * d.dt; d.gdt[k] = q.g[k] * d.dt; }
+        for (int k = 0; k < 3; ++k) { d.ghf[k] = (float)d.gh[k]; d.gdtf[k] = (float)d.gdt[k]; }
+        d.dtf = (float)d.dt;
         d.sd = q.mass > 0 ? std::sqrt(q.kT / q.mass) : 0.0;
         const double alpha = q.alpha_deg * 3.141592653589793 / 180.0;
         d.cos_a = std::cos(alpha);

@@ -53,6 +53,7 @@ struct InstDesc {
     long long prof_off;   // first profile row (NCOPY copies of R rows each)
     // MPCD constants
     double a, dt, gh[3], gdt[3], sd, cos_a, sin_a, mass, kT;
+    float ghf[3], gdtf[3], dtf, padf;  // binary32 roundings of gh, gdt, dt (binary32 particles)
     uint32_t key0, key1;
     int S, pad2;          // MPCD steps per LB step
 };

@@ -344,7 +344,16 @@ k_particles(PArgs<PT> A) {
         const int rb_lo = d.buf_lo * d.r, rb_hi = d.R - d.buf_hi * d.r;
         const long long NF = (long long)d.Cx * d.NB * d.Cz;
         const double* uf = A.ufine + d.ufine_off * DIM;
-        const PT dtp = (PT)d.dt;
+        // per-tile constants in the particle precision (read once, not per particle)
+        PT dtp, ghp[3], gdp[3];
+        if constexpr (sizeof(PT) == 4) {
+            dtp = (PT)d.dtf;
+            for (int q = 0; q < 3; ++q) { ghp[q] = (PT)d.ghf[q]; gdp[q] = (PT)d.gdtf[q]; }
+        } else {
+            dtp = (PT)d.dt;
+            for (int q = 0; q < 3; ++q) { ghp[q] = (PT)d.gh[q]; gdp[q] = (PT)d.gdt[q]; }
+        }
+        const PT nxp = (PT)d.nx, nzp = (PT)d.nz, nyp = (PT)d.ny;
         uint32_t dest[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -367,9 +376,9 @@ k_particles(PArgs<PT> A) {
             PT r1[3] = {r0[0], r0[1], r0[2]}, v1[3] = {v0[0], v0[1], v0[2]};
 #pragma unroll
             for (int q = 0; q < DIM; ++q) {
-                const PT vh = v0[q] + (PT)d.gh[q];
+                const PT vh = v0[q] + ghp[q];
                 r1[q] = fma_t<PT>(vh, dtp, r0[q]);
-                v1[q] = v0[q] + (PT)d.gdt[q];
+                v1[q] = v0[q] + gdp[q];
             }
             const bool below = r1[1] < ylo_p, above = r1[1] >= yhi_p;
             if (!ywrap && (below || above)) {
@@ -400,10 +409,10 @@ k_particles(PArgs<PT> A) {
                 if (r1[1] < ylo_p) r1[1] = ylo_p;
                 if (r1[1] >= yhi_p) r1[1] = prev_below<PT>(yhi_p, ylo_p);
             } else if (ywrap) {
-                r1[1] = wrap_periodic<PT>(r1[1], (PT)0, (PT)d.ny);
+                r1[1] = wrap_periodic<PT>(r1[1], (PT)0, nyp);
             }
-            r1[0] = wrap_periodic<PT>(r1[0], (PT)0, (PT)d.nx);
-            if constexpr (DIM == 3) r1[2] = wrap_periodic<PT>(r1[2], (PT)0, (PT)d.nz);
+            r1[0] = wrap_periodic<PT>(r1[0], (PT)0, nxp);
+            if constexpr (DIM == 3) r1[2] = wrap_periodic<PT>(r1[2], (PT)0, nzp);
 #pragma unroll
             for (int q = 0; q < 3; ++q) { px[k][q] = r1[q]; pv[k][q] = v1[q]; }
 
