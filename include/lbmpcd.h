@@ -118,7 +118,10 @@ typedef struct lbmpcd_params {
 /*
  * Workspace bytes for n_inst channels described by p[0..n_inst-1].  All
  * channels of one context share dim, lb_fp, part_fp, substeps and refine.
- * Returns E_INVALID (with no context, see lbmpcd_strerror) for bad params.
+ * Returns E_INVALID (with no context, see lbmpcd_strerror) for bad params,
+ * among them a channel whose particle slots (tiles x capacity) exceed 4 GiB
+ * per component (about 830M binary32 or 415M binary64 particles at the
+ * default capacity).
  */
 int lbmpcd_workspace_size(const lbmpcd_params* p, int32_t n_inst, size_t* bytes);
 

@@ -171,6 +171,11 @@ int geometry(const lbmpcd_params& p, Geometry& g, std::string& msg) {
     g.nty = (g.CyB + g.Ty - 1) / g.Ty;
     g.ntz = (g.Cz + g.Tz - 1) / g.Tz;
     g.ntiles = (long long)g.ntx * g.nty * g.ntz;
+    // the particle kernels address a channel's slots with 32-bit offsets
+    if (g.ntiles >= (1LL << 31) || g.ntiles * g.cap * (p.part_fp / 8) >= (1LL << 32)) {
+        msg = "the particle slots of one channel exceed 4 GiB per component";
+        return 1;
+    }
     // initial placement: the particles of every slab cell in the tile of that cell
     g.init_per = (long long)g.nct * p.ppc;
     if (g.init_per > g.cap) { msg = "initial placement exceeds the tile capacity"; return 1; }

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fmath.hpp"
+
 namespace lbmpcd {
 
 constexpr int WG = 256;           // threads per workgroup of every kernel
@@ -110,12 +112,12 @@ __device__ __forceinline__ void rng_uniforms4(Key k, uint32_t elem, uint32_t t,
     u[3] = u01(w.z, w.w);
 }
 
-// Box-Muller pair (the exchange step's generator of normal deviates).
+// Box-Muller pair (the exchange step's generator of normal deviates):
+// radius sqrt(-2 ln(1 - u0)), angle 2 pi u1.
 __device__ __forceinline__ void box_muller(double u0, double u1, double& z0, double& z1) {
-    double r = sqrt(-2.0 * log(1.0 - u0));
-    double th = 6.283185307179586 * u1;
+    const double r = sqrt(-2.0 * ln_unit(1.0 - u0));
     double s, c;
-    sincos(th, &s, &c);
+    sincos_2pi(u1, &s, &c);
     z0 = r * c;
     z1 = r * s;
 }

@@ -150,12 +150,18 @@ k_particles(PArgs<PT> A) {
     const int ii = cptr(A.tile_inst)[T];
     cst<InstDesc>& d = cptr(A.D)[ii];
     const Key key = key_of(d);
-    const long long lt = T - d.tile_off;
-    const int tx = (int)(lt % d.ntx);
-    const int ty = (int)((lt / d.ntx) % d.nty);
-    const int tz = (int)(lt / ((long long)d.ntx * d.nty));
+    // tile coordinates in 32-bit arithmetic (a channel has fewer than 2^31 tiles)
+    const uint32_t lt = (uint32_t)(T - d.tile_off);
+    const uint32_t nxy = (uint32_t)d.ntx * (uint32_t)d.nty;
+    const uint32_t tzu = lt / nxy, rem = lt - tzu * nxy;
+    const uint32_t tyu = rem / (uint32_t)d.ntx;
+    const int tx = (int)(rem - tyu * (uint32_t)d.ntx), ty = (int)tyu, tz = (int)tzu;
     const int cap = d.cap;
-    const long long base = d.slot_off + lt * cap;
+    const long long base = d.slot_off + (long long)lt * cap;
+    // A channel's slots span less than 4 GiB per component, so every particle
+    // access is a uniform 64-bit base plus a 32-bit lane offset.
+    const unsigned char* tin = A.in.b + base * (long long)sizeof(PT);
+    const unsigned char* tin_id = A.in.b + 2 * DIM * cs + base * 4;
     uint32_t n = cptr(A.fill_in)[T];
     if (n > (uint32_t)cap) n = (uint32_t)cap;
     const long long t_now = *cptr(A.clock);
@@ -177,11 +183,12 @@ k_particles(PArgs<PT> A) {
         for (int c = 0; c < 3; ++c) { px[k][c] = (PT)0; pv[k][c] = (PT)0; }
         pid[k] = 0;
         if (valid[k]) {
-            pid[k] = A.in.id(DIM, cs)[base + s];
+            const uint32_t o = (uint32_t)s * (uint32_t)sizeof(PT);
+            pid[k] = *(const uint32_t*)(tin_id + (uint32_t)s * 4u);
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
-                px[k][c] = A.in.comp(c, cs)[base + s];
-                pv[k][c] = A.in.comp(DIM + c, cs)[base + s];
+                px[k][c] = *(const PT*)(tin + c * cs + o);
+                pv[k][c] = *(const PT*)(tin + (DIM + c) * cs + o);
             }
         }
     }
@@ -200,10 +207,10 @@ k_particles(PArgs<PT> A) {
                 crot[3 * j] = (w.x & 1u) ? 1.0 : -1.0;
             } else {
                 const double u0 = u01(w.x, w.y), u1 = u01(w.z, w.w);
-                const double nz = 2.0 * u0 - 1.0, phi = 6.283185307179586 * u1;
+                const double nz = 2.0 * u0 - 1.0;  // azimuth 2 pi u1
                 const double sxy = sqrt(fmax(0.0, 1.0 - nz * nz));
                 double sp, cp;
-                sincos(phi, &sp, &cp);
+                sincos_2pi(u1, &sp, &cp);
                 crot[3 * j] = sxy * cp;
                 crot[3 * j + 1] = sxy * sp;
                 crot[3 * j + 2] = nz;
@@ -301,12 +308,13 @@ k_particles(PArgs<PT> A) {
         }
         if constexpr (!STREAM) {
             // collision only: velocities go back to their slots
+            unsigned char* tout = A.out.b + base * (long long)sizeof(PT);
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (!valid[k]) continue;
-                const int s = tid + k * NT;
+                const uint32_t o = (uint32_t)(tid + k * NT) * (uint32_t)sizeof(PT);
 #pragma unroll
-                for (int q = 0; q < DIM; ++q) A.out.comp(DIM + q, cs)[base + s] = pv[k][q];
+                for (int q = 0; q < DIM; ++q) *(PT*)(tout + (DIM + q) * cs + o) = pv[k][q];
             }
             if (tid == 0 && wstat[1]) atomicAdd(&A.stats->misplaced, (unsigned long long)wstat[1]);
             return;
@@ -320,14 +328,16 @@ k_particles(PArgs<PT> A) {
         const PT sh[3] = {(PT)shs[0], (PT)shs[1], (PT)shs[2]};
         // sample windows (node sums for the feedback, fine rows for profiles)
         const int nslab_y = d.yhi - d.ylo;
-        const int wnx = (d.Tx + d.r - 1) / d.r + 2, wny = (d.Ty + d.r - 1) / d.r + 2;
-        const int wnz = (DIM == 3) ? (d.Tz + d.r - 1) / d.r + 2 : 1;
-        const int wx0 = (tx << d.lTx) / d.r - 1, wy0 = (ty << d.lTy) / d.r - 1;
-        const int wz0 = (DIM == 3) ? (tz << d.lTz) / d.r - 1 : 0;
+        // non-negative quotients by r (a shift when r is a power of two)
+        auto divr = [&](int v) { return d.lr >= 0 ? (v >> d.lr) : v / d.r; };
+        const int wnx = divr(d.Tx + d.r - 1) + 2, wny = divr(d.Ty + d.r - 1) + 2;
+        const int wnz = (DIM == 3) ? divr(d.Tz + d.r - 1) + 2 : 1;
+        const int wx0 = divr(tx << d.lTx) - 1, wy0 = divr(ty << d.lTy) - 1;
+        const int wz0 = (DIM == 3) ? divr(tz << d.lTz) - 1 : 0;
         const bool win_ok = wnx * wny * wnz <= MAX_WIN;
         const int wj0 = (ty << d.lTy) - 2, wnj = d.Ty + 4;
         const bool wj_ok = wnj <= MAX_WJ;
-        const int copy = (int)(lt % NCOPY);
+        const int copy = (int)(lt % (uint32_t)NCOPY);
         if (A.do_fb)
             for (int i = tid; i < MAX_WIN * 4; i += NT) wacc[i] = 0.0;
         if (A.do_prof)
@@ -535,29 +545,32 @@ k_particles(PArgs<PT> A) {
             gbase[tid] = c > 0u ? atomicAdd(&A.fill_out[d.tile_off + hkey[tid]], c) : 0u;
         }
         __syncthreads();
+        unsigned char* och = A.out.b + d.slot_off * (long long)sizeof(PT);
+        unsigned char* och_id = A.out.b + 2 * DIM * cs + d.slot_off * 4;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const uint32_t e = pk[k];
             if (e == BAD_SLOT) continue;
-            long long g;
-            if (e == DROP_SLOT) {
-                g = -1;
-            } else if (e & 0x80000000u) {
-                g = d.slot_off + (long long)(e & 0x7FFFFFFFu);
-            } else {
+            uint32_t g = 0u;  // slot within the channel
+            bool ok = e != DROP_SLOT;
+            if (ok && (e & 0x80000000u)) {
+                g = e & 0x7FFFFFFFu;
+            } else if (ok) {
                 const int row = (int)(e >> 24) - 1;
                 const uint32_t r_ = gbase[row] + (e & 0xFFFFFFu);
-                g = r_ < (uint32_t)cap ? d.slot_off + (long long)hkey[row] * cap + r_ : -1;
+                ok = r_ < (uint32_t)cap;
+                g = hkey[row] * (uint32_t)cap + r_;
             }
-            if (g < 0) {
+            if (!ok) {
                 atomicAdd(&A.stats->dropped, 1ull);
                 continue;
             }
-            A.out.id(DIM, cs)[g] = pid[k];
+            const uint32_t o = g * (uint32_t)sizeof(PT);
+            *(uint32_t*)(och_id + g * 4u) = pid[k];
 #pragma unroll
             for (int q = 0; q < DIM; ++q) {
-                A.out.comp(q, cs)[g] = px[k][q];
-                A.out.comp(DIM + q, cs)[g] = pv[k][q];
+                *(PT*)(och + q * cs + o) = px[k][q];
+                *(PT*)(och + (DIM + q) * cs + o) = pv[k][q];
             }
         }
         // ---- sample windows to global memory
