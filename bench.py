@@ -370,7 +370,7 @@ def main():
         "config": {
             "workload": wl, "channels": len(plist),
             "lb_nodes": tot["nodes"], "particles": tot["particles"], "substeps": p["substeps"],
-            "launch_shape": tuning if tuning else "default (tile_target 640, 256 threads)",
+            "launch_shape": tuning if tuning else "default (tile_target 1280, 256 threads)",
         },
         "lb_mlups": tot["nodes"] * sps / 1e6,
         "mpcd_particle_updates_per_s": tot["particles"] * p["substeps"] * sps,

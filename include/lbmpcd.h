@@ -108,7 +108,7 @@ typedef struct lbmpcd_params {
     uint32_t instance;     /* instance number inside the key */
     int32_t tile[3];       /* particle tile in cells per axis (powers of two); 0 = from tile_target */
     double capacity_factor;/* tile capacity / expected occupancy; 0 = default 1.3 */
-    int32_t tile_target;   /* expected particles per tile when tile[] is 0; 0 = default 640 */
+    int32_t tile_target;   /* expected particles per tile when tile[] is 0; 0 = default 1280 */
     int32_t wg_threads;    /* particle kernel workgroup: 128, 256 or 512 threads; 0 = 256.
                               All instances of a context must agree. */
     int32_t closure;       /* 1: reserve the learned closure (lbmpcd_closure_*); needs
@@ -221,7 +221,7 @@ typedef struct lbmpcd_tuning {
     int32_t wg_threads;    /* chosen workgroup size */
     int32_t tried;         /* candidates measured */
     double ms_per_step;    /* ms per coupled LB step of the chosen candidate */
-    double ms_default;     /* ms per coupled LB step of (640, 256), -1 if not measured */
+    double ms_default;     /* ms per coupled LB step of (1280, 256), -1 if not measured */
 } lbmpcd_tuning;
 
 int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, size_t bytes,

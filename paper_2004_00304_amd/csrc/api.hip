@@ -128,8 +128,8 @@ int ilog2(int v) {
 int choose_tile(const lbmpcd_params& p, Geometry& g, std::string& msg) {
     int T[3] = {p.tile[0], p.tile[1], p.tile[2]};
     if (T[0] <= 0 || T[1] <= 0 || (p.dim == 3 && T[2] <= 0)) {
-        // aim at ~640 expected particles per tile
-        const int per_tile = p.tile_target > 0 ? p.tile_target : 640;
+        // aim at ~1280 expected particles per tile
+        const int per_tile = p.tile_target > 0 ? p.tile_target : 1280;
         int target = std::max(8, std::min(MAX_NCT, per_tile / std::max(1, p.ppc)));
         static const int opts3[][3] = {{2, 2, 2}, {4, 2, 2}, {4, 4, 2}, {4, 4, 4}, {4, 4, 8}};
         static const int opts2[][3] = {{4, 2, 1}, {4, 4, 1}, {8, 4, 1}, {8, 8, 1}, {16, 8, 1}};
@@ -138,6 +138,10 @@ int choose_tile(const lbmpcd_params& p, Geometry& g, std::string& msg) {
         for (int i = 0; i < 5; ++i) {
             if (opts[i][0] * opts[i][1] * opts[i][2] >= target) { pick = i; break; }
         }
+        // the next smaller shape when the capacity would exceed the kernel's limit
+        const double cf0 = p.capacity_factor > 0 ? p.capacity_factor : 1.3;
+        while (pick > 0 && std::ceil(cf0 * p.ppc * opts[pick][0] * opts[pick][1] * opts[pick][2]) + 64 > 8 * WG)
+            --pick;
         T[0] = opts[pick][0]; T[1] = opts[pick][1]; T[2] = opts[pick][2];
     }
     if (p.dim == 2) T[2] = 1;
@@ -974,7 +978,7 @@ int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace,
             lbmpcd_destroy(c);
             const double per = (double)ms / lb_steps;
             ++out->tried;
-            if (tt == 640 && wg == 256) out->ms_default = per;
+            if (tt == 1280 && wg == 256) out->ms_default = per;
             if (best < 0 || per < best) {
                 best = per;
                 out->tile_target = tt;

@@ -77,11 +77,10 @@ __device__ __forceinline__ float prev_below<float>(float v, float toward) { retu
 template <>
 __device__ __forceinline__ double prev_below<double>(double v, double toward) { return nextafter(v, toward); }
 
-// Normal deviates of the exchange step, kept out of line: the particle loop
-// is unrolled over the particles a thread holds and one shared copy of the
-// FP64 transcendental code keeps the kernel small.
+// Normal deviates of the exchange step, inlined: a call would make the
+// caller save and restore most of its scalar registers around it.
 template <int DIM>
-__device__ __noinline__ void reinject_normals(Key key, uint32_t id, uint32_t t, uint32_t sub, double* z) {
+__device__ __forceinline__ void reinject_normals(Key key, uint32_t id, uint32_t t, uint32_t sub, double* z) {
     rng_normals<DIM>(key, id, t, sub, P_REINJ, z);
 }
 
