@@ -109,7 +109,8 @@ typedef struct lbmpcd_params {
     int32_t tile[3];       /* particle tile in cells per axis (powers of two); 0 = from tile_target */
     double capacity_factor;/* tile capacity / expected occupancy; 0 = default 1.3 */
     int32_t tile_target;   /* expected particles per tile when tile[] is 0; 0 = default 1280 */
-    int32_t wg_threads;    /* particle kernel workgroup: 128, 256 or 512 threads; 0 = 256.
+    int32_t wg_threads;    /* particle kernel workgroup: 128, 256 or 512 threads; 0 = 256,
+                              or 512 for binary64 particles in tiles of over 1024 slots.
                               All instances of a context must agree. */
     int32_t closure;       /* 1: reserve the learned closure (lbmpcd_closure_*); needs
                               dim 3, mpcd and a single channel */

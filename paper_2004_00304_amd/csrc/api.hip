@@ -48,7 +48,7 @@ struct lbmpcd_ctx {
               total_particles = 0, total_slab = 0;
     size_t lds = 0;
     int cap_max = 0;              // largest tile capacity
-    int wg_threads = 0;           // particle kernel workgroup size (0: 256)
+    int wg_threads = 0;           // particle kernel workgroup size
     int xcd_blocked = 1;          // XCD-blocked tile order of the particle kernel
     long long cstride = 0;        // bytes between the component arrays of a particle buffer
     long long t = 0;
@@ -536,7 +536,9 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
         if (d.feedback) c->any_feedback = true;
     }
     c->cap_max = cap_max;
-    c->wg_threads = p[0].wg_threads;
+    // default workgroup: 256 threads; 512 for binary64 particles in tiles of
+    // more than 1024 slots (four particles per thread instead of eight)
+    c->wg_threads = p[0].wg_threads ? p[0].wg_threads : (c->part_fp == 64 && cap_max > 4 * 256 ? 512 : 256);
     c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max);
 
     // tile -> instance table

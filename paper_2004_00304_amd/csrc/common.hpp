@@ -12,8 +12,8 @@ namespace lbmpcd {
 constexpr int WG = 256;           // threads per workgroup of every kernel
 constexpr int NCOPY = 64;         // replicas of the profile accumulators
 constexpr int MAX_NCT = 128;      // cells per particle tile
-constexpr int MAX_WIN = 64;       // LDS bins of the feedback sample window
-constexpr int MAX_WJ = 64;        // LDS rows of the profile sample window
+constexpr int MAX_WIN = 32;       // LDS bins of the feedback sample window
+constexpr int MAX_WJ = 16;        // LDS rows of the profile sample window
 constexpr uint32_t BAD_SLOT = 0xFFFFFFFFu;
 
 // Purposes of the random streams: the counter of every draw is

@@ -103,7 +103,11 @@ __device__ __forceinline__ void gl_add(double* p, double v) { unsafeAtomicAdd(p,
 constexpr int NHASH_BITS = 6;
 constexpr int NHASH = 1 << NHASH_BITS;
 constexpr size_t LDS_HDR = 1088;  // >= 4 * (4 + 3 * NHASH + 2), a multiple of 16
-constexpr size_t LDS_WIN = (size_t)(MAX_WIN + MAX_WJ) * 4 * sizeof(double);
+// Sample windows hold NREP interleaved replicas of every bin (lane l adds
+// into replica l mod NREP), so that the lanes of a wave, which mostly sample
+// the same one or two nodes, spread their FP64 atomics over more banks.
+constexpr int NREP = 8;
+constexpr size_t LDS_WIN = (size_t)(MAX_WIN + MAX_WJ) * NREP * 4 * sizeof(double);
 constexpr size_t LDS_COLL = (size_t)MAX_NCT * 4 + (size_t)MAX_NCT * 9 * sizeof(double);
 constexpr uint32_t DROP_SLOT = 0x7FFFFFFFu;  // never a slot: the slot total stays below it
 static_assert(4 * (4 + 3 * NHASH + 2) <= (int)LDS_HDR, "LDS header too small");
@@ -126,8 +130,8 @@ k_particles(PArgs<PT> A) {
     uint32_t* hkey = wstat + 4;                 // [NHASH] destination tiles (local index)
     uint32_t* hcnt = hkey + NHASH;              // [NHASH + 1] particles per destination
     uint32_t* gbase = hcnt + NHASH + 1;         // [NHASH + 1] reserved run start
-    double* wacc = (double*)(smem + LDS_HDR);   // [MAX_WIN][4] node sample window
-    double* wprof = wacc + MAX_WIN * 4;         // [MAX_WJ][4] profile window
+    double* wacc = (double*)(smem + LDS_HDR);   // [MAX_WIN][NREP][4] node sample window
+    double* wprof = wacc + MAX_WIN * NREP * 4;  // [MAX_WJ][NREP][4] profile window
     unsigned char* uni = smem + LDS_HDR + LDS_WIN;
     uint32_t* ccnt = (uint32_t*)uni;                 // [MAX_NCT]
     double* csv = (double*)(uni + MAX_NCT * 4);      // [MAX_NCT][3]
@@ -337,10 +341,11 @@ k_particles(PArgs<PT> A) {
         const int wj0 = (ty << d.lTy) - 2, wnj = d.Ty + 4;
         const bool wj_ok = wnj <= MAX_WJ;
         const int copy = (int)(lt % (uint32_t)NCOPY);
-        if (A.do_fb)
-            for (int i = tid; i < MAX_WIN * 4; i += NT) wacc[i] = 0.0;
-        if (A.do_prof)
-            for (int i = tid; i < MAX_WJ * 4; i += NT) wprof[i] = 0.0;
+        if (A.do_fb && win_ok)
+            for (int i = tid; i < wnx * wny * wnz * NREP * 4; i += NT) wacc[i] = 0.0;
+        if (A.do_prof && wj_ok)
+            for (int i = tid; i < wnj * NREP * 4; i += NT) wprof[i] = 0.0;
+        const int wrep = 4 * (lane & (NREP - 1));
         for (int i = tid; i < NHASH; i += NT) hkey[i] = BAD_SLOT;
         for (int i = tid; i <= NHASH; i += NT) hcnt[i] = 0u;
         __syncthreads();
@@ -365,10 +370,11 @@ k_particles(PArgs<PT> A) {
         const PT nxp = (PT)d.nx, nzp = (PT)d.nz, nyp = (PT)d.ny;
         uint32_t dest[PPT];
 #pragma unroll
+        for (int k = 0; k < PPT; ++k) dest[k] = BAD_SLOT;
+        // exchange step: redraw buffer particles about the LB velocity
+#pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            dest[k] = BAD_SLOT;
             if (!valid[k]) continue;
-            // exchange step: redraw buffer particles about the LB velocity
             const int J0 = clampi((int)floor(((double)px[k][1] - ylo_d) * (double)d.r), 0, d.R - 1);
             if (J0 < rb_lo || J0 >= rb_hi) {
                 const int I = clampi((int)floor((double)px[k][0] * (double)d.r), 0, d.Cx - 1);
@@ -380,7 +386,12 @@ k_particles(PArgs<PT> A) {
 #pragma unroll
                 for (int q = 0; q < DIM; ++q) pv[k][q] = (PT)(uf[q * NF + fc] + d.sd * z[q]);
             }
-            // streaming, Eq. 3, with the body force as constant acceleration
+        }
+
+        // streaming, Eq. 3, with the body force as constant acceleration
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (!valid[k]) continue;
             PT r0[3] = {px[k][0], px[k][1], px[k][2]}, v0[3] = {pv[k][0], pv[k][1], pv[k][2]};
             PT r1[3] = {r0[0], r0[1], r0[2]}, v1[3] = {v0[0], v0[1], v0[2]};
 #pragma unroll
@@ -424,9 +435,15 @@ k_particles(PArgs<PT> A) {
             if constexpr (DIM == 3) r1[2] = wrap_periodic<PT>(r1[2], (PT)0, nzp);
 #pragma unroll
             for (int q = 0; q < 3; ++q) { px[k][q] = r1[q]; pv[k][q] = v1[q]; }
+        }
 
-            // samples right after streaming (last MPCD step of an LB step)
-            if (A.do_fb | A.do_prof) {
+        // samples right after streaming (last MPCD step of an LB step); the
+        // loops over a thread's particles are split by task so that fewer
+        // per-tile constants are live at once
+        if (A.do_fb | A.do_prof) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if (!valid[k]) continue;
                 const int J = clampi((int)floor(((double)px[k][1] - ylo_d) * (double)d.r), 0, d.R - 1);
                 double vals[4] = {1.0, (double)pv[k][0], (double)pv[k][1], DIM == 3 ? (double)pv[k][2] : 0.0};
                 if (A.do_fb) {
@@ -438,7 +455,7 @@ k_particles(PArgs<PT> A) {
                     int az = izn - wz0;
                     if (DIM == 3) { if (az < 0) az += d.nz; else if (az >= d.nz) az -= d.nz; }
                     if (win_ok && ax < wnx && ay >= 0 && ay < wny && az < wnz) {
-                        double* wb = wacc + 4 * (ax + wnx * (ay + wny * az));
+                        double* wb = wacc + 4 * NREP * (ax + wnx * (ay + wny * az)) + wrep;
 #pragma unroll
                         for (int q = 0; q < DIM + 1; ++q) lds_add(&wb[q], vals[q]);
                     } else {
@@ -452,7 +469,7 @@ k_particles(PArgs<PT> A) {
                     const int aj = J - wj0;
                     if (wj_ok && aj >= 0 && aj < wnj) {
 #pragma unroll
-                        for (int q = 0; q < DIM + 1; ++q) lds_add(&wprof[4 * aj + q], vals[q]);
+                        for (int q = 0; q < DIM + 1; ++q) lds_add(&wprof[4 * NREP * aj + wrep + q], vals[q]);
                     } else {
                         double* gb = A.prof + (d.prof_off + (long long)copy * d.R + J) * 4;
 #pragma unroll
@@ -460,8 +477,12 @@ k_particles(PArgs<PT> A) {
                     }
                 }
             }
+        }
 
-            // binning into the shifted grid of this MPCD step
+        // binning into the shifted grid of this MPCD step
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (!valid[k]) continue;
             int ix = bin_coord<PT>(px[k][0], (PT)0, sh[0], rr);
             if (ix >= d.Cx) ix -= d.Cx;
             int iy = bin_coord<PT>(px[k][1], (PT)d.ylo, sh[1], rr);
@@ -575,8 +596,12 @@ k_particles(PArgs<PT> A) {
         // ---- sample windows to global memory
         if (A.do_fb && win_ok) {
             for (int i = tid; i < wnx * wny * wnz; i += NT) {
-                const double cnt = wacc[4 * i];
-                if (cnt == 0.0) continue;
+                double sum[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < NREP; ++r)
+#pragma unroll
+                    for (int q = 0; q < DIM + 1; ++q) sum[q] += wacc[4 * (NREP * i + r) + q];
+                if (sum[0] == 0.0) continue;
                 const int ax = i % wnx, ay = (i / wnx) % wny, az = i / (wnx * wny);
                 int ixn = wx0 + ax; if (ixn < 0) ixn += d.nx; else if (ixn >= d.nx) ixn -= d.nx;
                 const int iyn = wy0 + ay;
@@ -586,17 +611,21 @@ k_particles(PArgs<PT> A) {
                 const long long sidx = ((long long)izn * nslab_y + iyn) * d.nx + ixn;
                 double* gb = A.acc + (d.acc_off + sidx) * 4;
 #pragma unroll
-                for (int q = 0; q < DIM + 1; ++q) gl_add(&gb[q], wacc[4 * i + q]);
+                for (int q = 0; q < DIM + 1; ++q) gl_add(&gb[q], sum[q]);
             }
         }
         if (A.do_prof && wj_ok) {
             for (int i = tid; i < wnj; i += NT) {
-                const double cnt = wprof[4 * i];
-                if (cnt == 0.0) continue;
+                double sum[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < NREP; ++r)
+#pragma unroll
+                    for (int q = 0; q < DIM + 1; ++q) sum[q] += wprof[4 * (NREP * i + r) + q];
+                if (sum[0] == 0.0) continue;
                 const int J = wj0 + i;
                 double* gb = A.prof + (d.prof_off + (long long)copy * d.R + J) * 4;
 #pragma unroll
-                for (int q = 0; q < DIM + 1; ++q) gl_add(&gb[q], wprof[4 * i + q]);
+                for (int q = 0; q < DIM + 1; ++q) gl_add(&gb[q], sum[q]);
             }
         }
         if (tid == 0) {
