@@ -253,15 +253,16 @@ def pmc_summary(fetch_csv: str, write_csv: str, command: str) -> None:
     gib_kib = float(1 << 20)
     fscale = gib_kib / max(copy_f)  # the copy reads 1 GiB
     wscale = gib_kib / max(copy_w)  # and writes 1 GiB
-    fused = lambda d: [v for k, vs in d.items() if "k_particles" in k and k.rstrip(")").rstrip().endswith(
-        "3>(lbmpcd::PArgs<float>") or ("k_particles" in k and ", 3>" in k) for v in vs]
+    is_fused = lambda k: "k_particles" in k and ", 3>" in k
+    fused = lambda d: [v for k, vs in d.items() if is_fused(k) for v in vs]
     pf, pw = fused(f), fused(w)
+    names = sorted({k.split("(")[0].replace("void ", "").replace("lbmpcd::", "") for k in f if is_fused(k)})
     fetch_b = sum(pf) / len(pf) * 1024 * fscale
     write_b = sum(pw) / len(pw) * 1024 * wscale
     p = W.channel_3d()
     alg = W.algorithmic_bytes_per_lb_step(p)["per_particle_update"] * W.sizes(p)["particles"]
     out = {
-        "kernel": "k_particles<3, float, 256, 4, 3> (fused MPCD step), channel_3d",
+        "kernel": f"{', '.join(names)} (fused MPCD step), channel_3d",
         "kernel_hash": kernel_hash(),
         "command": command,
         "dispatches": len(pf),
@@ -288,6 +289,8 @@ def main():
                     choices=["channel_3d", "channel_2d", "thin_film_3d", "ensemble", "closure"])
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with lbmpcd_autotune first (always on for the ensemble)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shape for the ensemble too")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -315,7 +318,7 @@ def main():
     tot = totals(plist)
     torch.cuda.set_device(0)
     tuning = None
-    if args.autotune or args.workload == "ensemble":
+    if args.autotune or (args.workload == "ensemble" and not args.no_autotune):
         tuning = lbmpcd.autotune(plist, lb_steps=5)
         plist = lbmpcd.with_tuning(plist, tuning)
         print(f"[bench] autotune: {tuning}", file=sys.stderr, flush=True)
