@@ -1048,7 +1048,7 @@ int lbmpcd_closure_collect(lbmpcd_ctx* c, int32_t lb_steps, float* X, float* Y) 
         if (c->sampling) c->sampled_steps++;
         // the samples are taken from the collided state
         if (int e2 = finalize(c)) return e2;
-        HIPCHK(c, closure_node_moments(c->part_fp, c->d_desc, 0, d.ntiles * (long long)d.cap, c->part[c->pcur].pos[0],
+        HIPCHK(c, closure_node_moments(c->part_fp, c->d_desc, 0, d.ntiles, c->part[c->pcur].pos[0],
                                        c->cstride, c->fill[c->pcur], c->cl_nm, c->stream));
     }
     HIPCHK(c, closure_collect_finish(c->cl_nslab, lb_steps, d.mass, c->cl_facc, c->cl_nm, X, Y, c->stream));

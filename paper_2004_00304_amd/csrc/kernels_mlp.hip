@@ -541,40 +541,82 @@ hipError_t closure_to_acc(const InstDesc* D, int inst, long long nslab, const fl
     return hipGetLastError();
 }
 
-// One thread per particle slot of the channel: count, sum v, sum v v of the
-// particle's LB node (all particles of the slab lie in slab nodes).
+// One workgroup per particle tile: count, sum v and sum v v of every
+// particle's LB node (all particles of the slab lie in slab nodes).  A tile
+// of the shifted grid covers few nodes, so the sums go through an LDS window
+// of those nodes (NMREP interleaved replicas of each, lane l adding into
+// replica l mod NMREP) and reach memory with one global atomic per node and
+// moment; a particle outside the window adds to memory directly.
+constexpr int NM_WIN = 32;  // nodes of the LDS window
+constexpr int NMREP = 4;
+
 template <typename PT>
 __global__ void __launch_bounds__(256) k_node_moments(const InstDesc* __restrict__ D, int inst,
                                                       const unsigned char* pos0, long long cs,
                                                       const uint32_t* fill, double* nm) {
+    __shared__ double win[NM_WIN * NMREP * 10];
     const InstDesc& d = D[inst];
-    const long long sl = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (sl >= d.ntiles * d.cap) return;
-    const long long T = sl / d.cap;
-    const int k = (int)(sl % d.cap);
-    if ((uint32_t)k >= fill[d.tile_off + T]) return;
-    const long long g = d.slot_off + sl;
+    const uint32_t T = blockIdx.x;  // tile within the channel
+    const uint32_t nxy = (uint32_t)d.ntx * (uint32_t)d.nty;
+    const int tz = (int)(T / nxy), rem = (int)(T - (uint32_t)tz * nxy);
+    const int ty = rem / d.ntx, tx = rem - ty * d.ntx;
+    const int r = d.r, nsy = d.yhi - d.ylo;
+    // nodes that particles binned in this tile can occupy (one cell of margin per side)
+    const int wx0 = (tx * d.Tx) / r - 1, wy0 = (ty * d.Ty) / r - 1, wz0 = (tz * d.Tz) / r - 1;
+    const int wnx = (d.Tx + r - 1) / r + 2, wny = (d.Ty + r - 1) / r + 2, wnz = (d.Tz + r - 1) / r + 2;
+    const bool win_ok = wnx * wny * wnz <= NM_WIN;
+    const int nwin = win_ok ? wnx * wny * wnz : 0;
+    for (int i = threadIdx.x; i < nwin * NMREP * 10; i += 256) win[i] = 0.0;
+    __syncthreads();
+    const uint32_t n = min(fill[d.tile_off + T], (uint32_t)d.cap);
     const PT* c[6];
-    for (int q = 0; q < 6; ++q) c[q] = (const PT*)(pos0 + q * cs);
-    const int x = min(max((int)floor((double)c[0][g]), 0), d.nx - 1);
-    const int y = min(max((int)floor((double)c[1][g]), d.ylo), d.yhi - 1);
-    const int z = min(max((int)floor((double)c[2][g]), 0), d.nz - 1);
-    const double v[3] = {(double)c[3][g], (double)c[4][g], (double)c[5][g]};
-    const long long sn = ((long long)z * (d.yhi - d.ylo) + (y - d.ylo)) * d.nx + x;
-    double* o = nm + sn * 10;
-    atomicAdd(&o[0], 1.0);
-    for (int a = 0; a < 3; ++a) atomicAdd(&o[1 + a], v[a]);
+    for (int q = 0; q < 6; ++q) c[q] = (const PT*)(pos0 + q * cs) + d.slot_off + (long long)T * d.cap;
     const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
-    for (int q = 0; q < 6; ++q) atomicAdd(&o[4 + q], v[A[q]] * v[B[q]]);
+    const int rep = (threadIdx.x & 63) & (NMREP - 1);
+    for (uint32_t k = threadIdx.x; k < n; k += 256) {
+        const int x = min(max((int)floor((double)c[0][k]), 0), d.nx - 1);
+        const int y = min(max((int)floor((double)c[1][k]), d.ylo), d.yhi - 1);
+        const int z = min(max((int)floor((double)c[2][k]), 0), d.nz - 1);
+        const double v[3] = {(double)c[3][k], (double)c[4][k], (double)c[5][k]};
+        double m[10];
+        m[0] = 1.0;
+        for (int a = 0; a < 3; ++a) m[1 + a] = v[a];
+        for (int q = 0; q < 6; ++q) m[4 + q] = v[A[q]] * v[B[q]];
+        int ax = x - wx0; if (ax < 0) ax += d.nx; else if (ax >= d.nx) ax -= d.nx;
+        int az = z - wz0; if (az < 0) az += d.nz; else if (az >= d.nz) az -= d.nz;
+        const int ay = (y - d.ylo) - wy0;
+        double* o;
+        if (win_ok && ax < wnx && ay >= 0 && ay < wny && az < wnz)
+            o = win + 10 * (NMREP * (ax + wnx * (ay + wny * az)) + rep);
+        else
+            o = nm + (((long long)z * nsy + (y - d.ylo)) * d.nx + x) * 10;
+        for (int q = 0; q < 10; ++q) atomicAdd(&o[q], m[q]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nwin * 10; i += 256) {
+        const int w = i / 10, q = i - 10 * w;
+        double sum = 0.0, cnt = 0.0;
+        for (int rr = 0; rr < NMREP; ++rr) {
+            sum += win[10 * (NMREP * w + rr) + q];
+            cnt += win[10 * (NMREP * w + rr)];
+        }
+        if (cnt == 0.0) continue;  // no particle in this node
+        const int ax = w % wnx, ay = (w / wnx) % wny, az = w / (wnx * wny);
+        int x = wx0 + ax; if (x < 0) x += d.nx; else if (x >= d.nx) x -= d.nx;
+        int z = wz0 + az; if (z < 0) z += d.nz; else if (z >= d.nz) z -= d.nz;
+        const int yl = wy0 + ay;
+        if (yl < 0 || yl >= nsy) continue;
+        atomicAdd(&nm[(((long long)z * nsy + yl) * d.nx + x) * 10 + q], sum);
+    }
 }
 
-hipError_t closure_node_moments(int part_fp, const InstDesc* D, int inst, long long nslots, const void* pos0,
+hipError_t closure_node_moments(int part_fp, const InstDesc* D, int inst, long long ntiles, const void* pos0,
                                 long long cstride, const uint32_t* fill, double* nm, hipStream_t s) {
     if (part_fp == 64)
-        hipLaunchKernelGGL(k_node_moments<double>, dim3(nblk(nslots)), dim3(256), 0, s, D, inst,
+        hipLaunchKernelGGL(k_node_moments<double>, dim3((unsigned)ntiles), dim3(256), 0, s, D, inst,
                            (const unsigned char*)pos0, cstride, fill, nm);
     else
-        hipLaunchKernelGGL(k_node_moments<float>, dim3(nblk(nslots)), dim3(256), 0, s, D, inst,
+        hipLaunchKernelGGL(k_node_moments<float>, dim3((unsigned)ntiles), dim3(256), 0, s, D, inst,
                            (const unsigned char*)pos0, cstride, fill, nm);
     return hipGetLastError();
 }

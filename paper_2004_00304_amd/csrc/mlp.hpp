@@ -95,8 +95,9 @@ hipError_t closure_features(int lb_fp, const InstDesc* D, int inst, long long ns
 // node; with do_prof also into the profile accumulators.
 hipError_t closure_to_acc(const InstDesc* D, int inst, long long nslab, const float* Y, const float* stats,
                           const float* uc, double* acc, double* prof, int do_prof, hipStream_t s);
-// Particle moments per slab node (count, sum v, sum v v) of one channel.
-hipError_t closure_node_moments(int part_fp, const InstDesc* D, int inst, long long nslots, const void* pos0,
+// Particle moments per slab node (count, sum v, sum v v) of one channel;
+// one workgroup per particle tile.
+hipError_t closure_node_moments(int part_fp, const InstDesc* D, int inst, long long ntiles, const void* pos0,
                                 long long cstride, const uint32_t* fill, double* nm, hipStream_t s);
 // Averages of a collection window of K LB steps: features X [nslab][NF] and
 // targets Y [nslab][NOUT] (mean velocity, kinetic stress per unit volume).
