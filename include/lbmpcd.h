@@ -296,6 +296,14 @@ int lbmpcd_closure_features(struct lbmpcd_ctx* c, float* X);
 int lbmpcd_closure_forward(struct lbmpcd_ctx* c, const float* X, int64_t n, float* Y, void* scratch,
                            size_t scratch_bytes);
 
+/* Network output in physical units for every slab node of the current
+ * populations (device Y, nslab x 9, slab nodes x fastest, then y - ylo, then
+ * z), computed by the fused inference kernel that the surrogate step uses:
+ * band moments, features and the four layers in two launches.  Equal to
+ * lbmpcd_closure_forward on lbmpcd_closure_features' output.  Asynchronous;
+ * E_STATE before the parameters are set. */
+int lbmpcd_closure_predict(struct lbmpcd_ctx* c, float* Y);
+
 /* get_or_set 0: copy the parameter block out (host); 1: load it (resets Adam). Synchronises. */
 int lbmpcd_closure_weights(struct lbmpcd_ctx* c, int32_t get_or_set, float* buf, size_t bytes);
 

@@ -578,6 +578,16 @@ namespace {
 
 // Enqueue one coupled LB step on stream s (the context's stream, or the
 // capture stream while a graph is recorded).
+// The network's standardised output (cl_inf.Y) and the nodes' LB velocities
+// (cl_uc) for the current populations, by the fused inference kernel.  The
+// band moments it needs overlay the feature buffer of the separate products.
+static hipError_t closure_predict_now(lbmpcd_ctx* c, hipStream_t s) {
+    const InstDesc& d = c->desc[0];
+    const long long nband = (long long)d.nx * d.nyb * d.nz;
+    return closure_predict(c->lb_fp, c->d_desc, 0, c->cl_nslab, nband, d.by0, d.nyb, c->f[c->fcur],
+                           (double*)c->cl_inf.X, c->cl_stats, c->cl_Pb, c->cl_P, c->cl_inf.Y, c->cl_uc, s);
+}
+
 int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
     {
         HIPCHK(c, timed(c, 0, [&] {
@@ -590,9 +600,7 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
             // for the MPCD samples -- in the profile, and with feedback in
             // the projection onto the LB equilibria
             HIPCHK(c, timed(c, 4, [&] {
-                       hipError_t e = closure_features(c->lb_fp, c->d_desc, 0, c->cl_nslab, c->f[c->fcur], nullptr,
-                                                       c->cl_stats, c->cl_inf.X, c->cl_uc, s);
-                       if (e == hipSuccess) e = mlp_forward(c->cl_P, c->cl_Pb, c->cl_inf, s);
+                       hipError_t e = closure_predict_now(c, s);
                        if (e == hipSuccess)
                            e = closure_to_acc(c->d_desc, 0, c->cl_nslab, c->cl_inf.Y, c->cl_stats, c->cl_uc, c->acc,
                                               c->prof, c->sampling ? 1 : 0, s);
@@ -1140,6 +1148,15 @@ int lbmpcd_closure_forward(lbmpcd_ctx* c, const float* X, int64_t n, float* Y, v
     return 0;
 }
 
+int lbmpcd_closure_predict(lbmpcd_ctx* c, float* Y) {
+    if (int e = need_closure(c)) return e;
+    if (!c->cl_ready) return fail(c, LBMPCD_E_STATE, "closure parameters are not set");
+    if (!Y) return fail(c, LBMPCD_E_INVALID, "Y is null");
+    HIPCHK(c, closure_predict_now(c, c->stream));
+    HIPCHK(c, mlp_destandardize_uc(c->cl_inf.Y, c->cl_stats, c->cl_uc, c->cl_nslab, Y, c->stream));
+    return 0;
+}
+
 int lbmpcd_closure_weights(lbmpcd_ctx* c, int32_t get_or_set, float* buf, size_t bytes) {
     if (int e = need_closure(c)) return e;
     const size_t need = sizeof(float) * (size_t)(NPARAM + NSTATS);
@@ -1198,9 +1215,7 @@ int lbmpcd_closure_check(lbmpcd_ctx* c, int32_t burst_steps, double* rel_err) {
     if (int e = lbmpcd_moments(c, LBMPCD_PROFILE, 0, pm.data(), pm.size() * 8, 0)) return e;
     // the surrogate's profile of the current state
     HIPCHK(c, launch_zero(c->prof, c->prof_bytes, c->stream));
-    HIPCHK(c, closure_features(c->lb_fp, c->d_desc, 0, c->cl_nslab, c->f[c->fcur], nullptr, c->cl_stats,
-                               c->cl_inf.X, c->cl_uc, c->stream));
-    HIPCHK(c, mlp_forward(c->cl_P, c->cl_Pb, c->cl_inf, c->stream));
+    HIPCHK(c, closure_predict_now(c, c->stream));
     // written into the sample sums and profile; the sums are cleared again below
     HIPCHK(c, closure_to_acc(c->d_desc, 0, c->cl_nslab, c->cl_inf.Y, c->cl_stats, c->cl_uc, c->acc, c->prof, 1,
                              c->stream));

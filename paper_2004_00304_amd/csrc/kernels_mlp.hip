@@ -541,6 +541,188 @@ hipError_t closure_to_acc(const InstDesc* D, int inst, long long nslab, const fl
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// fused inference: features and the four layers in one kernel
+// ---------------------------------------------------------------------------
+constexpr int BMS = 12;  // doubles per band node: 10 moments, shear rate, pad
+
+// The 10 moments and the shear rate of every node of the rows [y0, y0 + nyb)
+// that the slab's 3x3x3 stencils reach, computed exactly as the per-node
+// feature kernel computes them.
+template <typename LT>
+__global__ void __launch_bounds__(256) k_band_moments(const InstDesc* __restrict__ D, int inst,
+                                                      const LT* __restrict__ f, int y0, int nyb, double* M) {
+    const InstDesc& d = D[inst];
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (long long)d.nx * nyb * d.nz) return;
+    const int x = (int)(i % d.nx), yb = (int)((i / d.nx) % nyb), z = (int)(i / ((long long)d.nx * nyb));
+    const long long n = ((long long)z * d.ny + (y0 + yb)) * d.nx + x;
+    double m[10];
+    node_moments<LT>(f + d.node_off * Lat<3>::Q, d.N, n, d.g, m);
+    const double rho = m[0], u[3] = {m[1], m[2], m[3]};
+    const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+    double ss = 0.0;
+    for (int q = 0; q < 6; ++q) {
+        const double Sab = -(m[4 + q] - rho * u[A[q]] * u[B[q]]) / (2.0 * rho * (1.0 / 3.0) * d.tau);
+        ss += (q < 3 ? 1.0 : 2.0) * Sab * Sab;
+    }
+    double* o = M + i * BMS;
+    for (int q = 0; q < 10; ++q) o[q] = m[q];
+    o[10] = sqrt(2.0 * ss);
+    o[11] = 0.0;
+}
+
+// One workgroup of four waves per block of 128 slab nodes, 32 per wave.  The
+// workgroup writes the block's standardised BF16 features into LDS; each
+// wave then runs its 32 rows through the four layers on the matrix cores
+// (v_mfma_f32_32x32x8_bf16, the k steps in the same order as the separate
+// products, so the results are the same), the hidden activations going back
+// into the wave's own rows of the LDS block between layers.  Weights are
+// read from memory (they stay in the caches).  Outputs: the standardised
+// network output Y and the centre node's LB velocity uc.
+constexpr int FR = 128;        // rows per workgroup
+constexpr int XPITCH = NFP + 4;  // LDS row pitch of the feature block (BF16 elements)
+constexpr int HPITCH = NH + 4;   // LDS row pitch of a hidden block
+
+__device__ __forceinline__ void mfma_layer(const uint16_t* act, int pitch, int K, const uint16_t* W, int ncol_blocks,
+                                           int nvalid, f32x16 acc[4]) {
+    const int lane = threadIdx.x & 63, lr = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
+    for (int k0 = 0; k0 < K; k0 += 8) {
+        const int kc = k0 + 4 * h;
+        // four consecutive BF16 values as one 8-byte load (rows and weight
+        // blocks start at multiples of 8 bytes)
+        const bf16x4 a = __builtin_bit_cast(bf16x4, *(const uint2*)(act + lr * pitch + kc));
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            if (nb >= ncol_blocks) break;
+            const int n = nb * 32 + lr;
+            const uint2 bw = n < nvalid ? *(const uint2*)(W + (long long)n * K + kc) : make_uint2(0u, 0u);
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, __builtin_bit_cast(bf16x4, bw), acc[nb], 0, 0, 0);
+        }
+    }
+}
+
+// bias, GELU, BF16 into the wave's rows (C layout: lane holds column lane & 31
+// of each 32-column block, rows 8 (r / 4) + 4 (lane / 32) + r % 4)
+__device__ __forceinline__ void hidden_out(const f32x16 acc[4], const float* bias, uint16_t* act) {
+    const int lane = threadIdx.x & 63, lr = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int col = nb * 32 + lr;
+        const float bc = bias[col];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+            act[row * HPITCH + col] = to_bf16(gelu(acc[nb][r] + bc));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mlp_fused(const InstDesc* __restrict__ D, int inst, long long nslab, int y0,
+                                                   int nyb, const double* __restrict__ M, const float* __restrict__ st,
+                                                   const uint16_t* __restrict__ Pb, const float* __restrict__ P32,
+                                                   float* Y, float* uc) {
+    __shared__ uint16_t xs[FR * XPITCH];
+    const InstDesc& d = D[inst];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long r0 = (long long)blockIdx.x * FR;
+    const int nsy = d.yhi - d.ylo;
+    auto band_index = [&](long long sn, int dx, int dy, int dz) {
+        const int x = (int)(sn % d.nx), y = d.ylo + (int)((sn / d.nx) % nsy), z = (int)(sn / ((long long)d.nx * nsy));
+        int xx = x + dx; if (xx < 0) xx += d.nx; else if (xx >= d.nx) xx -= d.nx;
+        int zz = z + dz; if (zz < 0) zz += d.nz; else if (zz >= d.nz) zz -= d.nz;
+        int yy = y + dy; yy = yy < 0 ? 0 : (yy >= d.ny ? d.ny - 1 : yy);
+        return ((long long)zz * nyb + (yy - y0)) * d.nx + xx;
+    };
+    // standardised features of the block: stencil entry s of row r (lanes of
+    // a wave take consecutive rows of one stencil entry)
+    for (int it = tid; it < FR * 27; it += 256) {
+        const int r = it % FR, s = it / FR;
+        const long long sn = r0 + r;
+        uint16_t* xr = xs + r * XPITCH + s * 10;
+        if (sn >= nslab) {
+            for (int q = 0; q < 10; ++q) xr[q] = 0;
+            continue;
+        }
+        const double* m = M + band_index(sn, s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1) * BMS;
+        for (int q = 0; q < 10; ++q) {
+            const int k = s * 10 + q;
+            xr[q] = to_bf16(((float)m[q] - st[k]) / st[NF + k]);
+        }
+    }
+    for (int r = tid; r < FR; r += 256) {
+        const long long sn = r0 + r;
+        uint16_t* xr = xs + r * XPITCH;
+        for (int q = NF - 1; q < NFP; ++q) xr[q] = 0;
+        if (sn >= nslab) continue;
+        const double* m = M + band_index(sn, 0, 0, 0) * BMS;
+        xr[NF - 1] = to_bf16(((float)m[10] - st[NF - 1]) / st[2 * NF - 1]);
+        for (int a = 0; a < 3; ++a) uc[sn * 3 + a] = (float)m[1 + a];
+    }
+    __syncthreads();
+
+    uint16_t* own = xs + wave * 32 * XPITCH;  // this wave's rows; hidden blocks reuse them
+    f32x16 acc[4];
+    mfma_layer(own, XPITCH, NFP, Pb + OFF_W1, 4, NH, acc);
+    __syncthreads();
+    hidden_out(acc, P32 + OFF_B1, own);
+    __syncthreads();
+    mfma_layer(own, HPITCH, NH, Pb + OFF_W2, 4, NH, acc);
+    __syncthreads();
+    hidden_out(acc, P32 + OFF_B2, own);
+    __syncthreads();
+    mfma_layer(own, HPITCH, NH, Pb + OFF_W3, 4, NH, acc);
+    __syncthreads();
+    hidden_out(acc, P32 + OFF_B3, own);
+    __syncthreads();
+    mfma_layer(own, HPITCH, NH, Pb + OFF_W4, 1, NOUT, acc);
+    const int lr = lane & 31, h = lane >> 5;
+    if (lr < NOUT) {
+        const float bc = P32[OFF_B4 + lr];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const long long sn = r0 + wave * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (sn < nslab) Y[sn * NOUT + lr] = acc[0][r] + bc;
+        }
+    }
+}
+static_assert(FR == 4 * 32, "four waves of 32 rows");
+
+hipError_t closure_predict(int lb_fp, const InstDesc* D, int inst, long long nslab, long long nband, int y0,
+                           int nyb, const void* f, double* M, const float* stats, const uint16_t* Pb,
+                           const float* P32, float* Y, float* uc, hipStream_t s) {
+    if (lb_fp == 64)
+        hipLaunchKernelGGL(k_band_moments<double>, dim3(nblk(nband)), dim3(256), 0, s, D, inst, (const double*)f,
+                           y0, nyb, M);
+    else
+        hipLaunchKernelGGL(k_band_moments<float>, dim3(nblk(nband)), dim3(256), 0, s, D, inst, (const float*)f,
+                           y0, nyb, M);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_fused, dim3(nblk(nslab, FR)), dim3(256), 0, s, D, inst, nslab, y0, nyb, M, stats, Pb,
+                       P32, Y, uc);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_destd_uc(const float* Y, const float* st, const float* uc, long long n,
+                                                  float* out) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int c = (int)(i % NOUT);
+    const long long r = i / NOUT;
+    out[i] = Y[i] * st[2 * NF + NOUT + c] + st[2 * NF + c] + (c < 3 ? uc[r * 3 + c] : 0.0f);
+}
+
+hipError_t mlp_destandardize_uc(const float* Y, const float* stats, const float* uc, long long rows, float* out,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_destd_uc, dim3(nblk(rows * NOUT)), dim3(256), 0, s, Y, stats, uc, rows * NOUT, out);
+    return hipGetLastError();
+}
+
 // One workgroup per particle tile: count, sum v and sum v v of every
 // particle's LB node (all particles of the slab lie in slab nodes).  A tile
 // of the shifted grid covers few nodes, so the sums go through an LDS window

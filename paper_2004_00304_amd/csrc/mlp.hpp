@@ -95,6 +95,16 @@ hipError_t closure_features(int lb_fp, const InstDesc* D, int inst, long long ns
 // node; with do_prof also into the profile accumulators.
 hipError_t closure_to_acc(const InstDesc* D, int inst, long long nslab, const float* Y, const float* stats,
                           const float* uc, double* acc, double* prof, int do_prof, hipStream_t s);
+// Fused inference of every slab node of the current populations: the moments
+// and shear rate of the band rows [y0, y0 + nyb) into M (nband x 12 doubles),
+// then features and the four layers in one kernel.  Y: standardised output
+// [nslab][NOUT]; uc: the node's LB velocity [nslab][3].
+hipError_t closure_predict(int lb_fp, const InstDesc* D, int inst, long long nslab, long long nband, int y0,
+                           int nyb, const void* f, double* M, const float* stats, const uint16_t* Pb,
+                           const float* P32, float* Y, float* uc, hipStream_t s);
+// Physical units from a standardised output and the nodes' LB velocities.
+hipError_t mlp_destandardize_uc(const float* Y, const float* stats, const float* uc, long long rows, float* out,
+                                hipStream_t s);
 // Particle moments per slab node (count, sum v, sum v v) of one channel;
 // one workgroup per particle tile.
 hipError_t closure_node_moments(int part_fp, const InstDesc* D, int inst, long long ntiles, const void* pos0,

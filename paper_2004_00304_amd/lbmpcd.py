@@ -94,6 +94,7 @@ def _load():
     L.lbmpcd_closure_loss_grad.argtypes = [P, P, P, C.c_int64, P, C.c_size_t, P, P]
     L.lbmpcd_closure_forward.argtypes = [P, P, C.c_int64, P, P, C.c_size_t]
     L.lbmpcd_closure_features.argtypes = [P, P]
+    L.lbmpcd_closure_predict.argtypes = [P, P]
     L.lbmpcd_closure_weights.argtypes = [P, C.c_int32, P, C.c_size_t]
     L.lbmpcd_closure_enable.argtypes = [P, C.c_int32, C.c_double, C.c_int32, C.c_int32]
     L.lbmpcd_closure_check.argtypes = [P, C.c_int32, C.POINTER(C.c_double)]
@@ -102,7 +103,7 @@ def _load():
     for name in ("lbmpcd_closure_scratch_size", "lbmpcd_closure_collect", "lbmpcd_closure_train",
                  "lbmpcd_closure_loss_grad", "lbmpcd_closure_forward", "lbmpcd_closure_weights",
                  "lbmpcd_closure_enable", "lbmpcd_closure_check", "lbmpcd_closure_status",
-                 "lbmpcd_closure_gemm_bf16", "lbmpcd_closure_features"):
+                 "lbmpcd_closure_gemm_bf16", "lbmpcd_closure_features", "lbmpcd_closure_predict"):
         getattr(L, name).restype = C.c_int
     L.lbmpcd_last_error.argtypes = [P]
     L.lbmpcd_last_error.restype = C.c_char_p
@@ -121,7 +122,7 @@ EXPORTED = ("lbmpcd_workspace_size", "lbmpcd_init", "lbmpcd_step", "lbmpcd_momen
             "lbmpcd_closure_collect", "lbmpcd_closure_train", "lbmpcd_closure_loss_grad",
             "lbmpcd_closure_forward", "lbmpcd_closure_weights", "lbmpcd_closure_enable",
             "lbmpcd_closure_check", "lbmpcd_closure_status", "lbmpcd_closure_gemm_bf16",
-            "lbmpcd_closure_features")
+            "lbmpcd_closure_features", "lbmpcd_closure_predict")
 
 # candidate tile sizes of lbmpcd_autotune (expected particles per tile)
 TUNE_TILE_TARGETS = (160, 320, 640, 1280)
@@ -431,6 +432,16 @@ class Sim:
         Y = self.torch.empty(n, CLOSURE_NOUT, dtype=self.torch.float32, device=self.device)
         _check(_lib.lbmpcd_closure_forward(self._h, C.c_void_p(X.data_ptr()), n, C.c_void_p(Y.data_ptr()),
                                            C.c_void_p(scr.data_ptr()), scr.numel()), self._h)
+        return Y
+
+    def closure_predict(self):
+        """Network output in physical units for every slab node of the current
+        populations (device tensor [nslab, 9]) through the fused inference
+        kernel of the surrogate step."""
+        p = self.plist[0]
+        nslab = p["n"][0] * (p["yhi"] - p["ylo"]) * p["n"][2]
+        Y = self.torch.empty(nslab, CLOSURE_NOUT, dtype=self.torch.float32, device=self.device)
+        _check(_lib.lbmpcd_closure_predict(self._h, C.c_void_p(Y.data_ptr())), self._h)
         return Y
 
     def closure_weights(self, block=None):

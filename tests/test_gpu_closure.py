@@ -153,6 +153,37 @@ def test_features_and_targets_match_oracle(env):
     assert err <= 2e-6
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(n=(13, 16, 5), lb_fp=32, part_fp=32)], ids=["fp64", "ragged_fp32"])
+def test_fused_prediction_equals_separate_products(env, kw):
+    """The surrogate step's fused kernel (band moments, features and the four
+    layers in one launch) against the separate path: the feature kernel, then
+    one matrix-core product per layer.  Both round the same operands to BF16
+    and accumulate the k steps in the same order, so they agree to the last
+    bit unless an FP32 sum lands on a BF16 rounding tie; the bound is that of
+    the forward pass against the oracle.  The ragged case has 520 slab nodes
+    (four full blocks of 128 and a partial one) and FP32 populations."""
+    torch, M, lbmpcd = env
+    p = channel(**kw)
+    sim = lbmpcd.Sim(p)
+    sim.step(3)
+    X = sim.closure_features()
+    rng = np.random.default_rng(5)
+    block = random_block(M, rng)
+    Xn = X.cpu().numpy().astype(np.float64)
+    block[M.NPARAM:] = M.stats_of(Xn, rng.normal(size=(Xn.shape[0], 9))).astype(np.float32)
+    sim.closure_weights(block)
+    Ys = sim.closure_forward(X).cpu().numpy().astype(np.float64)
+    Yf = sim.closure_predict().cpu().numpy().astype(np.float64)
+    assert Yf.shape == Ys.shape and np.all(np.isfinite(Yf))
+    sc = np.maximum(np.abs(Ys).max(axis=0), 1e-30)
+    el = (np.abs(Yf - Ys) / sc).max()
+    nrm = rel_l2(Yf, Ys)
+    banner(f"fused vs separate ({Xn.shape[0]} rows): max rel {el:.2e}, rel L2 {nrm:.2e}, "
+           f"identical {np.mean(Yf == Ys):.4f}")
+    assert el <= 1e-2
+    assert nrm <= 1e-3
+
+
 def oneway(**kw):
     """The paper's one-way coupling (feedback 0) on a wider channel: the LB
     does not see the particles, so the surrogate and the plain run share the
