@@ -72,6 +72,7 @@ struct lbmpcd_ctx {
     bool closure = false;          // region reserved
     float* cl_P = nullptr;         // [NPARAM] FP32 parameters
     uint16_t* cl_Pb = nullptr;     // [NPARAM] BF16 copy
+    uint16_t* cl_Pf = nullptr;     // [NFRAG] BF16 weights in the fused kernel's fragment order
     float* cl_G = nullptr;         // [NPARAM] gradient
     float* cl_m = nullptr;         // [NPARAM] Adam first moment
     float* cl_v = nullptr;         // [NPARAM] Adam second moment
@@ -232,7 +233,7 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
 
 struct Layout {
     size_t desc, tile_inst, f0, f1, ub, uf, acc, prof, fill0, fill1, stats, clock, shifts, scratch, end;
-    size_t cl_P, cl_Pb, cl_G, cl_m, cl_v, cl_stats, cl_sums, cl_loss, cl_facc, cl_nm, cl_uc, cl_inf;
+    size_t cl_P, cl_Pb, cl_Pf, cl_G, cl_m, cl_v, cl_stats, cl_sums, cl_loss, cl_facc, cl_nm, cl_uc, cl_inf;
     size_t part[2];       // particle buffer: 2 dim component arrays of cstride bytes, then ids
     size_t cstride;
     size_t acc_bytes, prof_bytes, scratch_bytes;
@@ -320,6 +321,7 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
     if (p[0].closure) {
         L.cl_P = take(4 * (size_t)NPARAM);
         L.cl_Pb = take(2 * (size_t)NPARAM);
+        L.cl_Pf = take(2 * (size_t)NFRAG);
         L.cl_G = take(4 * (size_t)NPARAM);
         L.cl_m = take(4 * (size_t)NPARAM);
         L.cl_v = take(4 * (size_t)NPARAM);
@@ -516,6 +518,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
         c->closure = true;
         c->cl_P = (float*)(c->ws + L.cl_P);
         c->cl_Pb = (uint16_t*)(c->ws + L.cl_Pb);
+        c->cl_Pf = (uint16_t*)(c->ws + L.cl_Pf);
         c->cl_G = (float*)(c->ws + L.cl_G);
         c->cl_m = (float*)(c->ws + L.cl_m);
         c->cl_v = (float*)(c->ws + L.cl_v);
@@ -585,7 +588,8 @@ static hipError_t closure_predict_now(lbmpcd_ctx* c, hipStream_t s) {
     const InstDesc& d = c->desc[0];
     const long long nband = (long long)d.nx * d.nyb * d.nz;
     return closure_predict(c->lb_fp, c->d_desc, 0, c->cl_nslab, nband, d.by0, d.nyb, c->f[c->fcur],
-                           (double*)c->cl_inf.X, c->cl_stats, c->cl_Pb, c->cl_P, c->cl_inf.Y, c->cl_uc, s);
+                           (double*)c->cl_inf.X, c->cl_stats, c->cl_Pb, c->cl_Pf, c->cl_P, c->cl_inf.Y,
+                           c->cl_uc, s);
 }
 
 int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {

@@ -19,12 +19,13 @@ namespace lbmpcd {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// BF16 with round-to-nearest-even (NaN kept quiet).
+// BF16 with round-to-nearest-even (NaN kept quiet); branch-free, so that
+// loops of conversions stay one basic block the scheduler can overlap.
 __device__ __forceinline__ uint16_t to_bf16(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const uint32_t u = __float_as_uint(x);
+    const uint32_t rounded = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t quiet = (u >> 16) | 0x40u;
+    return (uint16_t)((u & 0x7FFFFFFFu) > 0x7F800000u ? quiet : rounded);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -584,24 +585,45 @@ constexpr int FR = 128;        // rows per workgroup
 constexpr int XPITCH = NFP + 4;  // LDS row pitch of the feature block (BF16 elements)
 constexpr int HPITCH = NH + 4;   // LDS row pitch of a hidden block
 
-__device__ __forceinline__ void mfma_layer(const uint16_t* act, int pitch, int K, const uint16_t* W, int ncol_blocks,
-                                           int nvalid, f32x16 acc[4]) {
+// Weights of one layer in fragment order (see FRAG_L1): one thread per value.
+__global__ void __launch_bounds__(256) k_frag_weights(const uint16_t* __restrict__ Pb, uint16_t* Pf) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= NFRAG) return;
+    long long base, off;
+    int K, ncb, nvalid;
+    if (i < FRAG_L2) { base = FRAG_L1; off = OFF_W1; K = NFP; ncb = 4; nvalid = NH; }
+    else if (i < FRAG_L3) { base = FRAG_L2; off = OFF_W2; K = NH; ncb = 4; nvalid = NH; }
+    else if (i < FRAG_L4) { base = FRAG_L3; off = OFF_W3; K = NH; ncb = 4; nvalid = NH; }
+    else { base = FRAG_L4; off = OFF_W4; K = NH; ncb = 1; nvalid = NOUT; }
+    const long long e = i - base;
+    const int j = (int)(e & 3), t = (int)((e >> 2) & 63);
+    const long long sb = e >> 8;  // step * ncb + block
+    const int b = (int)(sb % ncb), st = (int)(sb / ncb);
+    const int n = 32 * b + (t & 31), k = 8 * st + 4 * (t >> 5) + j;
+    Pf[i] = n < nvalid ? Pb[off + (long long)n * K + k] : (uint16_t)0;
+}
+
+// One layer for the wave's 32 rows: each k step loads the rows' 4 inputs from
+// LDS and every column block's weight fragment (one coalesced 512-byte read
+// per wave), then issues the products.
+template <int K, int NCB>
+__device__ __forceinline__ void mfma_layer(const uint16_t* act, int pitch, const uint16_t* Wf, f32x16 acc[4]) {
+    constexpr int NS = K / 8;
     const int lane = threadIdx.x & 63, lr = lane & 31, h = lane >> 5;
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
-    for (int k0 = 0; k0 < K; k0 += 8) {
-        const int kc = k0 + 4 * h;
-        // four consecutive BF16 values as one 8-byte load (rows and weight
-        // blocks start at multiples of 8 bytes)
-        const bf16x4 a = __builtin_bit_cast(bf16x4, *(const uint2*)(act + lr * pitch + kc));
+    const uint2* wf = (const uint2*)Wf + lane;
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            if (nb >= ncol_blocks) break;
-            const int n = nb * 32 + lr;
-            const uint2 bw = n < nvalid ? *(const uint2*)(W + (long long)n * K + kc) : make_uint2(0u, 0u);
-            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, __builtin_bit_cast(bf16x4, bw), acc[nb], 0, 0, 0);
+    for (int st = 0; st < NS; ++st) {
+        // four consecutive BF16 inputs as one 8-byte load (rows start at
+        // multiples of 8 bytes)
+        const bf16x4 a = __builtin_bit_cast(bf16x4, *(const uint2*)(act + lr * pitch + st * 8 + 4 * h));
+#pragma unroll
+        for (int nb = 0; nb < NCB; ++nb) {
+            const uint2 b = wf[(st * NCB + nb) * 64];
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, __builtin_bit_cast(bf16x4, b), acc[nb], 0, 0, 0);
         }
     }
 }
@@ -624,7 +646,7 @@ __device__ __forceinline__ void hidden_out(const f32x16 acc[4], const float* bia
 
 __global__ void __launch_bounds__(256) k_mlp_fused(const InstDesc* __restrict__ D, int inst, long long nslab, int y0,
                                                    int nyb, const double* __restrict__ M, const float* __restrict__ st,
-                                                   const uint16_t* __restrict__ Pb, const float* __restrict__ P32,
+                                                   const uint16_t* __restrict__ Pf, const float* __restrict__ P32,
                                                    float* Y, float* uc) {
     __shared__ uint16_t xs[FR * XPITCH];
     const InstDesc& d = D[inst];
@@ -640,6 +662,7 @@ __global__ void __launch_bounds__(256) k_mlp_fused(const InstDesc* __restrict__ 
     };
     // standardised features of the block: stencil entry s of row r (lanes of
     // a wave take consecutive rows of one stencil entry)
+#pragma unroll 4
     for (int it = tid; it < FR * 27; it += 256) {
         const int r = it % FR, s = it / FR;
         const long long sn = r0 + r;
@@ -667,19 +690,19 @@ __global__ void __launch_bounds__(256) k_mlp_fused(const InstDesc* __restrict__ 
 
     uint16_t* own = xs + wave * 32 * XPITCH;  // this wave's rows; hidden blocks reuse them
     f32x16 acc[4];
-    mfma_layer(own, XPITCH, NFP, Pb + OFF_W1, 4, NH, acc);
+    mfma_layer<NFP, 4>(own, XPITCH, Pf + FRAG_L1, acc);
     __syncthreads();
     hidden_out(acc, P32 + OFF_B1, own);
     __syncthreads();
-    mfma_layer(own, HPITCH, NH, Pb + OFF_W2, 4, NH, acc);
+    mfma_layer<NH, 4>(own, HPITCH, Pf + FRAG_L2, acc);
     __syncthreads();
     hidden_out(acc, P32 + OFF_B2, own);
     __syncthreads();
-    mfma_layer(own, HPITCH, NH, Pb + OFF_W3, 4, NH, acc);
+    mfma_layer<NH, 4>(own, HPITCH, Pf + FRAG_L3, acc);
     __syncthreads();
     hidden_out(acc, P32 + OFF_B3, own);
     __syncthreads();
-    mfma_layer(own, HPITCH, NH, Pb + OFF_W4, 1, NOUT, acc);
+    mfma_layer<NH, 1>(own, HPITCH, Pf + FRAG_L4, acc);
     const int lr = lane & 31, h = lane >> 5;
     if (lr < NOUT) {
         const float bc = P32[OFF_B4 + lr];
@@ -694,7 +717,8 @@ static_assert(FR == 4 * 32, "four waves of 32 rows");
 
 hipError_t closure_predict(int lb_fp, const InstDesc* D, int inst, long long nslab, long long nband, int y0,
                            int nyb, const void* f, double* M, const float* stats, const uint16_t* Pb,
-                           const float* P32, float* Y, float* uc, hipStream_t s) {
+                           uint16_t* Pf, const float* P32, float* Y, float* uc, hipStream_t s) {
+    hipLaunchKernelGGL(k_frag_weights, dim3(nblk(NFRAG)), dim3(256), 0, s, Pb, Pf);
     if (lb_fp == 64)
         hipLaunchKernelGGL(k_band_moments<double>, dim3(nblk(nband)), dim3(256), 0, s, D, inst, (const double*)f,
                            y0, nyb, M);
@@ -703,7 +727,7 @@ hipError_t closure_predict(int lb_fp, const InstDesc* D, int inst, long long nsl
                            y0, nyb, M);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mlp_fused, dim3(nblk(nslab, FR)), dim3(256), 0, s, D, inst, nslab, y0, nyb, M, stats, Pb,
+    hipLaunchKernelGGL(k_mlp_fused, dim3(nblk(nslab, FR)), dim3(256), 0, s, D, inst, nslab, y0, nyb, M, stats, Pf,
                        P32, Y, uc);
     return hipGetLastError();
 }
