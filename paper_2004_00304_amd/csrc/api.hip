@@ -588,7 +588,7 @@ static hipError_t closure_predict_now(lbmpcd_ctx* c, hipStream_t s) {
     const InstDesc& d = c->desc[0];
     const long long nband = (long long)d.nx * d.nyb * d.nz;
     return closure_predict(c->lb_fp, c->d_desc, 0, c->cl_nslab, nband, d.by0, d.nyb, c->f[c->fcur],
-                           (double*)c->cl_inf.X, c->cl_stats, c->cl_Pb, c->cl_Pf, c->cl_P, c->cl_inf.Y,
+                           (float*)c->cl_inf.X, c->cl_stats, c->cl_Pb, c->cl_Pf, c->cl_P, c->cl_inf.Y,
                            c->cl_uc, s);
 }
 

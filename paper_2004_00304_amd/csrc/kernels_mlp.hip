@@ -16,7 +16,8 @@
 
 namespace lbmpcd {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // BF16 with round-to-nearest-even (NaN kept quiet); branch-free, so that
@@ -66,16 +67,19 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < GK; kk += 8) {
-            bf16x4 a, b;
+        for (int kk = 0; kk < GK; kk += 16) {
+            // v_mfma_f32_32x32x16_bf16: lane l holds row (column) l % 32 and
+            // the 8 k values 8 (l / 32) .. 8 (l / 32) + 7 of the step
+            s16x8 a, b;
             const int ar = wm * 32 + (lane & 31), br = wn * 32 + (lane & 31);
-            const int kc = kk + 4 * (lane >> 5);
+            const int kc = kk + 8 * (lane >> 5);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 8; ++j) {
                 a[j] = (short)As[ar][kc + j];
                 b[j] = (short)Bs[br][kc + j];
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                          acc, 0, 0, 0);
         }
         __syncthreads();
     }
@@ -545,14 +549,14 @@ hipError_t closure_to_acc(const InstDesc* D, int inst, long long nslab, const fl
 // ---------------------------------------------------------------------------
 // fused inference: features and the four layers in one kernel
 // ---------------------------------------------------------------------------
-constexpr int BMS = 12;  // doubles per band node: 10 moments, shear rate, pad
+constexpr int BMS = 12;  // floats per band node: 10 moments, shear rate, pad
 
 // The 10 moments and the shear rate of every node of the rows [y0, y0 + nyb)
 // that the slab's 3x3x3 stencils reach, computed exactly as the per-node
 // feature kernel computes them.
 template <typename LT>
 __global__ void __launch_bounds__(256) k_band_moments(const InstDesc* __restrict__ D, int inst,
-                                                      const LT* __restrict__ f, int y0, int nyb, double* M) {
+                                                      const LT* __restrict__ f, int y0, int nyb, float* M) {
     const InstDesc& d = D[inst];
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= (long long)d.nx * nyb * d.nz) return;
@@ -567,23 +571,25 @@ __global__ void __launch_bounds__(256) k_band_moments(const InstDesc* __restrict
         const double Sab = -(m[4 + q] - rho * u[A[q]] * u[B[q]]) / (2.0 * rho * (1.0 / 3.0) * d.tau);
         ss += (q < 3 ? 1.0 : 2.0) * Sab * Sab;
     }
-    double* o = M + i * BMS;
-    for (int q = 0; q < 10; ++q) o[q] = m[q];
-    o[10] = sqrt(2.0 * ss);
-    o[11] = 0.0;
+    // binary32 is what the features use of them: (float)m - mean, then / std
+    float* o = M + i * BMS;
+    for (int q = 0; q < 10; ++q) o[q] = (float)m[q];
+    o[10] = (float)sqrt(2.0 * ss);
+    o[11] = 0.0f;
 }
 
 // One workgroup of four waves per block of 128 slab nodes, 32 per wave.  The
 // workgroup writes the block's standardised BF16 features into LDS; each
 // wave then runs its 32 rows through the four layers on the matrix cores
-// (v_mfma_f32_32x32x8_bf16, the k steps in the same order as the separate
+// (v_mfma_f32_32x32x16_bf16, the k steps in the same order as the separate
 // products, so the results are the same), the hidden activations going back
 // into the wave's own rows of the LDS block between layers.  Weights are
 // read from memory (they stay in the caches).  Outputs: the standardised
 // network output Y and the centre node's LB velocity uc.
-constexpr int FR = 128;        // rows per workgroup
-constexpr int XPITCH = NFP + 4;  // LDS row pitch of the feature block (BF16 elements)
-constexpr int HPITCH = NH + 4;   // LDS row pitch of a hidden block
+constexpr int FNT = 256;       // threads per workgroup: four waves
+constexpr int FR = 32 * (FNT / 64);  // rows per workgroup, 32 per wave
+constexpr int XPITCH = NFP + 8;  // LDS row pitch of the feature block (BF16 elements, 16-byte rows)
+constexpr int HPITCH = NH + 8;   // LDS row pitch of a hidden block
 
 // Weights of one layer in fragment order (see FRAG_L1): one thread per value.
 __global__ void __launch_bounds__(256) k_frag_weights(const uint16_t* __restrict__ Pb, uint16_t* Pf) {
@@ -596,34 +602,34 @@ __global__ void __launch_bounds__(256) k_frag_weights(const uint16_t* __restrict
     else if (i < FRAG_L4) { base = FRAG_L3; off = OFF_W3; K = NH; ncb = 4; nvalid = NH; }
     else { base = FRAG_L4; off = OFF_W4; K = NH; ncb = 1; nvalid = NOUT; }
     const long long e = i - base;
-    const int j = (int)(e & 3), t = (int)((e >> 2) & 63);
-    const long long sb = e >> 8;  // step * ncb + block
+    const int j = (int)(e & 7), t = (int)((e >> 3) & 63);
+    const long long sb = e >> 9;  // step * ncb + block
     const int b = (int)(sb % ncb), st = (int)(sb / ncb);
-    const int n = 32 * b + (t & 31), k = 8 * st + 4 * (t >> 5) + j;
+    const int n = 32 * b + (t & 31), k = 16 * st + 8 * (t >> 5) + j;
     Pf[i] = n < nvalid ? Pb[off + (long long)n * K + k] : (uint16_t)0;
 }
 
-// One layer for the wave's 32 rows: each k step loads the rows' 4 inputs from
-// LDS and every column block's weight fragment (one coalesced 512-byte read
-// per wave), then issues the products.
+// One layer for the wave's 32 rows: each k step of 16 loads the rows' inputs
+// from LDS and every column block's weight fragment (one coalesced 1 KiB
+// read per wave), then issues the products.
 template <int K, int NCB>
 __device__ __forceinline__ void mfma_layer(const uint16_t* act, int pitch, const uint16_t* Wf, f32x16 acc[4]) {
-    constexpr int NS = K / 8;
+    constexpr int NS = K / 16;
     const int lane = threadIdx.x & 63, lr = lane & 31, h = lane >> 5;
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
-    const uint2* wf = (const uint2*)Wf + lane;
+    const uint4* wf = (const uint4*)Wf + lane;
 #pragma unroll
     for (int st = 0; st < NS; ++st) {
-        // four consecutive BF16 inputs as one 8-byte load (rows start at
-        // multiples of 8 bytes)
-        const bf16x4 a = __builtin_bit_cast(bf16x4, *(const uint2*)(act + lr * pitch + st * 8 + 4 * h));
+        // eight consecutive BF16 inputs as one 16-byte load (rows start at
+        // multiples of 16 bytes)
+        const bf16x8 a = __builtin_bit_cast(bf16x8, *(const uint4*)(act + lr * pitch + st * 16 + 8 * h));
 #pragma unroll
         for (int nb = 0; nb < NCB; ++nb) {
-            const uint2 b = wf[(st * NCB + nb) * 64];
-            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, __builtin_bit_cast(bf16x4, b), acc[nb], 0, 0, 0);
+            const uint4 b = wf[(st * NCB + nb) * 64];
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8, b), acc[nb], 0, 0, 0);
         }
     }
 }
@@ -644,8 +650,8 @@ __device__ __forceinline__ void hidden_out(const f32x16 acc[4], const float* bia
     }
 }
 
-__global__ void __launch_bounds__(256) k_mlp_fused(const InstDesc* __restrict__ D, int inst, long long nslab, int y0,
-                                                   int nyb, const double* __restrict__ M, const float* __restrict__ st,
+__global__ void __launch_bounds__(FNT) k_mlp_fused(const InstDesc* __restrict__ D, int inst, long long nslab, int y0,
+                                                   int nyb, const float* __restrict__ M, const float* __restrict__ st,
                                                    const uint16_t* __restrict__ Pf, const float* __restrict__ P32,
                                                    float* Y, float* uc) {
     __shared__ uint16_t xs[FR * XPITCH];
@@ -663,7 +669,7 @@ __global__ void __launch_bounds__(256) k_mlp_fused(const InstDesc* __restrict__ 
     // standardised features of the block: stencil entry s of row r (lanes of
     // a wave take consecutive rows of one stencil entry)
 #pragma unroll 4
-    for (int it = tid; it < FR * 27; it += 256) {
+    for (int it = tid; it < FR * 27; it += FNT) {
         const int r = it % FR, s = it / FR;
         const long long sn = r0 + r;
         uint16_t* xr = xs + r * XPITCH + s * 10;
@@ -671,20 +677,20 @@ __global__ void __launch_bounds__(256) k_mlp_fused(const InstDesc* __restrict__ 
             for (int q = 0; q < 10; ++q) xr[q] = 0;
             continue;
         }
-        const double* m = M + band_index(sn, s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1) * BMS;
+        const float* m = M + band_index(sn, s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1) * BMS;
         for (int q = 0; q < 10; ++q) {
             const int k = s * 10 + q;
-            xr[q] = to_bf16(((float)m[q] - st[k]) / st[NF + k]);
+            xr[q] = to_bf16((m[q] - st[k]) / st[NF + k]);
         }
     }
-    for (int r = tid; r < FR; r += 256) {
+    for (int r = tid; r < FR; r += FNT) {
         const long long sn = r0 + r;
         uint16_t* xr = xs + r * XPITCH;
         for (int q = NF - 1; q < NFP; ++q) xr[q] = 0;
         if (sn >= nslab) continue;
-        const double* m = M + band_index(sn, 0, 0, 0) * BMS;
-        xr[NF - 1] = to_bf16(((float)m[10] - st[NF - 1]) / st[2 * NF - 1]);
-        for (int a = 0; a < 3; ++a) uc[sn * 3 + a] = (float)m[1 + a];
+        const float* m = M + band_index(sn, 0, 0, 0) * BMS;
+        xr[NF - 1] = to_bf16((m[10] - st[NF - 1]) / st[2 * NF - 1]);
+        for (int a = 0; a < 3; ++a) uc[sn * 3 + a] = m[1 + a];
     }
     __syncthreads();
 
@@ -713,10 +719,9 @@ __global__ void __launch_bounds__(256) k_mlp_fused(const InstDesc* __restrict__ 
         }
     }
 }
-static_assert(FR == 4 * 32, "four waves of 32 rows");
 
 hipError_t closure_predict(int lb_fp, const InstDesc* D, int inst, long long nslab, long long nband, int y0,
-                           int nyb, const void* f, double* M, const float* stats, const uint16_t* Pb,
+                           int nyb, const void* f, float* M, const float* stats, const uint16_t* Pb,
                            uint16_t* Pf, const float* P32, float* Y, float* uc, hipStream_t s) {
     hipLaunchKernelGGL(k_frag_weights, dim3(nblk(NFRAG)), dim3(256), 0, s, Pb, Pf);
     if (lb_fp == 64)
@@ -727,7 +732,7 @@ hipError_t closure_predict(int lb_fp, const InstDesc* D, int inst, long long nsl
                            y0, nyb, M);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mlp_fused, dim3(nblk(nslab, FR)), dim3(256), 0, s, D, inst, nslab, y0, nyb, M, stats, Pf,
+    hipLaunchKernelGGL(k_mlp_fused, dim3(nblk(nslab, FR)), dim3(FNT), 0, s, D, inst, nslab, y0, nyb, M, stats, Pf,
                        P32, Y, uc);
     return hipGetLastError();
 }

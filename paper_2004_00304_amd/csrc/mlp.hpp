@@ -25,14 +25,15 @@ constexpr long long OFF_W4 = OFF_B3 + NH;
 constexpr long long OFF_B4 = OFF_W4 + (long long)NOUT * NH;
 constexpr long long NPARAM = OFF_B4 + NOUT;
 // The BF16 weights in the order the fused inference kernel reads them: for
-// layer l, k step s (8 inputs), 32-column block b and lane t of a wave, the 4
-// values W[32 b + t % 32][8 s + 4 (t / 32) + j], j = 0..3 (zero past the last
-// output), so that every lane's 8 bytes of a (step, block) are contiguous.
+// layer l, k step s (16 inputs), 32-column block b and lane t of a wave, the
+// 8 values W[32 b + t % 32][16 s + 8 (t / 32) + j], j = 0..7 (zero past the
+// last output), so that every lane's 16 bytes of a (step, block) are
+// contiguous.
 constexpr long long FRAG_L1 = 0;
-constexpr long long FRAG_L2 = FRAG_L1 + (long long)(NFP / 8) * 4 * 256;
-constexpr long long FRAG_L3 = FRAG_L2 + (long long)(NH / 8) * 4 * 256;
-constexpr long long FRAG_L4 = FRAG_L3 + (long long)(NH / 8) * 4 * 256;
-constexpr long long NFRAG = FRAG_L4 + (long long)(NH / 8) * 1 * 256;
+constexpr long long FRAG_L2 = FRAG_L1 + (long long)(NFP / 16) * 4 * 512;
+constexpr long long FRAG_L3 = FRAG_L2 + (long long)(NH / 16) * 4 * 512;
+constexpr long long FRAG_L4 = FRAG_L3 + (long long)(NH / 16) * 4 * 512;
+constexpr long long NFRAG = FRAG_L4 + (long long)(NH / 16) * 1 * 512;
 // Standardisation: feature mean[NF], std[NF], target mean[NOUT], std[NOUT].
 constexpr long long NSTATS = 2 * NF + 2 * NOUT;
 // The network's velocity outputs are relative to the LB velocity of the node
@@ -105,12 +106,12 @@ hipError_t closure_features(int lb_fp, const InstDesc* D, int inst, long long ns
 hipError_t closure_to_acc(const InstDesc* D, int inst, long long nslab, const float* Y, const float* stats,
                           const float* uc, double* acc, double* prof, int do_prof, hipStream_t s);
 // Fused inference of every slab node of the current populations: the moments
-// and shear rate of the band rows [y0, y0 + nyb) into M (nband x 12 doubles),
+// and shear rate of the band rows [y0, y0 + nyb) into M (nband x 12 floats),
 // then features and the four layers in one kernel (Pf: scratch for the
 // weights in fragment order, NFRAG BF16 values).  Y: standardised output
 // [nslab][NOUT]; uc: the node's LB velocity [nslab][3].
 hipError_t closure_predict(int lb_fp, const InstDesc* D, int inst, long long nslab, long long nband, int y0,
-                           int nyb, const void* f, double* M, const float* stats, const uint16_t* Pb,
+                           int nyb, const void* f, float* M, const float* stats, const uint16_t* Pb,
                            uint16_t* Pf, const float* P32, float* Y, float* uc, hipStream_t s);
 // Physical units from a standardised output and the nodes' LB velocities.
 hipError_t mlp_destandardize_uc(const float* Y, const float* stats, const float* uc, long long rows, float* out,
