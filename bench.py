@@ -199,7 +199,14 @@ def closure_bench(lbmpcd, W, args):
     sim.closure_weights(block)
     sim.closure_enable(True, tol=0.02, check_every=0)
     sim.step(args.warmup)
+    sim.timing(1)
     sur = timed(args.steps)
+    sim.timing(0)
+    kt = sim.timing_read()
+    cl_ms = kt["closure"]["ms"] / max(1, kt["closure"]["launches"])
+    # network flops of one inference over every slab node (271 real inputs)
+    nslab = p["n"][0] * (p["yhi"] - p["ylo"]) * p["n"][2]
+    flops = 2.0 * nslab * (271 * 128 + 128 * 128 * 2 + 128 * 9)
     out = {
         "metric": "coupled steps/s: LB MLUPS + MPCD particle-updates/s, % HBM roofline",
         "value": 1.0 / sur, "unit": "coupled LB steps/s", "n_gpus": 1, "steps": args.steps,
@@ -211,6 +218,11 @@ def closure_bench(lbmpcd, W, args):
                                 f"271-128-128-128-9"), "lb_nodes": sz["nodes"], "particles": sz["particles"]},
         "plain_steps_per_s": 1.0 / plain, "plain_ms_per_step": 1e3 * plain,
         "surrogate_speedup": plain / sur,
+        "kernels_ms_per_launch": {k: v["ms"] / max(1, v["launches"]) for k, v in kt.items()},
+        "roofline": {"bound": "mfma", "kernel": "closure inference (band moments + fused features/MLP)",
+                     "achieved": flops / (cl_ms * 1e-3) / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flops / (cl_ms * 1e-3) / 1e12 / 2500.0, "traffic": None,
+                     "algorithmic_flops_per_launch": flops},
         "lb_mlups": sz["nodes"] / sur / 1e6,
         "training": {"samples": int(n_samples), "data_s": t_data, "train_s": t_train,
                      "epoch_loss": [float(x) for x in losses]},
