@@ -100,7 +100,11 @@ typedef struct lbmpcd_params {
     int32_t ppc;           /* initial particles per cell */
     int32_t part_fp;       /* particle storage: 32 or 64 (cell sums always 64) */
     double mass, kT, alpha_deg;
-    int32_t collision;     /* 0: SRD (stochastic rotation); others unsupported */
+    int32_t collision;     /* 0: SRD (stochastic rotation, Eq. 4); 1: MPCD with Andersen
+                              thermostat (Eq. 6): every particle gets the cell's centre of
+                              mass plus its own Gaussian velocity (variance kT/m per
+                              component) less the cell mean of those; all instances of a
+                              context share it */
     int32_t grid_shift;    /* 1: random grid shift every MPCD step */
     int32_t feedback;      /* 1: project MPCD averages onto LB equilibria */
     int32_t init_flow;     /* 0: rest, 1: discrete Poiseuille profile (needs walls) */

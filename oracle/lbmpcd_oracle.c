@@ -57,7 +57,7 @@ double orc_u01(uint32_t lo, uint32_t hi) {
 
 /* READING: purposes of the random streams; the counter is
  * (element, LB step, substep<<8 | purpose, block). */
-enum { P_INIT_POS = 1, P_INIT_VEL = 2, P_REINJ = 3, P_SHIFT = 4, P_ROT = 5, P_WALL = 6 };
+enum { P_INIT_POS = 1, P_INIT_VEL = 2, P_REINJ = 3, P_SHIFT = 4, P_ROT = 5, P_WALL = 6, P_AT = 9 };
 
 static void rng_block(const orc_params* p, uint32_t elem, uint32_t t, uint32_t sub,
                       uint32_t purpose, uint32_t blk, uint32_t out[4]) {
@@ -209,6 +209,40 @@ void orc_srd_rotate(int32_t dim, int32_t n, double* vel, double cos_a, double si
     }
 }
 
+/* ------------------------------------------------------------------------
+ * MPCD with Andersen thermostat, Eq. 6: every particle of the cell gets the
+ * centre-of-mass velocity plus its own random velocity minus the cell mean
+ * of the random velocities (the sum over the cell's N_c particles).  The
+ * centre of mass includes virtual wall particles as for SRD (READING); the
+ * mean of the random part runs over the real particles only (Eq. 6 divides
+ * by the actual number N_c).  vel and vran are [dim][n].
+ * ---------------------------------------------------------------------- */
+void orc_at_collide(int32_t dim, int32_t n, double* vel, const double* vran, const double p_virt[3],
+                    double m_virt, double vcm_out[3]) {
+    if (n <= 0) return;
+    double P[3] = {0.0, 0.0, 0.0}, Sr[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < dim; ++k)
+        for (int i = 0; i < n; ++i) {
+            P[k] += vel[k * n + i];
+            Sr[k] += vran[k * n + i];
+        }
+    double vcm[3] = {0.0, 0.0, 0.0}, mean[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < dim; ++k) {
+        vcm[k] = (P[k] + p_virt[k]) / ((double)n + m_virt);
+        mean[k] = Sr[k] / (double)n;
+    }
+    if (vcm_out)
+        for (int k = 0; k < 3; ++k) vcm_out[k] = vcm[k];
+    for (int k = 0; k < dim; ++k)
+        for (int i = 0; i < n; ++i) vel[k * n + i] = vcm[k] + (vran[k * n + i] - mean[k]);
+}
+
+/* Eq. 7 (the paper's viscosity of MPCD-AT) */
+double orc_nu_at(double kT, double mass, double dt, double a, double N) {
+    const double q = N - 1.0 + exp(-N);
+    return kT * dt / mass * (N / q - 0.5) + a * a / (12.0 * dt) * q / N;
+}
+
 /* Stable counting sort: histogram, exclusive prefix sum, scatter in input order. */
 void orc_counting_sort(int32_t n, const int32_t* cell, int32_t nc, int32_t* count,
                        int32_t* start, int32_t* order) {
@@ -285,6 +319,7 @@ static int validate(const orc_params* p) {
     if ((bw && p->buf_lo) || (tw && p->buf_hi)) return 1;
     if ((bw || tw) && p->g[1] != 0.0) return 1;
     if (!(p->mass > 0.0) || p->kT < 0.0) return 1;
+    if (p->collision != 0 && p->collision != 1) return 1;
     return 0;
 }
 
@@ -757,14 +792,14 @@ static int32_t particle_cell(const orc_state* s, int64_t k, const double sh[3]) 
     return cell_of_pos(s, r, sh);
 }
 
-/* SRD collision of every cell (Eq. 4).  READING: 2D sign and 3D axis per
- * cell and step from the ROT stream; cells cut by a wall get virtual
- * particles up to the nominal occupancy. */
-/* SRD collision of the n particles of cell c: v is [dim][n] (unit-mass
+/* Collision of every cell: SRD (Eq. 4; READING: 2D sign and 3D axis per
+ * cell and step from the ROT stream) or MPCD-AT (Eq. 6); cells cut by a wall
+ * get virtual particles up to the nominal occupancy. */
+/* Collision of the n particles (ids[n]) of cell c: v is [dim][n] (unit-mass
  * velocities, updated in place and rounded to the store precision); vcm
  * receives the centre-of-mass velocity including virtual wall particles. */
 static void collide_one(const orc_state* s, int32_t c, uint32_t t, uint32_t sub, const double sh[3], int32_t n,
-                        double* v, double vcm_out[3]) {
+                        const int32_t* ids, double* v, double vcm_out[3]) {
     const orc_params* p = &s->p;
     int d = p->dim;
     int iy = (c / s->Cx) % s->CyB;
@@ -778,6 +813,28 @@ static void collide_one(const orc_state* s, int32_t c, uint32_t t, uint32_t sub,
         for (int k = 0; k < d; ++k) pv[k] = sdv * z[k];
         mv = (double)nv;
     }
+    /* virtual momentum enters in units of m; the collision routines use
+     * unit mass so the momentum is divided by m */
+    double pvu[3] = {pv[0] / p->mass, pv[1] / p->mass, pv[2] / p->mass};
+    if (p->collision == 1) {
+        /* MPCD-AT: one Gaussian velocity per particle (READING: variance
+         * kT/m per component, as for the exchange step), keyed by the
+         * particle's id and the collision's MPCD step; stored in the
+         * particle precision before use */
+        double* vr = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+        const double sd = sqrt(p->kT / p->mass);
+        for (int i = 0; i < n; ++i) {
+            double z[3];
+            rng_normals(p, (uint32_t)ids[i], t, sub, P_AT, z);
+            for (int k = 0; k < d; ++k) vr[k * n + i] = st(s, sd * z[k]);
+        }
+        double vc[3] = {0.0, 0.0, 0.0};
+        orc_at_collide(d, n, v, vr, pvu, mv, vc);
+        free(vr);
+        for (int k = 0; k < 3; ++k) vcm_out[k] = vc[k];
+        for (int i = 0; i < d * n; ++i) v[i] = st(s, v[i]);
+        return;
+    }
     uint32_t w[4];
     rng_block(p, (uint32_t)c, t, sub, P_ROT, 0, w);
     double sign2d = (w[0] & 1u) ? 1.0 : -1.0;
@@ -790,9 +847,6 @@ static void collide_one(const orc_state* s, int32_t c, uint32_t t, uint32_t sub,
         axis[1] = sxy * sin(phi);
         axis[2] = nz;
     }
-    /* virtual momentum enters in units of m; the rotation routine uses
-     * unit mass so the momentum is divided by m */
-    double pvu[3] = {pv[0] / p->mass, pv[1] / p->mass, pv[2] / p->mass};
     double vc[3] = {0.0, 0.0, 0.0};
     orc_srd_rotate(d, n, v, s->cos_a, s->sin_a, sign2d, axis, pvu, mv, vc);
     for (int k = 0; k < 3; ++k) vcm_out[k] = vc[k];
@@ -813,7 +867,7 @@ static void collide_cells(orc_state* s, uint32_t t, uint32_t sub, const double s
             for (int k = 0; k < d; ++k) v[k * n + i] = s->vel[k][id];
         }
         double vc[3];
-        collide_one(s, c, t, sub, sh, n, v, vc);
+        collide_one(s, c, t, sub, sh, n, s->order + s->start[c], v, vc);
         for (int k = 0; k < d; ++k) s->vcm[k * s->ncells + c] = vc[k];
         for (int i = 0; i < n; ++i) {
             int32_t id = s->order[s->start[c] + i];
@@ -986,10 +1040,17 @@ void orc_exchange_stream(const orc_state* s, uint32_t t, uint32_t sub, int64_t n
 /* 1 when the fine cell of the position is a buffer cell */
 int32_t orc_in_buffer(const orc_state* s, const double r[3]) { return buffer_cell(s, r) >= 0; }
 
-/* SRD collision of one cell (index c of the shifted grid of (t, sub)). */
+/* Collision of one cell (index c of the shifted grid of (t, sub)). */
 void orc_collide_cell(const orc_state* s, int32_t c, uint32_t t, uint32_t sub, const double sh[3], int32_t n,
-                      double* vel, double vcm[3]) {
-    collide_one(s, c, t, sub, sh, n, vel, vcm);
+                      const int32_t* ids, double* vel, double vcm[3]) {
+    int32_t* seq = NULL;
+    if (!ids) {
+        seq = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        for (int32_t i = 0; i < n; ++i) seq[i] = i;
+        ids = seq;
+    }
+    collide_one(s, c, t, sub, sh, n, ids, vel, vcm);
+    free(seq);
 }
 
 /* Buffer fine-cell velocities [3][Cz][R][Cx] (zero outside the buffers) from

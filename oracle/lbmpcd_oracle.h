@@ -49,6 +49,7 @@ typedef struct orc_params {
     int32_t init_flow;      /* 0: rest, 1: discrete Poiseuille steady profile */
     uint64_t seed;
     uint32_t instance;
+    int32_t collision;      /* 0: SRD rotation (Eq. 4); 1: MPCD with Andersen thermostat (Eq. 6) */
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -104,9 +105,11 @@ void orc_exchange_stream(const orc_state* s, uint32_t t, uint32_t sub, int64_t n
 int32_t orc_in_buffer(const orc_state* s, const double r[3]);
 /* buffer fine-cell velocities ufine[3][Cz][R][Cx] from node velocities unode[3][N] */
 void orc_interpolate(const orc_state* s, const double* unode, double* ufine);
-/* SRD collision of the n particles (vel[dim][n], in place) of cell c */
+/* collision (SRD or MPCD-AT, per the parameters) of the n particles
+ * (vel[dim][n], in place) of cell c; ids[n] are the particles' ids (the
+ * MPCD-AT draws are keyed by them; may be NULL for SRD) */
 void orc_collide_cell(const orc_state* s, int32_t c, uint32_t t, uint32_t sub, const double sh[3], int32_t n,
-                      double* vel, double vcm[3]);
+                      const int32_t* ids, double* vel, double vcm[3]);
 
 /* ---- building blocks, exported for the pins ---------------------------- */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -122,6 +125,14 @@ void orc_box_muller(double u0, double u1, double* z0, double* z1);
 void orc_srd_rotate(int32_t dim, int32_t n, double* vel, double cos_a, double sin_a,
                     double sign2d, const double axis[3], const double p_virt[3], double m_virt,
                     double vcm_out[3]);
+/* MPCD-AT collision (Eq. 6) of n velocities (vel[d][n], in place) given
+ * their random velocities vran[d][n]: v <- v_cm + vran - mean(vran), the
+ * centre of mass including virtual wall momentum p_virt and mass m_virt */
+void orc_at_collide(int32_t dim, int32_t n, double* vel, const double* vran, const double p_virt[3],
+                    double m_virt, double vcm_out[3]);
+/* kinematic viscosity of MPCD-AT (Eq. 7): kT dt / m [N / (N - 1 + e^-N) - 1/2]
+ * + a^2 / (12 dt) (N - 1 + e^-N) / N */
+double orc_nu_at(double kT, double mass, double dt, double a, double N);
 /* stable counting sort of cell ids: count[nc], start[nc], order[n] */
 void orc_counting_sort(int32_t n, const int32_t* cell, int32_t nc,
                        int32_t* count, int32_t* start, int32_t* order);

@@ -39,7 +39,7 @@ class _Params(C.Structure):
         ("substeps", C.c_int32), ("ppc", C.c_int32), ("part_fp32", C.c_int32),
         ("mass", C.c_double), ("kT", C.c_double), ("alpha_deg", C.c_double),
         ("grid_shift", C.c_int32), ("feedback", C.c_int32), ("init_flow", C.c_int32),
-        ("seed", C.c_uint64), ("instance", C.c_uint32),
+        ("seed", C.c_uint64), ("instance", C.c_uint32), ("collision", C.c_int32),
     ]
 
 
@@ -85,6 +85,9 @@ def lib():
         L.orc_srd_rotate.argtypes = [C.c_int32, C.c_int32, P, C.c_double, C.c_double,
                                      C.c_double, P, P, C.c_double, P]
         L.orc_counting_sort.argtypes = [C.c_int32, P, C.c_int32, P, P, P]
+        L.orc_at_collide.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_double, P]
+        L.orc_nu_at.argtypes = [C.c_double] * 5
+        L.orc_nu_at.restype = C.c_double
         _lib = L
     return _lib
 
@@ -107,6 +110,7 @@ def params_struct(p: dict) -> _Params:
     s.mass, s.kT, s.alpha_deg = p["mass"], p["kT"], p["alpha_deg"]
     s.grid_shift, s.feedback, s.init_flow = p["grid_shift"], p["feedback"], p["init_flow"]
     s.seed, s.instance = p["seed"], p["instance"]
+    s.collision = int(p.get("collision", 0))
     return s
 
 
@@ -115,8 +119,6 @@ class Oracle:
 
     def __init__(self, p: dict):
         self.p = dict(p)
-        if p.get("collision", 0) != 0:
-            raise ValueError("oracle implements the SRD collision only")
         self._L = lib()
         self._ps = params_struct(p)
         h = C.c_void_p()
@@ -287,6 +289,21 @@ def srd_rotate(dim, vel, alpha_deg, sign2d=1.0, axis=(0.0, 0.0, 1.0), p_virt=(0,
     return v, vcm[:dim]
 
 
+def at_collide(dim, vel, vran, p_virt=(0, 0, 0), m_virt=0.0):
+    """MPCD-AT collision (Eq. 6) of vel [dim][n] with random velocities vran [dim][n]."""
+    v = np.ascontiguousarray(vel, np.float64).copy()
+    r = np.ascontiguousarray(vran, np.float64)
+    pv = np.asarray(p_virt, np.float64)
+    vcm = np.zeros(3)
+    lib().orc_at_collide(dim, v.shape[1], _ptr(v), _ptr(r), _ptr(pv), float(m_virt), _ptr(vcm))
+    return v, vcm[:dim]
+
+
+def nu_at(kT, mass, dt, a, N):
+    """Kinematic viscosity of MPCD-AT, Eq. 7."""
+    return float(lib().orc_nu_at(float(kT), float(mass), float(dt), float(a), float(N)))
+
+
 def counting_sort(cell, nc):
     cell = np.ascontiguousarray(cell, np.int32)
     count = np.empty(nc, np.int32)
@@ -313,7 +330,7 @@ class Probe:
             L.orc_exchange_stream.argtypes = [P, C.c_uint32, C.c_uint32, C.c_int64, P, P, P, P]
             L.orc_in_buffer.argtypes = [P, P]
             L.orc_in_buffer.restype = C.c_int32
-            L.orc_collide_cell.argtypes = [P, C.c_int32, C.c_uint32, C.c_uint32, P, C.c_int32, P, P]
+            L.orc_collide_cell.argtypes = [P, C.c_int32, C.c_uint32, C.c_uint32, P, C.c_int32, P, P, P]
             L.orc_interpolate.argtypes = [P, P, P]
             L._probe_types = True
         self._L = L
@@ -369,9 +386,13 @@ class Probe:
         self._L.orc_interpolate(self._h, _ptr(u), _ptr(out))
         return out[: self.dim]
 
-    def collide_cell(self, c, t, sub, sh, vel):
+    def collide_cell(self, c, t, sub, sh, vel, ids=None):
         v = np.ascontiguousarray(vel, np.float64).copy()
         sh = np.ascontiguousarray(sh, np.float64)
         vcm = np.zeros(3)
-        self._L.orc_collide_cell(self._h, int(c), t, sub, _ptr(sh), v.shape[1], _ptr(v), _ptr(vcm))
+        idp = None
+        if ids is not None:
+            ids = np.ascontiguousarray(ids, np.int32)
+            idp = _ptr(ids)
+        self._L.orc_collide_cell(self._h, int(c), t, sub, _ptr(sh), v.shape[1], idp, _ptr(v), _ptr(vcm))
         return v, vcm[: self.dim]

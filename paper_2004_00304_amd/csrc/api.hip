@@ -49,6 +49,7 @@ struct lbmpcd_ctx {
     size_t lds = 0;
     int cap_max = 0;              // largest tile capacity
     int wg_threads = 0;           // particle kernel workgroup size
+    int coll_bit = 0;             // 4 for the MPCD-AT collision (particle kernel mode bit)
     int xcd_blocked = 1;          // XCD-blocked tile order of the particle kernel
     long long cstride = 0;        // bytes between the component arrays of a particle buffer
     long long t = 0;
@@ -207,7 +208,7 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     if ((long long)p.n[0] * p.n[1] * p.n[2] > (1LL << 40)) { msg = "domain too large"; return LBMPCD_E_INVALID; }
     if (p.closure && !p.mpcd) { msg = "the closure needs the MPCD slab"; return LBMPCD_E_INVALID; }
     if (!p.mpcd) return 0;
-    if (p.collision != 0) { msg = "only the SRD collision (0) is implemented"; return LBMPCD_E_UNSUPPORTED; }
+    if (p.collision != 0 && p.collision != 1) { msg = "collision must be 0 (SRD) or 1 (MPCD-AT)"; return LBMPCD_E_UNSUPPORTED; }
     if (p.wg_threads != 0 && p.wg_threads != 128 && p.wg_threads != 256 && p.wg_threads != 512) { msg = "wg_threads must be 0, 128, 256 or 512"; return LBMPCD_E_INVALID; }
     if (p.tile_target < 0 || p.tile_target > 8 * WG) { msg = "tile_target out of range"; return LBMPCD_E_INVALID; }
     if (p.closure && p.dim != 3) { msg = "the closure needs dim 3"; return LBMPCD_E_INVALID; }
@@ -347,8 +348,8 @@ int validate_all(const lbmpcd_params* p, int n, std::string& msg) {
             msg = "all instances must share dim, lb_fp, mpcd, part_fp and substeps";
             return LBMPCD_E_INVALID;
         }
-        if (p[i].wg_threads != p[0].wg_threads) {
-            msg = "all instances must share wg_threads";
+        if (p[i].wg_threads != p[0].wg_threads || p[i].collision != p[0].collision) {
+            msg = "all instances must share wg_threads and the collision rule";
             return LBMPCD_E_INVALID;
         }
         if (p[i].closure && n != 1) {
@@ -403,7 +404,7 @@ hipError_t timed(lbmpcd_ctx* c, int cls, F f) {
 int finalize(lbmpcd_ctx* c) {
     if (!c->pending || !c->mpcd) return 0;
     ParticleLaunch L{};
-    L.dim = c->dim; L.part_fp = c->part_fp; L.mode = 1;
+    L.dim = c->dim; L.part_fp = c->part_fp; L.mode = 1 | c->coll_bit;
     L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
     L.in = c->part[c->pcur]; L.out = c->part[c->pcur];
     L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
@@ -543,6 +544,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     // more than 1024 slots (four particles per thread instead of eight)
     c->wg_threads = p[0].wg_threads ? p[0].wg_threads : (c->part_fp == 64 && cap_max > 4 * 256 ? 512 : 256);
     c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max);
+    c->coll_bit = p[0].collision == 1 ? 4 : 0;
 
     // tile -> instance table
     std::vector<int> tinst((size_t)std::max<long long>(c->total_tiles, 1));
@@ -631,7 +633,7 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
             for (int sub = 0; sub < c->S; ++sub) {
                 ParticleLaunch L{};
                 L.dim = c->dim; L.part_fp = c->part_fp;
-                L.mode = (sub == 0 && !c->pending) ? 2 : 3;
+                L.mode = (sub == 0 && !c->pending) ? 2 : (3 | c->coll_bit);
                 L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
                 L.in = c->part[c->pcur]; L.out = c->part[c->pcur ^ 1];
                 L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
@@ -794,7 +796,7 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             if (!c->pending) return fail(c, LBMPCD_E_STATE, "cell velocities exist only right after lbmpcd_step");
             HIPCHK(c, launch_zero(dst, nbytes, s));
             ParticleLaunch L{};
-            L.dim = c->dim; L.part_fp = c->part_fp; L.mode = 1;
+            L.dim = c->dim; L.part_fp = c->part_fp; L.mode = 1 | c->coll_bit;
             L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
             // the pending collision is evaluated into the idle particle buffer, so
             // the state (and the other instances' pending collisions) is untouched

@@ -22,6 +22,7 @@ enum Purpose : uint32_t {
     P_INIT_POS = 1, P_INIT_VEL = 2, P_REINJ = 3, P_SHIFT = 4, P_ROT = 5, P_WALL = 6,
     P_MLP_INIT = 7,   // closure network initial weights
     P_MLP_BATCH = 8,  // closure training batch draws
+    P_AT = 9,         // random velocities of the MPCD-AT collision
 };
 
 // Everything a kernel needs to know about one channel.  One array of these

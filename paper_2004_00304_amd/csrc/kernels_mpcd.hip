@@ -125,6 +125,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(LBMPCD_
 k_particles(PArgs<PT> A) {
     constexpr bool COLL = (MODE & 1) != 0;
     constexpr bool STREAM = (MODE & 2) != 0;
+    constexpr bool AT = (MODE & 4) != 0;  // MPCD-AT collision (Eq. 6) instead of SRD (Eq. 4)
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* wstat = (uint32_t*)smem;          // [4] far moves, misplaced
     uint32_t* hkey = wstat + 4;                 // [NHASH] destination tiles (local index)
@@ -136,7 +137,7 @@ k_particles(PArgs<PT> A) {
     uint32_t* ccnt = (uint32_t*)uni;                 // [MAX_NCT]
     double* csv = (double*)(uni + MAX_NCT * 4);      // [MAX_NCT][3]
     double* cvcm = csv + MAX_NCT * 3;                // [MAX_NCT][3]
-    double* crot = cvcm + MAX_NCT * 3;               // [MAX_NCT][3]
+    double* crot = cvcm + MAX_NCT * 3;               // [MAX_NCT][3] SRD sign/axis; MPCD-AT: sum, then mean, of the random velocities
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -205,8 +206,10 @@ k_particles(PArgs<PT> A) {
             const int lx = j & (d.Tx - 1), ly = (j >> d.lTx) & (d.Ty - 1), lz = j >> (d.lTx + d.lTy);
             const int ix = (tx << d.lTx) + lx, iy = (ty << d.lTy) + ly, iz = (tz << d.lTz) + lz;
             const uint32_t cg = (uint32_t)(ix + d.Cx * (iy + d.CyB * iz));
-            const U4 w = rng_block(key, cg, tc, sc, P_ROT, 0);
-            if constexpr (DIM == 2) {
+            const U4 w = AT ? U4{0u, 0u, 0u, 0u} : rng_block(key, cg, tc, sc, P_ROT, 0);
+            if constexpr (AT) {
+                crot[3 * j] = 0.0; crot[3 * j + 1] = 0.0; crot[3 * j + 2] = 0.0;
+            } else if constexpr (DIM == 2) {
                 crot[3 * j] = (w.x & 1u) ? 1.0 : -1.0;
             } else {
                 const double u0 = u01(w.x, w.y), u1 = u01(w.z, w.w);
@@ -224,11 +227,15 @@ k_particles(PArgs<PT> A) {
         __syncthreads();
     }
 
-    // ---- phase 1: SRD collision of the binning these particles sit in
+    // ---- phase 1: collision (SRD, or MPCD-AT) of the binning these particles sit in
     if constexpr (COLL) {
         cst<double>* shc = shtab + ((tcl & 1) * d.S + sc) * 3;
         const PT sh[3] = {(PT)shc[0], (PT)shc[1], (PT)shc[2]};
         int lc[PPT];
+        // MPCD-AT: each particle's random velocity (variance kT/m per
+        // component, keyed by its id and the collision's MPCD step), kept in
+        // the particle precision between the two passes over the cell
+        [[maybe_unused]] PT vr[AT ? PPT : 1][3];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             lc[k] = -1;
@@ -253,6 +260,15 @@ k_particles(PArgs<PT> A) {
             atomicAdd(&ccnt[c], 1u);
 #pragma unroll
             for (int q = 0; q < DIM; ++q) lds_add(&csv[3 * c + q], (double)pv[k][q]);
+            if constexpr (AT) {
+                double z[3];
+                rng_normals<DIM>(key, pid[k], tc, sc, P_AT, z);
+#pragma unroll
+                for (int q = 0; q < DIM; ++q) {
+                    vr[k][q] = (PT)(d.sd * z[q]);
+                    lds_add(&crot[3 * c + q], (double)vr[k][q]);
+                }
+            }
         }
         __syncthreads();
         for (int j = tid; j < d.nct; j += NT) {
@@ -276,6 +292,11 @@ k_particles(PArgs<PT> A) {
             for (int q = 0; q < 3; ++q) cvcm[3 * j + q] = 0.0;
 #pragma unroll
             for (int q = 0; q < DIM; ++q) cvcm[3 * j + q] = (csv[3 * j + q] + pvv[q]) / ((double)nc + mv);
+            if constexpr (AT) {
+                // mean random velocity over the cell's real particles
+#pragma unroll
+                for (int q = 0; q < DIM; ++q) crot[3 * j + q] = crot[3 * j + q] / (double)nc;
+            }
             if (A.cell_vcm && ii == A.diag_inst) {
 #pragma unroll
                 for (int q = 0; q < DIM; ++q) A.cell_vcm[(long long)q * d.ncells + cg] = cvcm[3 * j + q];
@@ -288,6 +309,12 @@ k_particles(PArgs<PT> A) {
             if (lc[k] < 0) continue;
             const int c = lc[k];
             double vc[3] = {cvcm[3 * c], cvcm[3 * c + 1], cvcm[3 * c + 2]};
+            if constexpr (AT) {
+                // Eq. 6: centre of mass plus the random velocity less the cell mean
+#pragma unroll
+                for (int q = 0; q < DIM; ++q) pv[k][q] = (PT)(vc[q] + ((double)vr[k][q] - crot[3 * c + q]));
+                continue;
+            }
             double wv[3] = {0.0, 0.0, 0.0}, rv[3];
 #pragma unroll
             for (int q = 0; q < DIM; ++q) wv[q] = (double)pv[k][q] - vc[q];
@@ -663,6 +690,8 @@ static hipError_t launch_p3(const ParticleLaunch& L, hipStream_t s) {
         case 1: return launch_p4<DIM, PT, NT, PPT, 1>(L, s);
         case 2: return launch_p4<DIM, PT, NT, PPT, 2>(L, s);
         case 3: return launch_p4<DIM, PT, NT, PPT, 3>(L, s);
+        case 5: return launch_p4<DIM, PT, NT, PPT, 5>(L, s);
+        case 7: return launch_p4<DIM, PT, NT, PPT, 7>(L, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -36,7 +36,7 @@ inline PartPtrs<PT> typed(const PartBuf& b) {
 }
 
 struct ParticleLaunch {
-    int dim, part_fp, mode;       // mode bit 0: collide, bit 1: stream
+    int dim, part_fp, mode;       // mode bit 0: collide, bit 1: stream, bit 2: MPCD-AT instead of SRD
     const InstDesc* D;
     int n_inst;
     long long tiles;              // workgroups (tiles of all instances)

@@ -55,7 +55,7 @@ def test_workspace_sizes(binding):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(tau=0.5), 1), (dict(dim=4), 1), (dict(lb_fp=16), 1), (dict(ylo=20, yhi=10), 1),
-    (dict(buf_lo=5, buf_hi=5), 1), (dict(walls_y=1, ylo=0, buf_lo=1), 1), (dict(collision=1), 6),
+    (dict(buf_lo=5, buf_hi=5), 1), (dict(walls_y=1, ylo=0, buf_lo=1), 1), (dict(collision=2), 6),
     (dict(part_fp=16), 1), (dict(refine=0), 1), (dict(n=(8, 8, 2)), 1),
     (dict(walls_y=0, ylo=0, yhi=8), 6), (dict(substeps=300), 1),
 ])

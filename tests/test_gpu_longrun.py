@@ -10,7 +10,8 @@ velocity by the buffers, so
            + g (y - y_a)(y_b - y) / (2 nu_M),
 with nu_M the SRD viscosity of a 2D fluid with random grid shift
 (kinetic part kT dt / m [N / ((N - 1 + e^-N)(1 - cos 2 alpha)) - 1/2],
-collisional part a^2 (1 - cos alpha)(N - 1 + e^-N) / (12 dt N)).  In these
+collisional part a^2 (1 - cos alpha)(N - 1 + e^-N) / (12 dt N)), or, for
+MPCD with Andersen thermostat, nu_M of Eq. 7 at dt = 1/S.  In these
 channels the curvature term is a few percent of u, so the check is mostly
 of the buffers transferring the LB velocity into the slab."""
 import numpy as np
@@ -53,11 +54,21 @@ def nu_srd_2d(p):
     return kin + col
 
 
+def nu_at(p):
+    """MPCD-AT viscosity, Eq. 7, at the MPCD step dt = 1/S."""
+    a = 1.0 / p["refine"]
+    dt = 1.0 / p["substeps"]
+    N = p["ppc"]
+    q = N - 1 + np.exp(-N)
+    return p["kT"] * dt / p["mass"] * (N / q - 0.5) + a * a / (12 * dt) * q / N
+
+
 def analytic(p, y):
     ya = p["ylo"] + p["buf_lo"]
     yb = p["yhi"] - p["buf_hi"]
     ua, ub = lb_poiseuille(p, ya), lb_poiseuille(p, yb)
-    return ua + (ub - ua) * (y - ya) / (yb - ya) + p["g"][0] * (y - ya) * (yb - y) / (2 * nu_srd_2d(p))
+    nu_m = nu_at(p) if p.get("collision", 0) == 1 else nu_srd_2d(p)
+    return ua + (ub - ua) * (y - ya) / (yb - ya) + p["g"][0] * (y - ya) * (yb - y) / (2 * nu_m)
 
 
 def interior_rows(p):
@@ -72,10 +83,11 @@ def profile_u(prof, J):
     return prof[J, 1] / prof[J, 0]
 
 
-def test_longrun_profile_matches_analytic(env):
+@pytest.mark.parametrize("collision", [0, 1], ids=["srd", "mpcd_at"])
+def test_longrun_profile_matches_analytic(env, collision):
     O, lbmpcd = env
     p = W.make(n=(128, 32, 1), tau=0.8, g=(4e-5, 0.0, 0.0), ylo=12, yhi=20, buf_lo=2, buf_hi=2, ppc=10,
-               feedback=0, init_flow=1)
+               feedback=0, init_flow=1, collision=collision)
     sim = lbmpcd.Sim(p)
     sim.step(1000)
     sim.sample(1)
@@ -84,7 +96,9 @@ def test_longrun_profile_matches_analytic(env):
     u = profile_u(sim.profile(), J)
     ua = analytic(p, y)
     err = np.linalg.norm(u - ua) / np.linalg.norm(ua)
-    banner(f"long run vs analytic: rel L2 {err:.4f}; nu_M {nu_srd_2d(p):.4f}; u {np.round(u, 5)}")
+    nu_m = nu_at(p) if collision else nu_srd_2d(p)
+    banner(f"long run vs analytic ({'MPCD-AT' if collision else 'SRD'}): rel L2 {err:.4f}; nu_M {nu_m:.4f}; "
+           f"u {np.round(u, 5)}")
     assert err <= 0.01
 
 
