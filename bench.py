@@ -41,6 +41,8 @@ def workload(name: str) -> list:
     from paper_2004_00304_amd import workloads as W
     if name == "ensemble":
         return W.ensemble(256)
+    if name == "channel_3d_at":
+        return [W.make(**{**W.channel_3d(), "collision": 1})]
     return [{"channel_3d": W.channel_3d, "channel_2d": W.channel_2d, "thin_film_3d": W.thin_film_3d}[name]()]
 
 
@@ -298,7 +300,7 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="channel_3d",
-                    choices=["channel_3d", "channel_2d", "thin_film_3d", "ensemble", "closure"])
+                    choices=["channel_3d", "channel_3d_at", "channel_2d", "thin_film_3d", "ensemble", "closure"])
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with lbmpcd_autotune first (always on for the ensemble)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -368,7 +370,8 @@ def main():
         wl = (f"{args.workload}: {lat} {p['n'][0]}x{p['n'][1]}x{p['n'][2]} tau {p['tau']}, "
               f"slab y[{p['ylo']},{p['yhi']}) buffers {p['buf_lo']}/{p['buf_hi']}, r {p['refine']}, "
               f"{p['ppc']} ppc ({tot['particles']} particles), S {p['substeps']}, "
-              f"SRD {p['alpha_deg']} deg, feedback {p['feedback']}")
+              f"{'MPCD-AT' if p.get('collision', 0) == 1 else 'SRD ' + str(p['alpha_deg']) + ' deg'}, "
+              f"feedback {p['feedback']}")
     out = {
         "metric": "coupled steps/s: LB MLUPS + MPCD particle-updates/s, % HBM roofline",
         "value": sps,
