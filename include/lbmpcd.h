@@ -131,6 +131,19 @@ typedef struct lbmpcd_params {
 int lbmpcd_workspace_size(const lbmpcd_params* p, int32_t n_inst, size_t* bytes);
 
 /*
+ * Kinematic viscosities of one parameter set, in LB units (host only, no
+ * device work): nu_lb = (tau - 1/2) / 3 of the BGK lattice (Sec. 2.1), and
+ * nu_mpcd of the MPCD fluid at its step dt = 1/substeps, cell side
+ * a = 1/refine and N = ppc particles per cell: for MPCD-AT (collision 1)
+ * Eq. 7, kT dt / m [N / (N - 1 + e^-N) - 1/2] + a^2 / (12 dt) (N - 1 + e^-N) / N;
+ * for 2D SRD the kinetic part kT dt / m [N / ((N - 1 + e^-N)(1 - cos 2 alpha))
+ * - 1/2] plus the collisional part a^2 (1 - cos alpha)(N - 1 + e^-N) / (12 dt N)
+ * of the SRD literature (Ihle, Tuzel, Kroll; not in the paper).  3D SRD:
+ * E_UNSUPPORTED.  Either output may be NULL.  E_INVALID for bad parameters.
+ */
+int lbmpcd_viscosity(const lbmpcd_params* p, double* nu_lb, double* nu_mpcd);
+
+/*
  * Initialise n_inst channels in the caller's device workspace (bytes at
  * least lbmpcd_workspace_size) and bind them to hip_stream (a hipStream_t,
  * may be NULL for the default stream).  Particles: exactly ppc per fine cell,

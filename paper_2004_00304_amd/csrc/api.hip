@@ -450,6 +450,25 @@ const char* lbmpcd_strerror(int code) {
 
 const char* lbmpcd_last_error(const lbmpcd_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
+int lbmpcd_viscosity(const lbmpcd_params* p, double* nu_lb, double* nu_mpcd) {
+    std::string msg;
+    if (!p) return fail(nullptr, LBMPCD_E_INVALID, "null parameters");
+    if (int e = validate_one(*p, msg)) return fail(nullptr, e, msg);
+    if (nu_lb) *nu_lb = (p->tau - 0.5) / 3.0;
+    if (!nu_mpcd) return 0;
+    if (!p->mpcd) return fail(nullptr, LBMPCD_E_INVALID, "no MPCD region");
+    const double dt = 1.0 / p->substeps, a = 1.0 / p->refine, N = (double)p->ppc;
+    const double q = N - 1.0 + std::exp(-N), kin = p->kT * dt / p->mass;
+    if (p->collision == 1) {
+        *nu_mpcd = kin * (N / q - 0.5) + a * a / (12.0 * dt) * q / N;  // Eq. 7
+        return 0;
+    }
+    if (p->dim != 2) return fail(nullptr, LBMPCD_E_UNSUPPORTED, "the SRD viscosity is given for 2D only");
+    const double al = p->alpha_deg * 3.14159265358979323846 / 180.0;
+    *nu_mpcd = kin * (N / (q * (1.0 - std::cos(2.0 * al))) - 0.5) + a * a * (1.0 - std::cos(al)) * q / (12.0 * dt * N);
+    return 0;
+}
+
 int lbmpcd_workspace_size(const lbmpcd_params* p, int32_t n_inst, size_t* bytes) {
     if (!bytes) return fail(nullptr, LBMPCD_E_INVALID, "bytes is null");
     std::string msg;

@@ -95,6 +95,8 @@ def _load():
     L.lbmpcd_closure_forward.argtypes = [P, P, C.c_int64, P, P, C.c_size_t]
     L.lbmpcd_closure_features.argtypes = [P, P]
     L.lbmpcd_closure_predict.argtypes = [P, P]
+    L.lbmpcd_viscosity.argtypes = [C.POINTER(Params), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.lbmpcd_viscosity.restype = C.c_int
     L.lbmpcd_closure_weights.argtypes = [P, C.c_int32, P, C.c_size_t]
     L.lbmpcd_closure_enable.argtypes = [P, C.c_int32, C.c_double, C.c_int32, C.c_int32]
     L.lbmpcd_closure_check.argtypes = [P, C.c_int32, C.POINTER(C.c_double)]
@@ -122,7 +124,7 @@ EXPORTED = ("lbmpcd_workspace_size", "lbmpcd_init", "lbmpcd_step", "lbmpcd_momen
             "lbmpcd_closure_collect", "lbmpcd_closure_train", "lbmpcd_closure_loss_grad",
             "lbmpcd_closure_forward", "lbmpcd_closure_weights", "lbmpcd_closure_enable",
             "lbmpcd_closure_check", "lbmpcd_closure_status", "lbmpcd_closure_gemm_bf16",
-            "lbmpcd_closure_features", "lbmpcd_closure_predict")
+            "lbmpcd_closure_features", "lbmpcd_closure_predict", "lbmpcd_viscosity")
 
 # candidate tile sizes of lbmpcd_autotune (expected particles per tile)
 TUNE_TILE_TARGETS = (160, 320, 640, 1280)
@@ -168,6 +170,14 @@ def workspace_size(params) -> int:
     n = C.c_size_t()
     _check(_lib.lbmpcd_workspace_size(C.cast(arr, C.c_void_p), len(plist), C.byref(n)))
     return int(n.value)
+
+
+def viscosity(params) -> tuple:
+    """(nu_lb, nu_mpcd) of one parameter set (lbmpcd_viscosity; host only)."""
+    ps = params_struct(params)
+    nl, nm = C.c_double(), C.c_double()
+    _check(_lib.lbmpcd_viscosity(C.byref(ps), C.byref(nl), C.byref(nm)))
+    return float(nl.value), float(nm.value)
 
 
 def autotune(params, lb_steps: int = 5, device="cuda", stream=None) -> dict:

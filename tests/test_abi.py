@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2004_00304_amd import workloads as W
@@ -128,3 +129,24 @@ def test_autotune_argument_checks(binding):
     rc = lib.lbmpcd_autotune(ctypes.cast(arr, ctypes.c_void_p), 1, None, 0, None, 1, ctypes.byref(out))
     assert rc == 1
     assert b"tile" in lib.lbmpcd_last_error(None)
+
+
+def test_viscosity_matches_eq7_and_the_oracle(binding):
+    """lbmpcd_viscosity (host arithmetic of the library): the LB viscosity of
+    BGK, and for MPCD-AT Eq. 7 at dt = 1/S as the oracle evaluates it; 2D
+    SRD against the formula the long-run test uses; 3D SRD is refused."""
+    from oracle import oracle as O
+    p = W.small_3d(collision=1, kT=0.3, mass=1.5)
+    nl, nm = binding.viscosity(p)
+    assert nl == pytest.approx((p["tau"] - 0.5) / 3.0, rel=1e-15)
+    assert nm == pytest.approx(O.nu_at(p["kT"], p["mass"], 1.0 / p["substeps"], 1.0 / p["refine"], p["ppc"]),
+                               rel=1e-13)
+    q = W.small_2d()
+    _, ns = binding.viscosity(q)
+    a, dt, N, al = 1.0 / q["refine"], 1.0 / q["substeps"], q["ppc"], np.deg2rad(q["alpha_deg"])
+    e = N - 1 + np.exp(-N)
+    ref = q["kT"] * dt / q["mass"] * (N / (e * (1 - np.cos(2 * al))) - 0.5) + a * a * (1 - np.cos(al)) * e / (12 * dt * N)
+    assert ns == pytest.approx(ref, rel=1e-13)
+    with pytest.raises(binding.LbmpcdError) as ex:
+        binding.viscosity(W.small_3d())
+    assert ex.value.code == 6
