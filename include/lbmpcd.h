@@ -7,7 +7,8 @@
  * over the whole channel (Sec. 2.1, Eq. 1-2; BGK with a body force, periodic
  * along x and z, half-way bounce-back walls at y = 0 and y = ny) coupled to a
  * fine MPCD solver in a slab y in [ylo, yhi) (Sec. 2.2, Eq. 3-4: ballistic
- * streaming, random grid shift, cell binning, stochastic rotation).  The two
+ * streaming, random grid shift, cell binning, stochastic rotation; or the
+ * collision with Andersen thermostat of Eq. 6).  The two
  * are joined by the coupling procedure of Alg. 1 and Alg. 2: after each LB
  * step the LB velocity is interpolated to the fine cells of the buffer and
  * the buffer particles are redrawn from the Maxwell-Boltzmann distribution
@@ -159,7 +160,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
  * and stream, optional feedback projection, interpolation of the LB
  * velocity to the buffer cells, then per MPCD step: Maxwell-Boltzmann redraw
  * in the buffer, streaming with wall / periodic / slab re-wrap conditions,
- * random grid shift, binning and SRD collision.  Asynchronous.
+ * random grid shift, binning and the collision (SRD or MPCD-AT).  Asynchronous.
  */
 int lbmpcd_step(struct lbmpcd_ctx* c, int32_t n_lb_steps);
 
