@@ -79,8 +79,17 @@ enum lbmpcd_field {
     LBMPCD_STATS = 11,     /* int64[8]: lb steps, sampled steps, dropped particles,
                               misplaced particles, far moves, max tile fill,
                               particles, cells                                     */
-    LBMPCD_PART_VEL_PENDING = 12 /* double[dim][Np] by id: velocities before the
+    LBMPCD_PART_VEL_PENDING = 12, /* double[dim][Np] by id: velocities before the
                               collision of the last MPCD step (get only)          */
+    LBMPCD_CELL_START = 13, /* int32[ncells]: where each cell of the last binning
+                              starts in the cell order of a stable counting sort
+                              (exclusive prefix sum of CELL_COUNT; the library
+                              keeps particles grouped by tile, not in that order) */
+    LBMPCD_NODE_MPCD_U = 14 /* double[dim][nx*(yhi-ylo)*nz]: mean velocity of the
+                              particles sampled in each slab node (x fastest, then
+                              y - ylo, then z) in the last LB step, the average
+                              the feedback projects; needs feedback 1 (E_STATE
+                              otherwise); 0 where no particle was sampled          */
 };
 
 typedef struct lbmpcd_params {

@@ -759,6 +759,8 @@ int lbmpcd_field_bytes(const lbmpcd_ctx* c, int32_t field, int32_t inst, size_t*
         case LBMPCD_PROFILE: *bytes = (size_t)d.R * 4 * 8; break;
         case LBMPCD_UFINE: *bytes = (size_t)c->dim * d.Cx * d.R * d.Cz * 8; break;
         case LBMPCD_STATS: *bytes = 8 * 8; break;
+        case LBMPCD_CELL_START: *bytes = (size_t)d.ncells * 4; break;
+        case LBMPCD_NODE_MPCD_U: *bytes = (size_t)c->dim * d.nslab * 8; break;
         default: return LBMPCD_E_INVALID;
     }
     return 0;
@@ -810,6 +812,14 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             HIPCHK(c, launch_zero(dst, nbytes, s));
             HIPCHK(c, launch_cell_count(c->dim, c->part_fp, c->d_desc, inst, c->part[c->pcur], c->fill[c->pcur],
                                         (int*)dst, slots, tl, sl, s));
+            return 0;
+        case LBMPCD_CELL_START:
+            if (int e = produce(c, LBMPCD_CELL_COUNT, inst, dst, nbytes)) return e;
+            HIPCHK(c, launch_exclusive_scan((int*)dst, d.ncells, s));
+            return 0;
+        case LBMPCD_NODE_MPCD_U:
+            if (!d.feedback) return fail(c, LBMPCD_E_STATE, "node sample averages are kept only with feedback 1");
+            HIPCHK(c, launch_node_mean(c->acc + d.acc_off * 4, d.nslab, c->dim, (double*)dst, s));
             return 0;
         case LBMPCD_CELL_VCM: {
             if (!c->pending) return fail(c, LBMPCD_E_STATE, "cell velocities exist only right after lbmpcd_step");

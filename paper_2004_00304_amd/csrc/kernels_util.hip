@@ -241,6 +241,54 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Exclusive prefix sum of n ints in place, by one workgroup walking the
+// array in chunks (a diagnostic field; n is the cell count of one channel).
+__global__ void __launch_bounds__(WG) k_exclusive_scan(int* a, long long n) {
+    __shared__ int part[WG];
+    __shared__ int carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (long long c0 = 0; c0 < n; c0 += WG) {
+        const long long i = c0 + tid;
+        const int v = i < n ? a[i] : 0;
+        part[tid] = v;
+        __syncthreads();
+        // Hillis-Steele inclusive scan of the chunk
+        for (int o = 1; o < WG; o <<= 1) {
+            const int add = tid >= o ? part[tid - o] : 0;
+            __syncthreads();
+            part[tid] += add;
+            __syncthreads();
+        }
+        if (i < n) a[i] = carry + part[tid] - v;
+        __syncthreads();
+        if (tid == WG - 1) carry += part[WG - 1];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_exclusive_scan(int* a, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(WG), 0, s, a, n);
+    return hipGetLastError();
+}
+
+// Mean particle velocity per slab node from the per-node sample sums
+// [count, sum v_x, sum v_y, sum v_z]: out[q][node], zero where no particle.
+__global__ void __launch_bounds__(WG) k_node_mean(const double* acc, long long nslab, int dim, double* out) {
+    const long long i = (long long)blockIdx.x * WG + threadIdx.x;
+    if (i >= nslab) return;
+    const double* a = acc + 4 * i;
+    for (int q = 0; q < dim; ++q) out[(long long)q * nslab + i] = a[0] > 0.0 ? a[1 + q] / a[0] : 0.0;
+}
+
+hipError_t launch_node_mean(const double* acc, long long nslab, int dim, double* out, hipStream_t s) {
+    if (nslab <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_node_mean, dim3(nblk(nslab)), dim3(WG), 0, s, acc, nslab, dim, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_profile_reduce(const InstDesc* D, int inst, int R, const double* prof, double* out, hipStream_t s) {
     if (R <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_profile_reduce, dim3(nblk(4LL * R)), dim3(WG), 0, s, D, inst, prof, out);

@@ -77,6 +77,8 @@ hipError_t launch_cell_count(int dim, int part_fp, const InstDesc* D, int inst, 
 hipError_t launch_set_field(int dim, int part_fp, const InstDesc* D, int inst, PartBuf buf, const uint32_t* fill,
                             int which, const double* src, long long slots, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_exclusive_scan(int* a, long long n, hipStream_t s);
+hipError_t launch_node_mean(const double* acc, long long nslab, int dim, double* out, hipStream_t s);
 hipError_t launch_profile_reduce(const InstDesc* D, int inst, int R, const double* prof, double* out,
                                  hipStream_t s);
 

@@ -18,10 +18,10 @@ LIB_PATH = os.path.join(_HERE, "liblbmpcd.so")
 ABI_VERSION = 3
 
 RHO, U, PI, POP, PART_POS, PART_VEL, CELL_ID, CELL_COUNT, CELL_VCM, PROFILE, UFINE, STATS, \
-    PART_VEL_PENDING = range(13)
+    PART_VEL_PENDING, CELL_START, NODE_MPCD_U = range(15)
 FIELD_NAMES = dict(rho=RHO, u=U, pi=PI, pop=POP, pos=PART_POS, vel=PART_VEL, cell_id=CELL_ID,
                    cell_count=CELL_COUNT, cell_vcm=CELL_VCM, profile=PROFILE, ufine=UFINE, stats=STATS,
-                   vel_pending=PART_VEL_PENDING)
+                   vel_pending=PART_VEL_PENDING, cell_start=CELL_START, node_mpcd_u=NODE_MPCD_U)
 ERRORS = {1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_OVERFLOW", 5: "E_STATE", 6: "E_UNSUPPORTED"}
 
 
@@ -315,7 +315,7 @@ class Sim:
             keys = ("lb_steps", "sampled_steps", "dropped", "misplaced", "far_moves", "max_fill",
                     "particles", "cells")
             return dict(zip(keys, (int(x) for x in out)))
-        dtype = torch.int32 if field in (CELL_ID, CELL_COUNT) else torch.float64
+        dtype = torch.int32 if field in (CELL_ID, CELL_COUNT, CELL_START) else torch.float64
         if field == POP:
             dtype = torch.float64 if self.plist[inst]["lb_fp"] == 64 else torch.float32
         out = self._alloc(field, inst, dtype)
@@ -370,6 +370,16 @@ class Sim:
         cell = self.moments(CELL_ID, inst).cpu().numpy()
         count = self.moments(CELL_COUNT, inst).cpu().numpy()
         return dict(cell=cell, count=count, vcm=vcm)
+
+    def cell_start(self, inst=0) -> np.ndarray:
+        """Start of every cell of the last binning in a stable counting sort's order."""
+        return self.moments(CELL_START, inst).cpu().numpy()
+
+    def node_mpcd_u(self, inst=0) -> np.ndarray:
+        """Mean sampled particle velocity per slab node in the last LB step, [dim][nz][ny_slab][nx]."""
+        p = self.plist[inst]
+        return self.moments(NODE_MPCD_U, inst).cpu().numpy().reshape(p["dim"], p["n"][2], p["yhi"] - p["ylo"],
+                                                                      p["n"][0])
 
     def profile(self, inst=0) -> np.ndarray:
         return self.moments(PROFILE, inst).cpu().numpy().reshape(-1, 4)

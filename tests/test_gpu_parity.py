@@ -148,3 +148,31 @@ def test_batched_instances_match_standalone(env):
         rep = compare_state(sim, orc, p, RTOL64, inst=i, binning=bins[i])
         banner(f"batch inst {i}: {rep}")
         assert_parity(rep, RTOL64)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(collision=1)], ids=["srd", "mpcd_at"])
+def test_cell_start_and_node_average(env, kw):
+    """CELL_START equals the oracle's stable counting sort offsets (bit-exact)
+    and NODE_MPCD_U the mean of the oracle's per-step samples pooled over the
+    fine rows of each node (FP64 tolerance)."""
+    O, lbmpcd = env
+    p = W.small_3d(**kw)
+    sim = lbmpcd.Sim(p)
+    orc = O.Oracle(_params(p))
+    sim.step(3)
+    orc.step(3)
+    start = sim.cell_start()
+    b_o = orc.binning()
+    assert np.array_equal(start, b_o["start"])
+    un = sim.node_mpcd_u()  # [dim][nz][nsy][nx]
+    acc = orc.step_acc()     # [nz][R][nx][4] per fine row
+    r = p["refine"]
+    nz, R, nx, _ = acc.shape
+    pooled = acc.reshape(nz, R // r, r, nx, 4).sum(axis=2)
+    cnt = pooled[..., 0]
+    ref = np.where((cnt > 0)[..., None], pooled[..., 1:1 + p["dim"]] / np.maximum(cnt, 1)[..., None], 0.0)
+    ref = np.moveaxis(ref, -1, 0)
+    scale = np.sqrt(p["kT"] / p["mass"])
+    err = np.abs(un - ref).max() / scale
+    banner(f"node averages: max err {err:.2e} of the thermal velocity; cells {start.size}")
+    assert err <= RTOL64
