@@ -133,11 +133,15 @@ int choose_tile(const lbmpcd_params& p, Geometry& g, std::string& msg) {
         // aim at ~1280 expected particles per tile
         const int per_tile = p.tile_target > 0 ? p.tile_target : 1280;
         int target = std::max(8, std::min(MAX_NCT, per_tile / std::max(1, p.ppc)));
-        static const int opts3[][3] = {{2, 2, 2}, {4, 2, 2}, {4, 4, 2}, {4, 4, 4}, {4, 4, 8}};
-        static const int opts2[][3] = {{4, 2, 1}, {4, 4, 1}, {8, 4, 1}, {8, 8, 1}, {16, 8, 1}};
+        // shapes below 8 cells serve only dense cells (hundreds of particles
+        // per cell, as in the paper's runs), whose tiles would overflow
+        static const int opts3[][3] = {{1, 1, 1}, {2, 1, 1}, {2, 2, 1}, {2, 2, 2},
+                                       {4, 2, 2}, {4, 4, 2}, {4, 4, 4}, {4, 4, 8}};
+        static const int opts2[][3] = {{1, 1, 1}, {2, 1, 1}, {2, 2, 1}, {4, 2, 1},
+                                       {4, 4, 1}, {8, 4, 1}, {8, 8, 1}, {16, 8, 1}};
         const int(*opts)[3] = p.dim == 3 ? opts3 : opts2;
-        int pick = 4;
-        for (int i = 0; i < 5; ++i) {
+        int pick = 7;
+        for (int i = 0; i < 8; ++i) {
             if (opts[i][0] * opts[i][1] * opts[i][2] >= target) { pick = i; break; }
         }
         // the next smaller shape when the capacity would exceed the kernel's limit

@@ -1,0 +1,81 @@
+"""The paper's coupled runs (Sec. 3.2 and 3.3, Table 1) on the GPU: MPCD with
+Andersen thermostat at 60 to 1000 particles per cell, one MPCD step per LB
+step, coupled one way to a D2Q9 Poiseuille channel.  The paper shows the
+time-averaged MPCD profile overlapping the LB solution (Fig. 4e) and the
+near-wall MPCD profile on the analytic Poiseuille flow (Fig. 5 inset); the
+figures' data are not in the text, so the checks are against the analytic
+forms:
+  * the MPCD slab between the wall (no slip) and the inner face y_b of its
+    buffer: u(y) = u_LB(y_b) y / y_b + g y (y_b - y) / (2 nu_M), nu_M from
+    Eq. 7 (lbmpcd_viscosity);
+  * the LB Poiseuille profile g y (H - y) / (2 nu) (+ the BGK slip term),
+    which the MPCD profile follows because Table 1 matches nu_M to nu."""
+import numpy as np
+import pytest
+
+from paper_2004_00304_amd import workloads as W
+from tests.gpu_util import banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbmpcd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_00304_amd import lbmpcd as L
+    return L
+
+
+def lb_poiseuille(p, y):
+    H = p["n"][1]
+    tau = p["tau"]
+    nu = (tau - 0.5) / 3.0
+    g = p["g"][0]
+    return g * y * (H - y) / (2 * nu) + g * (16 * tau * tau - 16 * tau + 1) / (24 * nu)
+
+
+def run_profile(lbmpcd, p, warm, steps):
+    sim = lbmpcd.Sim(p)
+    sim.step(warm)
+    sim.sample(1)
+    sim.step(steps)
+    prof = np.asarray(sim.profile()).reshape(-1, 4)
+    st = sim.stats()
+    assert st["dropped"] == 0 and st["misplaced"] == 0
+    return prof[:, 1] / prof[:, 0]
+
+
+def check(lbmpcd, p, u, tol_mpcd, tol_lb, label):
+    r = p["refine"]
+    yb = p["yhi"] - p["buf_hi"]
+    J = np.arange(0, yb * r)
+    y = (J + 0.5) / r
+    nu_m = lbmpcd.viscosity(p)[1]
+    um = lb_poiseuille(p, yb) * y / yb + p["g"][0] * y * (yb - y) / (2 * nu_m)
+    ul = lb_poiseuille(p, y)
+    e_m = np.linalg.norm(u[J] - um) / np.linalg.norm(um)
+    e_l = np.linalg.norm(u[J] - ul) / np.linalg.norm(ul)
+    banner(f"{label}: vs MPCD analytic {e_m:.4f}, vs LB Poiseuille {e_l:.4f}; nu_M {nu_m:.4f}; "
+           f"u {np.round(u[J], 4)}")
+    assert e_m <= tol_mpcd
+    assert e_l <= tol_lb
+
+
+@pytest.mark.parametrize("N", [60, 1000])
+def test_centreline_coupling(lbmpcd, N):
+    """Sec. 3.2: MPCD-AT on the lower half of a 30x30 channel, coupled at
+    the centre line through a two-row buffer."""
+    p = W.paper_centreline(N)
+    u = run_profile(lbmpcd, p, 500, 3000)
+    check(lbmpcd, p, u, 0.02 if N == 1000 else 0.03, 0.03 if N == 1000 else 0.04, f"centre line, N {N}")
+
+
+@pytest.mark.parametrize("a", [1.0, 0.5])
+def test_near_wall_coupling(lbmpcd, a):
+    """Sec. 3.3: the MPCD slab on the wall at the LB's resolution (a = 1) and
+    at twice it (a = 1/2), N = 1000."""
+    p = W.paper_near_wall(a)
+    u = run_profile(lbmpcd, p, 500, 3000)
+    check(lbmpcd, p, u, 0.02, 0.03, f"near wall, a {a}")
