@@ -249,7 +249,8 @@ typedef struct lbmpcd_tuning {
     int32_t wg_threads;    /* chosen workgroup size */
     int32_t tried;         /* candidates measured */
     double ms_per_step;    /* ms per coupled LB step of the chosen candidate */
-    double ms_default;     /* ms per coupled LB step of (1280, 256), -1 if not measured */
+    double ms_default;     /* ms per coupled LB step of the library's default shape (tile
+                              target 1280, its default workgroup), -1 if not measured */
 } lbmpcd_tuning;
 
 int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, size_t bytes,

@@ -1024,10 +1024,12 @@ int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace,
                 rc = e;
                 break;
             }
+            // the shape the library takes with tile_target = wg_threads = 0
+            const int default_wg = (c->part_fp == 64 && c->cap_max > 4 * 256) ? 512 : 256;
             lbmpcd_destroy(c);
             const double per = (double)ms / lb_steps;
             ++out->tried;
-            if (tt == 1280 && wg == 256) out->ms_default = per;
+            if (tt == 1280 && wg == default_wg) out->ms_default = per;
             if (best < 0 || per < best) {
                 best = per;
                 out->tile_target = tt;
