@@ -12,7 +12,8 @@
  *
  * Readings of points the paper leaves open are marked READING and listed in
  * the design notes: lattice weights, Guo forcing, wall positions, random grid
- * shift, substeps, virtual wall particles, sampling instant, feedback.
+ * shift, substeps, virtual wall particles, sampling instant, feedback, and the
+ * Chapman-Enskog form of the exchange step.
  */
 #include "lbmpcd_oracle.h"
 
@@ -89,14 +90,27 @@ void orc_box_muller(double u0, double u1, double* z0, double* z1) {
     *z1 = r * sin(th);
 }
 
-/* d standard normals of one stream element */
-static void rng_normals(const orc_params* p, uint32_t elem, uint32_t t, uint32_t sub,
-                        uint32_t purpose, double z[3]) {
+/* d standard normals of one stream element from the Philox blocks blk and
+ * blk + 1 */
+static void rng_normals_at(const orc_params* p, uint32_t elem, uint32_t t, uint32_t sub,
+                           uint32_t purpose, uint32_t blk, double z[3]) {
+    uint32_t w[4];
     double u[4], dummy;
-    rng_uniforms4(p, elem, t, sub, purpose, u);
+    rng_block(p, elem, t, sub, purpose, blk, w);
+    u[0] = orc_u01(w[0], w[1]);
+    u[1] = orc_u01(w[2], w[3]);
+    rng_block(p, elem, t, sub, purpose, blk + 1, w);
+    u[2] = orc_u01(w[0], w[1]);
+    u[3] = orc_u01(w[2], w[3]);
     orc_box_muller(u[0], u[1], &z[0], &z[1]);
     orc_box_muller(u[2], u[3], &z[2], &dummy);
     if (p->dim == 2) z[2] = 0.0;
+}
+
+/* d standard normals of one stream element */
+static void rng_normals(const orc_params* p, uint32_t elem, uint32_t t, uint32_t sub,
+                        uint32_t purpose, double z[3]) {
+    rng_normals_at(p, elem, t, sub, purpose, 0, z);
 }
 
 /* ------------------------------------------------------------------------
@@ -243,6 +257,74 @@ double orc_nu_at(double kT, double mass, double dt, double a, double N) {
     return kT * dt / mass * (N / q - 0.5) + a * a / (12.0 * dt) * q / N;
 }
 
+/* Kinetic part of the MPCD viscosity (the part carried by the particles'
+ * velocity distribution, which is what the Chapman-Enskog exchange has to
+ * reproduce).  MPCD-AT: the first term of Eq. 7.  SRD (not in the paper; the
+ * SRD literature's kinetic terms): 2D kT dt/m [N/((N-1+e^-N)(1-cos 2 alpha))
+ * - 1/2], 3D kT dt/m [5N/((N-1+e^-N)(4-2cos alpha-2cos 2 alpha)) - 1/2]. */
+double orc_nu_kinetic(const orc_params* p) {
+    if (p->nu_kin > 0.0) return p->nu_kin;
+    const double N = (double)p->ppc, q = N - 1.0 + exp(-N);
+    const double kin = p->kT * (1.0 / p->substeps) / p->mass;
+    if (p->collision == 1) return kin * (N / q - 0.5);
+    const double al = p->alpha_deg * 3.141592653589793 / 180.0;
+    if (p->dim == 2) return kin * (N / (q * (1.0 - cos(2.0 * al))) - 0.5);
+    return kin * (5.0 * N / (q * (4.0 - 2.0 * cos(al) - 2.0 * cos(2.0 * al))) - 0.5);
+}
+
+/* ------------------------------------------------------------------------
+ * Chapman-Enskog exchange (READING; the paper names sampling from an Enskog
+ * distribution, after Garcia and Alexander, as the remedy when velocity
+ * gradients are strong, Sec. 2.3).  To first order in the gradients the
+ * velocity distribution about u is the Maxwellian times 1 - T:zz, with z the
+ * thermal velocity in units of sqrt(kT/m) and T = (nu_kin m / kT) dev S, S the
+ * strain rate; its covariance is (kT/m)(I - 2T), i.e. the kinetic stress
+ * 2 rho nu_kin dev S.  Heat flux is absent (isothermal fluid).  Samples come
+ * by acceptance-rejection against the Maxwellian: attempt k draws z from the
+ * Philox blocks 4k and 4k+1 of the exchange stream (attempt 0 is the
+ * Maxwell-Boltzmann draw itself) and a uniform u from block 4k+2, and accepts
+ * when A u <= 1 - T:zz, with the envelope A = 1 + 30 b, b the largest absolute
+ * row sum of T (a bound on |T:zz| / |z|^2).  After CE_ATTEMPTS rejections the
+ * first attempt's draw is kept.
+ * ---------------------------------------------------------------------- */
+#define CE_ATTEMPTS 32
+#define CE_KAPPA 30.0
+
+/* T:zz with T[6] = (xx, yy, zz, xy, xz, yz) */
+static double ce_contract(const double T[6], const double z[3]) {
+    return T[0] * z[0] * z[0] + T[1] * z[1] * z[1] + T[2] * z[2] * z[2] +
+           2.0 * (T[3] * z[0] * z[1] + T[4] * z[0] * z[2] + T[5] * z[1] * z[2]);
+}
+
+static double ce_envelope(const double T[6]) {
+    double r0 = fabs(T[0]) + fabs(T[3]) + fabs(T[4]);
+    double r1 = fabs(T[3]) + fabs(T[1]) + fabs(T[5]);
+    double r2 = fabs(T[4]) + fabs(T[5]) + fabs(T[2]);
+    double b = fmax(r0, fmax(r1, r2));
+    return 1.0 + CE_KAPPA * b;
+}
+
+int32_t orc_ce_normals(const orc_params* p, uint32_t id, uint32_t t, uint32_t sub, const double T[6],
+                       double z[3]) {
+    const double A = ce_envelope(T);
+    double z0[3];
+    for (int32_t k = 0; k < CE_ATTEMPTS; ++k) {
+        double zk[3];
+        uint32_t w[4];
+        rng_normals_at(p, id, t, sub, P_REINJ, 4u * (uint32_t)k, zk);
+        if (k == 0)
+            for (int d = 0; d < 3; ++d) z0[d] = zk[d];
+        rng_block(p, id, t, sub, P_REINJ, 4u * (uint32_t)k + 2u, w);
+        double u = orc_u01(w[0], w[1]);
+        if (A * u <= 1.0 - ce_contract(T, zk)) {
+            for (int d = 0; d < 3; ++d) z[d] = zk[d];
+            return k;
+        }
+    }
+    for (int d = 0; d < 3; ++d) z[d] = z0[d];
+    return CE_ATTEMPTS;
+}
+
 /* Stable counting sort: histogram, exclusive prefix sum, scatter in input order. */
 void orc_counting_sort(int32_t n, const int32_t* cell, int32_t nc, int32_t* count,
                        int32_t* start, int32_t* order) {
@@ -280,6 +362,8 @@ struct orc_state {
     double* vcm;        /* [3][ncells] */
     double* ufine;      /* [3][Cz][R][Cx] */
     double* unode;      /* [3][N] */
+    double* tnode;      /* [6][N] Chapman-Enskog tensor of every node */
+    double* tfine;      /* [6][Cz][R][Cx] interpolated to the buffer fine cells */
     double* acc;        /* [(iz*R+J)*nx+ix][4] */
     double* prof;       /* [R][4] */
     int64_t prof_steps;
@@ -320,6 +404,8 @@ static int validate(const orc_params* p) {
     if ((bw || tw) && p->g[1] != 0.0) return 1;
     if (!(p->mass > 0.0) || p->kT < 0.0) return 1;
     if (p->collision != 0 && p->collision != 1) return 1;
+    if (p->reinject != 0 && p->reinject != 1) return 1;
+    if (p->reinject && (!(p->kT > 0.0) || !(p->nu_kin >= 0.0))) return 1;
     return 0;
 }
 
@@ -329,6 +415,7 @@ void orc_destroy(orc_state* s) {
     for (int k = 0; k < 3; ++k) { free(s->pos[k]); free(s->vel[k]); }
     free(s->cell_of); free(s->count); free(s->start); free(s->order);
     free(s->vcm); free(s->ufine); free(s->unode); free(s->acc); free(s->prof);
+    free(s->tnode); free(s->tfine);
     free(s->scratch);
     free(s);
 }
@@ -409,13 +496,15 @@ int orc_create(const orc_params* p, orc_state** out) {
         s->start = (int32_t*)calloc((size_t)s->ncells, sizeof(int32_t));
         s->vcm = (double*)calloc((size_t)(3 * s->ncells), sizeof(double));
         s->ufine = (double*)calloc((size_t)(3 * s->Cx * s->R * s->Cz), sizeof(double));
+        s->tnode = (double*)calloc((size_t)(6 * s->N), sizeof(double));
+        s->tfine = (double*)calloc((size_t)(6 * s->Cx * s->R * s->Cz), sizeof(double));
         s->acc = (double*)calloc((size_t)(4 * p->nx * s->R * p->nz), sizeof(double));
         s->prof = (double*)calloc((size_t)(4 * s->R), sizeof(double));
         s->scratch = (double*)malloc(sizeof(double) * 3 * 4096);
         for (int k = 0; k < 3; ++k)
             if (!s->pos[k] || !s->vel[k]) { orc_destroy(s); return 2; }
         if (!s->cell_of || !s->order || !s->count || !s->start || !s->vcm || !s->ufine ||
-            !s->acc || !s->prof || !s->scratch) {
+            !s->acc || !s->prof || !s->scratch || !s->tnode || !s->tfine) {
             orc_destroy(s);
             return 2;
         }
@@ -550,7 +639,35 @@ static void interp_axis(int L, int periodic, double X, int* i0, int* i1, double*
     }
 }
 
-static void interpolate_from(const orc_state* s, const double* unode, double* ufine);
+static void interpolate_from(const orc_state* s, int ncomp, const double* unode, double* ufine);
+
+/* Chapman-Enskog tensor of node n (READING): the strain rate of the BGK
+ * lattice from the non-equilibrium second moment of the post-stream
+ * populations, S = -(sum f c c - rho cs2 I - rho u u) / (2 rho cs2 tau) with
+ * the physical velocity u, its deviatoric part over the d axes, scaled by
+ * nu_kin m / kT.  T[6] = (xx, yy, zz, xy, xz, yz); zero components in 2D. */
+static void node_ce_tensor(const orc_state* s, int64_t n, double T[6]) {
+    static const int ab[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    const orc_params* p = &s->p;
+    const double cs2 = 1.0 / 3.0;
+    double rho, u[3];
+    node_moments(s, n, &rho, u);
+    double S[6];
+    for (int m = 0; m < 6; ++m) {
+        int a = ab[m][0], b = ab[m][1];
+        double pi = 0.0;
+        for (int i = 0; i < s->Q; ++i) pi += s->f[i * s->N + n] * (double)(s->c[3 * i + a] * s->c[3 * i + b]);
+        double pneq = pi - (a == b ? rho * cs2 : 0.0) - rho * u[a] * u[b];
+        S[m] = -pneq / (2.0 * rho * cs2 * p->tau);
+    }
+    if (p->dim == 2) S[2] = S[4] = S[5] = 0.0;
+    double tr = (S[0] + S[1] + S[2]) / (double)p->dim;
+    S[0] -= tr;
+    S[1] -= tr;
+    if (p->dim == 3) S[2] -= tr;
+    double c = orc_nu_kinetic(p) * p->mass / p->kT;
+    for (int m = 0; m < 6; ++m) T[m] = c * S[m];
+}
 
 static void interpolate_buffers(orc_state* s) {
     for (int64_t n = 0; n < s->N; ++n) {
@@ -558,11 +675,20 @@ static void interpolate_buffers(orc_state* s) {
         node_moments(s, n, &rho, u);
         for (int k = 0; k < 3; ++k) s->unode[k * s->N + n] = u[k];
     }
-    interpolate_from(s, s->unode, s->ufine);
+    interpolate_from(s, s->p.dim, s->unode, s->ufine);
+    if (s->p.reinject) {
+        for (int64_t n = 0; n < s->N; ++n) {
+            double T[6];
+            node_ce_tensor(s, n, T);
+            for (int m = 0; m < 6; ++m) s->tnode[m * s->N + n] = T[m];
+        }
+        interpolate_from(s, 6, s->tnode, s->tfine);
+    }
 }
 
-/* buffer fine-cell velocities ufine[3][Cz][R][Cx] from node velocities unode[3][N] */
-static void interpolate_from(const orc_state* s, const double* unode, double* ufine) {
+/* buffer fine-cell values ufine[ncomp][Cz][R][Cx] of the node fields unode[ncomp][N]
+ * (the velocity, ncomp = d, or the Chapman-Enskog tensor, ncomp = 6) */
+static void interpolate_from(const orc_state* s, int ncomp, const double* unode, double* ufine) {
     const orc_params* p = &s->p;
     int r = p->refine;
     int64_t nf = (int64_t)s->Cx * s->R * s->Cz;
@@ -582,7 +708,7 @@ static void interpolate_from(const orc_state* s, const double* unode, double* uf
                 else {
                     iz[0] = 0; iz[1] = 0; wz[0] = 1.0; wz[1] = 0.0;
                 }
-                for (int k = 0; k < p->dim; ++k) {
+                for (int k = 0; k < ncomp; ++k) {
                     double val[2] = {0.0, 0.0};
                     for (int c = 0; c < (p->dim == 3 ? 2 : 1); ++c) {
                         double row[2];
@@ -625,13 +751,17 @@ static int64_t buffer_cell(const orc_state* s, const double r[3]) {
     return ((int64_t)K * s->R + J) * s->Cx + I;
 }
 
-/* redraw one buffer particle about the LB velocity u of its fine cell */
+/* redraw one buffer particle about the LB velocity u of its fine cell; with
+ * the Chapman-Enskog exchange T is the cell's tensor (NULL otherwise) */
 static void reinject_one(const orc_state* s, uint32_t id, uint32_t t, uint32_t sub, const double u[3],
-                         double v[3]) {
+                         const double* T, double v[3]) {
     const orc_params* p = &s->p;
     double sd = sqrt(p->kT / p->mass);
     double z[3];
-    rng_normals(p, id, t, sub, P_REINJ, z);
+    if (p->reinject && T)
+        orc_ce_normals(p, id, t, sub, T, z);
+    else
+        rng_normals(p, id, t, sub, P_REINJ, z);
     for (int d = 0; d < p->dim; ++d) v[d] = st(s, u[d] + sd * z[d]);
 }
 
@@ -641,9 +771,10 @@ static void reinject(orc_state* s, uint32_t t, uint32_t sub) {
         double r[3] = {s->pos[0][k], s->pos[1][k], s->pos[2][k]};
         int64_t fc = buffer_cell(s, r);
         if (fc < 0) continue;
-        double u[3] = {0.0, 0.0, 0.0}, v[3];
+        double u[3] = {0.0, 0.0, 0.0}, v[3], T[6];
         for (int d = 0; d < s->p.dim; ++d) u[d] = s->ufine[d * nf + fc];
-        reinject_one(s, (uint32_t)k, t, sub, u, v);
+        for (int m = 0; m < 6; ++m) T[m] = s->tfine[m * nf + fc];
+        reinject_one(s, (uint32_t)k, t, sub, u, T, v);
         for (int d = 0; d < s->p.dim; ++d) s->vel[d][k] = v[d];
     }
 }
@@ -1020,15 +1151,16 @@ void orc_bin_positions(const orc_state* s, const double sh[3], int64_t n, const 
 /* Exchange step (buffer particles redrawn about u, given per particle) and
  * streaming of one MPCD step, in place. */
 void orc_exchange_stream(const orc_state* s, uint32_t t, uint32_t sub, int64_t n, const uint32_t* ids,
-                         double* pos, double* vel, const double* u) {
+                         double* pos, double* vel, const double* u, const double* tens) {
     for (int64_t k = 0; k < n; ++k) {
-        double r[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0}, uu[3] = {0.0, 0.0, 0.0};
+        double r[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0}, uu[3] = {0.0, 0.0, 0.0}, T[6];
         for (int d = 0; d < s->p.dim; ++d) {
             r[d] = pos[d * n + k];
             v[d] = vel[d * n + k];
             uu[d] = u[d * n + k];
         }
-        if (buffer_cell(s, r) >= 0) reinject_one(s, ids[k], t, sub, uu, v);
+        for (int m = 0; m < 6; ++m) T[m] = tens ? tens[m * n + k] : 0.0;
+        if (buffer_cell(s, r) >= 0) reinject_one(s, ids[k], t, sub, uu, tens ? T : NULL, v);
         stream_one(s, r, v);
         for (int d = 0; d < s->p.dim; ++d) {
             pos[d * n + k] = r[d];
@@ -1057,5 +1189,17 @@ void orc_collide_cell(const orc_state* s, int32_t c, uint32_t t, uint32_t sub, c
  * given node velocities [3][N] (bi/trilinear interpolation, Alg. 2). */
 void orc_interpolate(const orc_state* s, const double* unode, double* ufine) {
     memset(ufine, 0, sizeof(double) * 3 * (size_t)s->Cx * s->R * s->Cz);
-    interpolate_from(s, unode, ufine);
+    interpolate_from(s, s->p.dim, unode, ufine);
+}
+
+void orc_ce_tensor(const orc_state* s, double* out) {
+    for (int64_t n = 0; n < s->N; ++n) {
+        double T[6];
+        node_ce_tensor(s, n, T);
+        for (int m = 0; m < 6; ++m) out[m * s->N + n] = T[m];
+    }
+}
+
+void orc_get_tfine(const orc_state* s, double* tfine) {
+    memcpy(tfine, s->tfine, sizeof(double) * 6 * (size_t)s->Cx * s->R * s->Cz);
 }

@@ -50,6 +50,11 @@ typedef struct orc_params {
     uint64_t seed;
     uint32_t instance;
     int32_t collision;      /* 0: SRD rotation (Eq. 4); 1: MPCD with Andersen thermostat (Eq. 6) */
+    int32_t reinject;       /* exchange step: 0 Maxwell-Boltzmann (Sec. 2.3); 1 first-order
+                               Chapman-Enskog about the LB strain rate (the remedy the paper
+                               names for strong gradients, Sec. 2.3) */
+    double nu_kin;          /* kinetic viscosity that sets the Chapman-Enskog stress; 0: the
+                               kinetic part of the collision rule's viscosity */
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -99,9 +104,10 @@ void orc_grid_shift(const orc_state* s, uint32_t t, uint32_t sub, double sh[3]);
 /* shifted-grid cell of n positions pos[dim][n] */
 void orc_bin_positions(const orc_state* s, const double sh[3], int64_t n, const double* pos, int32_t* cell);
 /* exchange step + streaming of one MPCD step for n particles in place; u[dim][n]
- * is the interpolated LB velocity of each particle's fine cell */
+ * is the interpolated LB velocity of each particle's fine cell and tens[6][n]
+ * its Chapman-Enskog tensor (NULL: Maxwell-Boltzmann exchange) */
 void orc_exchange_stream(const orc_state* s, uint32_t t, uint32_t sub, int64_t n, const uint32_t* ids,
-                         double* pos, double* vel, const double* u);
+                         double* pos, double* vel, const double* u, const double* tens);
 int32_t orc_in_buffer(const orc_state* s, const double r[3]);
 /* buffer fine-cell velocities ufine[3][Cz][R][Cx] from node velocities unode[3][N] */
 void orc_interpolate(const orc_state* s, const double* unode, double* ufine);
@@ -133,6 +139,20 @@ void orc_at_collide(int32_t dim, int32_t n, double* vel, const double* vran, con
 /* kinematic viscosity of MPCD-AT (Eq. 7): kT dt / m [N / (N - 1 + e^-N) - 1/2]
  * + a^2 / (12 dt) (N - 1 + e^-N) / N */
 double orc_nu_at(double kT, double mass, double dt, double a, double N);
+/* kinetic part of the MPCD viscosity of the parameter set (the Chapman-Enskog
+ * reinjection's default): MPCD-AT the first term of Eq. 7; SRD the kinetic
+ * term of the SRD literature in 2D and 3D */
+double orc_nu_kinetic(const orc_params* p);
+/* Chapman-Enskog tensor T[6] (xx,yy,zz,xy,xz,yz) of every node from the
+ * current populations: out[6][N] */
+void orc_ce_tensor(const orc_state* s, double* out);
+/* buffer fine-cell tensors tfine[6][Cz][R][Cx] of the last exchange step */
+void orc_get_tfine(const orc_state* s, double* tfine);
+/* d standard normals of element `id` accepted against the Maxwellian with the
+ * weight 1 - T:zz (T[6] as above); returns the attempt that was accepted
+ * (CE_ATTEMPTS when none was, and z is then the first attempt's draw) */
+int32_t orc_ce_normals(const orc_params* p, uint32_t id, uint32_t t, uint32_t sub, const double T[6],
+                       double z[3]);
 /* stable counting sort of cell ids: count[nc], start[nc], order[n] */
 void orc_counting_sort(int32_t n, const int32_t* cell, int32_t nc,
                        int32_t* count, int32_t* start, int32_t* order);

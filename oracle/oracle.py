@@ -40,6 +40,7 @@ class _Params(C.Structure):
         ("mass", C.c_double), ("kT", C.c_double), ("alpha_deg", C.c_double),
         ("grid_shift", C.c_int32), ("feedback", C.c_int32), ("init_flow", C.c_int32),
         ("seed", C.c_uint64), ("instance", C.c_uint32), ("collision", C.c_int32),
+        ("reinject", C.c_int32), ("nu_kin", C.c_double),
     ]
 
 
@@ -88,6 +89,12 @@ def lib():
         L.orc_at_collide.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_double, P]
         L.orc_nu_at.argtypes = [C.c_double] * 5
         L.orc_nu_at.restype = C.c_double
+        L.orc_nu_kinetic.argtypes = [C.POINTER(_Params)]
+        L.orc_nu_kinetic.restype = C.c_double
+        L.orc_ce_tensor.argtypes = [P, P]
+        L.orc_get_tfine.argtypes = [P, P]
+        L.orc_ce_normals.argtypes = [C.POINTER(_Params), C.c_uint32, C.c_uint32, C.c_uint32, P, P]
+        L.orc_ce_normals.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -111,6 +118,8 @@ def params_struct(p: dict) -> _Params:
     s.grid_shift, s.feedback, s.init_flow = p["grid_shift"], p["feedback"], p["init_flow"]
     s.seed, s.instance = p["seed"], p["instance"]
     s.collision = int(p.get("collision", 0))
+    s.reinject = int(p.get("reinject", 0))
+    s.nu_kin = float(p.get("ce_nu_kin", 0.0))
     return s
 
 
@@ -217,6 +226,24 @@ class Oracle:
     def refresh_ufine(self):
         self._L.orc_refresh_ufine(self._h)
 
+    def ce_tensor(self) -> np.ndarray:
+        """Chapman-Enskog tensor of every node from the current populations,
+        [6][nz][ny][nx] (xx, yy, zz, xy, xz, yz)."""
+        out = np.empty((6,) + self.shape(), np.float64)
+        self._L.orc_ce_tensor(self._h, _ptr(out))
+        return out
+
+    def tfine(self) -> np.ndarray:
+        """Chapman-Enskog tensor of the buffer fine cells of the last exchange
+        step, [6][Cz][R][Cx]."""
+        p = self.p
+        r = p["refine"]
+        Cx = p["n"][0] * r
+        Cz = p["n"][2] * r if self.dim == 3 else 1
+        out = np.empty((6, Cz, self.R, Cx), np.float64)
+        self._L.orc_get_tfine(self._h, _ptr(out))
+        return out
+
     def profile(self):
         acc = np.empty((self.R, 4), np.float64)
         n = C.c_int64()
@@ -304,6 +331,29 @@ def nu_at(kT, mass, dt, a, N):
     return float(lib().orc_nu_at(float(kT), float(mass), float(dt), float(a), float(N)))
 
 
+def nu_kinetic(p: dict) -> float:
+    """Kinetic part of the MPCD viscosity of a parameter set (or its ce_nu_kin)."""
+    ps = params_struct(p)
+    return float(lib().orc_nu_kinetic(C.byref(ps)))
+
+
+def ce_normals(p: dict, ids, t: int, sub: int, T) -> tuple:
+    """Chapman-Enskog exchange deviates (in units of sqrt(kT/m)) of the
+    elements ids for the tensor T[6]: returns z [3][n] and the accepted
+    attempt of each element."""
+    ps = params_struct(p)
+    T = np.ascontiguousarray(T, np.float64)
+    ids = np.asarray(ids, np.uint32)
+    z = np.empty((3, len(ids)))
+    att = np.empty(len(ids), np.int32)
+    zz = np.empty(3)
+    L = lib()
+    for i, e in enumerate(ids):
+        att[i] = L.orc_ce_normals(C.byref(ps), int(e), int(t), int(sub), _ptr(T), _ptr(zz))
+        z[:, i] = zz
+    return z, att
+
+
 def counting_sort(cell, nc):
     cell = np.ascontiguousarray(cell, np.int32)
     count = np.empty(nc, np.int32)
@@ -327,7 +377,7 @@ class Probe:
             L.orc_create_geometry.restype = C.c_int
             L.orc_grid_shift.argtypes = [P, C.c_uint32, C.c_uint32, P]
             L.orc_bin_positions.argtypes = [P, P, C.c_int64, P, P]
-            L.orc_exchange_stream.argtypes = [P, C.c_uint32, C.c_uint32, C.c_int64, P, P, P, P]
+            L.orc_exchange_stream.argtypes = [P, C.c_uint32, C.c_uint32, C.c_int64, P, P, P, P, P]
             L.orc_in_buffer.argtypes = [P, P]
             L.orc_in_buffer.restype = C.c_int32
             L.orc_collide_cell.argtypes = [P, C.c_int32, C.c_uint32, C.c_uint32, P, C.c_int32, P, P, P]
@@ -361,12 +411,16 @@ class Probe:
         self._L.orc_bin_positions(self._h, _ptr(sh), n, _ptr(pos), _ptr(out))
         return out
 
-    def exchange_stream(self, t, sub, ids, pos, vel, u):
+    def exchange_stream(self, t, sub, ids, pos, vel, u, tens=None):
         ids = np.ascontiguousarray(ids, np.uint32)
         pos = np.ascontiguousarray(pos, np.float64).copy()
         vel = np.ascontiguousarray(vel, np.float64).copy()
         u = np.ascontiguousarray(u, np.float64)
-        self._L.orc_exchange_stream(self._h, t, sub, len(ids), _ptr(ids), _ptr(pos), _ptr(vel), _ptr(u))
+        tp = None
+        if tens is not None:
+            tens = np.ascontiguousarray(tens, np.float64)
+            tp = _ptr(tens)
+        self._L.orc_exchange_stream(self._h, t, sub, len(ids), _ptr(ids), _ptr(pos), _ptr(vel), _ptr(u), tp)
         return pos, vel
 
     def in_buffer(self, r) -> bool:

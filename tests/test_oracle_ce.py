@@ -1,0 +1,147 @@
+"""Pins of the oracle's Chapman-Enskog exchange step: the reinjection from a
+first-order Chapman-Enskog distribution about the LB strain rate, which the
+paper names (after Garcia and Alexander) as the remedy for strong velocity
+gradients at the end of Sec. 2.3.
+
+What fixes each part, independently of the oracle's own code:
+* the strain rate of the lattice on the exact discrete steady state of the
+  body-force channel, whose shear rate is the derivative of the closed-form
+  profile, g (H - 2y) / (2 nu), and whose other strain components vanish up
+  to the lattice's O(g u) terms;
+* the sampled distribution: the Maxwellian times 1 - T:zz has mean zero and
+  covariance I - 2T exactly (fourth moments of the unit Gaussian), so sample
+  moments must agree within their standard errors; acceptance-rejection with
+  envelope A takes A attempts on average;
+* T = 0 is the Maxwell-Boltzmann exchange itself, draw for draw;
+* the kinetic viscosity is Eq. 7 without its collisional term.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2004_00304_amd import workloads as W
+
+
+def _lb_channel(dim, tau, g, ny=16):
+    n = (8, ny, 4) if dim == 3 else (8, ny, 1)
+    return W.make(dim=dim, n=n, tau=tau, g=(g, 0.0, 0.0), mpcd=0, init_flow=1, feedback=0,
+                  reinject=1, alpha_deg=120.0 if dim == 3 else 130.0)
+
+
+@pytest.mark.parametrize("dim,tau", [(2, 0.7), (2, 1.0), (3, 0.8)])
+def test_strain_of_the_discrete_poiseuille_state(dim, tau):
+    g, ny = 1e-5, 16
+    p = _lb_channel(dim, tau, g, ny)
+    o = O.Oracle(p)
+    o.step(6000)  # the slowest mode decays as exp(-pi^2 nu t / H^2): converged to ~1e-12
+    T = o.ce_tensor()
+    nu = (tau - 0.5) / 3.0
+    y = np.arange(ny) + 0.5
+    dudy = g * (ny - 2 * y) / (2 * nu)
+    c = O.nu_kinetic(p) * p["mass"] / p["kT"]
+    want_xy = c * 0.5 * dudy  # S_xy = du/dy / 2; the trace of S vanishes
+    scale = np.abs(want_xy).max()
+    got_xy = T[3]  # [nz][ny][nx]
+    assert np.abs(got_xy - want_xy[None, :, None]).max() <= 1e-7 * scale
+    # the other components are the lattice's O(g u) terms only
+    for m in (0, 1, 2, 4, 5):
+        assert np.abs(T[m]).max() <= 2e-3 * scale, m
+    # traceless over the d axes
+    tr = T[0] + T[1] + (T[2] if dim == 3 else 0.0)
+    assert np.abs(tr).max() <= 1e-15 * max(scale, 1e-300) + 1e-22
+
+
+def _traceless(dim, rng, amp):
+    A = rng.uniform(-amp, amp, (3, 3))
+    A = 0.5 * (A + A.T)
+    if dim == 2:
+        A[2, :] = 0.0
+        A[:, 2] = 0.0
+    A -= np.trace(A) / dim * np.diag([1.0, 1.0, 1.0 if dim == 3 else 0.0])
+    return A, np.array([A[0, 0], A[1, 1], A[2, 2], A[0, 1], A[0, 2], A[1, 2]])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sampler_moments_and_attempts(dim):
+    p = W.make(dim=dim, n=(8, 16, 4 if dim == 3 else 1), reinject=1)
+    rng = np.random.default_rng(5)
+    A, T6 = _traceless(dim, rng, 0.04)
+    n = 120_000
+    z, att = O.ce_normals(p, np.arange(n), 3, 1, T6)
+    z = z[:dim]
+    assert np.all(att < 32)
+    mean = z.mean(axis=1)
+    assert np.all(np.abs(mean) <= 5.0 / np.sqrt(n)), mean
+    cov = z @ z.T / n
+    want = np.eye(dim) - 2.0 * A[:dim, :dim]
+    se = np.sqrt((1.0 + np.eye(dim)) / n)  # standard error of a Gaussian second moment
+    assert np.all(np.abs(cov - want) <= 5.0 * se), (cov, want)
+    # a sign or factor slip in T would move the covariance by at least 2 |T|
+    assert np.abs(2.0 * A[:dim, :dim]).max() > 10.0 * se.max()
+    # envelope A = 1 + 30 b, b the largest absolute row sum: attempts ~ geometric with mean A
+    b = np.abs(A).sum(axis=1).max()
+    Aenv = 1.0 + 30.0 * b
+    tries = (att + 1).astype(np.float64)
+    sd = np.sqrt(Aenv * (Aenv - 1.0) / n)
+    assert abs(tries.mean() - Aenv) <= 5.0 * sd, (tries.mean(), Aenv)
+
+
+def test_zero_tensor_draws_are_the_maxwell_boltzmann_draws():
+    p = W.make(dim=3, n=(8, 16, 4), reinject=1)
+    ids = np.arange(2000)
+    z, att = O.ce_normals(p, ids, 7, 2, np.zeros(6))
+    assert np.all(att == 0)
+    # the same stream through the exchange step of a Maxwell-Boltzmann probe:
+    # a particle at rest in the lower buffer, u = 0, unit thermal speed
+    q = W.make(dim=3, n=(8, 16, 4), ylo=4, yhi=12, buf_lo=2, buf_hi=2, kT=1.0, mass=1.0,
+               g=(0.0, 0.0, 0.0), substeps=1)
+    pr = O.Probe(q)
+    pos = np.tile(np.array([[1.1], [4.3], [1.7]]), (1, len(ids)))
+    vel = np.zeros((3, len(ids)))
+    _, v = pr.exchange_stream(7, 2, ids.astype(np.uint32), pos, vel, np.zeros((3, len(ids))))
+    assert np.array_equal(v, z)
+
+
+def test_zero_strain_run_equals_maxwell_boltzmann_run():
+    base = dict(dim=2, n=(16, 16, 1), ylo=4, yhi=12, ppc=5, g=(0.0, 0.0, 0.0), feedback=0)
+    a = O.Oracle(W.make(**base, reinject=0))
+    b = O.Oracle(W.make(**base, reinject=1))
+    a.step(3)
+    b.step(3)
+    pa, va = a.particles()
+    pb, vb = b.particles()
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+
+
+def test_nonzero_strain_changes_only_buffer_draws():
+    """With a sheared LB the Chapman-Enskog exchange rejects some Maxwellian
+    draws; the tensor of the buffer cells is the interpolated node tensor."""
+    base = dict(dim=2, n=(16, 16, 1), ylo=4, yhi=12, ppc=5, g=(1e-4, 0.0, 0.0), init_flow=1,
+                feedback=0, tau=0.8, ce_nu_kin=2.0)
+    b = O.Oracle(W.make(**base, reinject=1))
+    b.step(1)
+    tf = b.tfine()
+    # the exchange used the tensor of the populations after the step's LB
+    # update, which the one-way coupling leaves as they are
+    tn = b.ce_tensor()
+    pr = O.Probe(W.make(**base, reinject=1))
+    got = np.stack([pr.interpolate(np.stack([tn[m], tn[m], tn[m]]))[0] for m in range(6)])
+    r, R = 4, (base["yhi"] - base["ylo"]) * 4
+    rows = np.r_[0:2 * r, R - 2 * r:R]  # the two buffers, two LB rows each
+    assert np.array_equal(tf[:, :, rows], got[:, :, rows])
+    # and the draws differ from the Maxwell-Boltzmann ones only in the buffers
+    a = O.Oracle(W.make(**base, reinject=0))
+    a.step(1)
+    assert not np.array_equal(a.particles()[1], b.particles()[1])
+    assert np.abs(tf[3][:, rows]).max() > 1e-4
+
+
+def test_kinetic_viscosity_is_eq7_without_the_collisional_term():
+    for N in (5, 10, 20, 80):
+        p = W.make(collision=1, ppc=N)
+        dt, a = 1.0 / p["substeps"], 1.0 / p["refine"]
+        q = N - 1.0 + np.exp(-N)
+        coll = a * a / (12.0 * dt) * q / N
+        full = O.nu_at(p["kT"], p["mass"], dt, a, N)
+        assert abs(O.nu_kinetic(p) + coll - full) <= 1e-15 * full
+    assert O.nu_kinetic(W.make(ce_nu_kin=0.25)) == 0.25
