@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LBMPCD_ABI_VERSION 3u
+#define LBMPCD_ABI_VERSION 4u
 
 enum lbmpcd_status {
     LBMPCD_OK = 0,
@@ -85,11 +85,15 @@ enum lbmpcd_field {
                               starts in the cell order of a stable counting sort
                               (exclusive prefix sum of CELL_COUNT; the library
                               keeps particles grouped by tile, not in that order) */
-    LBMPCD_NODE_MPCD_U = 14 /* double[dim][nx*(yhi-ylo)*nz]: mean velocity of the
+    LBMPCD_NODE_MPCD_U = 14, /* double[dim][nx*(yhi-ylo)*nz]: mean velocity of the
                               particles sampled in each slab node (x fastest, then
                               y - ylo, then z) in the last LB step, the average
                               the feedback projects; needs feedback 1 (E_STATE
                               otherwise); 0 where no particle was sampled          */
+    LBMPCD_TFINE = 15      /* double[6][nz*r][R][nx*r]: the Chapman-Enskog tensor T of
+                              each buffer cell (xx yy zz xy xz yz; zero outside the
+                              buffers) of the last exchange step; needs reinject 1
+                              (E_STATE otherwise)                                  */
 };
 
 typedef struct lbmpcd_params {
@@ -128,6 +132,21 @@ typedef struct lbmpcd_params {
                               All instances of a context must agree. */
     int32_t closure;       /* 1: reserve the learned closure (lbmpcd_closure_*); needs
                               dim 3, mpcd and a single channel */
+    int32_t reinject;      /* exchange step (Sec. 2.3) in the buffer cells: 0 the paper's
+                              Maxwell-Boltzmann draw about the interpolated LB velocity; 1 a
+                              first-order Chapman-Enskog draw about it, the remedy Sec. 2.3
+                              names for strong gradients: the Maxwellian times 1 - T:z z,
+                              z the thermal velocity in units of sqrt(kT/m), T = (nu m/kT)
+                              dev S with S = -(sum f c c - rho I/3 - rho u u)/(2 rho tau/3)
+                              the lattice's strain rate, interpolated like u; sampled by
+                              acceptance-rejection against the Maxwellian (envelope
+                              1 + 30 x the largest absolute row sum of T, at most 32
+                              attempts, else the first attempt's draw).  Needs kT > 0;
+                              all instances of a context share it */
+    double ce_nu_kin;      /* nu of the Chapman-Enskog stress (> 0), or 0: the kinetic part
+                              of the collision rule's viscosity (MPCD-AT: Eq. 7's first
+                              term; SRD: kT dt/m [N/((N-1+e^-N)(1-cos 2a)) - 1/2] in 2D,
+                              kT dt/m [5N/((N-1+e^-N)(4-2cos a-2cos 2a)) - 1/2] in 3D) */
 } lbmpcd_params;
 
 /*

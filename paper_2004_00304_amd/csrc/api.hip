@@ -36,6 +36,8 @@ struct lbmpcd_ctx {
     uint32_t* fill[2] = {nullptr, nullptr};
     double* ub = nullptr;
     double* uf = nullptr;
+    double* tb = nullptr;         // [6][band nodes] Chapman-Enskog tensor (reinject 1)
+    double* tf = nullptr;         // [6][buffer cells] the same, interpolated
     double* acc = nullptr;
     double* prof = nullptr;
     double* shifts = nullptr;   // [n_inst][2][S][3] grid shifts drawn by the LB kernel
@@ -50,6 +52,7 @@ struct lbmpcd_ctx {
     int cap_max = 0;              // largest tile capacity
     int wg_threads = 0;           // particle kernel workgroup size
     int coll_bit = 0;             // 4 for the MPCD-AT collision (particle kernel mode bit)
+    int ce_bit = 0;               // 8 for the Chapman-Enskog exchange (particle kernel mode bit)
     int xcd_blocked = 1;          // XCD-blocked tile order of the particle kernel
     long long cstride = 0;        // bytes between the component arrays of a particle buffer
     long long t = 0;
@@ -225,6 +228,9 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     if ((bw && p.buf_lo) || (tw && p.buf_hi)) { msg = "a wall face has no buffer"; return LBMPCD_E_INVALID; }
     if ((bw || tw) && p.g[1] != 0.0) { msg = "walls in the slab need g_y = 0"; return LBMPCD_E_INVALID; }
     if (!(p.mass > 0.0) || p.kT < 0.0) { msg = "mass must be positive, kT non-negative"; return LBMPCD_E_INVALID; }
+    if (p.reinject != 0 && p.reinject != 1) { msg = "reinject must be 0 or 1"; return LBMPCD_E_INVALID; }
+    if (!(p.ce_nu_kin >= 0.0) || !std::isfinite(p.ce_nu_kin)) { msg = "ce_nu_kin must be finite and non-negative"; return LBMPCD_E_INVALID; }
+    if (p.reinject && !(p.kT > 0.0)) { msg = "the Chapman-Enskog exchange needs kT > 0"; return LBMPCD_E_INVALID; }
     const bool ywrap = !p.walls_y && p.ylo == 0 && p.yhi == p.n[1] && p.buf_lo == 0 && p.buf_hi == 0;
     if (!p.walls_y && !ywrap && (p.ylo < 1 || p.yhi > p.n[1] - 1)) {
         msg = "without walls the slab must be the whole periodic box or stay one row clear of y = 0, ny";
@@ -236,8 +242,20 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     return 0;
 }
 
+// Kinetic part of the MPCD viscosity, the stress the Chapman-Enskog exchange
+// reproduces: MPCD-AT Eq. 7's first term; SRD the kinetic terms of the SRD
+// literature (2D and 3D).  ce_nu_kin > 0 overrides it.
+double nu_kinetic(const lbmpcd_params& p) {
+    if (p.ce_nu_kin > 0.0) return p.ce_nu_kin;
+    const double N = (double)p.ppc, q = N - 1.0 + std::exp(-N), kin = p.kT / p.substeps / p.mass;
+    if (p.collision == 1) return kin * (N / q - 0.5);
+    const double al = p.alpha_deg * 3.14159265358979323846 / 180.0;
+    if (p.dim == 2) return kin * (N / (q * (1.0 - std::cos(2.0 * al))) - 0.5);
+    return kin * (5.0 * N / (q * (4.0 - 2.0 * std::cos(al) - 2.0 * std::cos(2.0 * al))) - 0.5);
+}
+
 struct Layout {
-    size_t desc, tile_inst, f0, f1, ub, uf, acc, prof, fill0, fill1, stats, clock, shifts, scratch, end;
+    size_t desc, tile_inst, f0, f1, ub, uf, tb, tf, acc, prof, fill0, fill1, stats, clock, shifts, scratch, end;
     size_t cl_P, cl_Pb, cl_Pf, cl_G, cl_m, cl_v, cl_stats, cl_sums, cl_loss, cl_facc, cl_nm, cl_uc, cl_inf;
     size_t part[2];       // particle buffer: 2 dim component arrays of cstride bytes, then ids
     size_t cstride;
@@ -285,6 +303,8 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
         d.key0 = (uint32_t)(q.seed & 0xFFFFFFFFu);
         d.key1 = (uint32_t)(q.seed >> 32) ^ q.instance;
         d.S = q.mpcd ? q.substeps : 0;
+        d.ce = (q.mpcd && q.reinject) ? 1 : 0;
+        d.ce_scale = d.ce ? nu_kinetic(q) * q.mass / q.kT / (2.0 * q.tau / 3.0) : 0.0;
         node += d.N;
         band += g.nband;
         ufine += g.nufine;
@@ -310,6 +330,9 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
     L.f1 = take((size_t)Q * node * lbw);
     L.ub = take(3 * (size_t)band * 8);
     L.uf = take((size_t)dim * ufine * 8);
+    const bool ce = p[0].mpcd && p[0].reinject;
+    L.tb = take(ce ? (size_t)CE_NT * band * 8 : 0);
+    L.tf = take(ce ? (size_t)CE_NT * ufine * 8 : 0);
     L.acc_bytes = 4 * (size_t)slab * 8;
     L.acc = take(L.acc_bytes);
     L.prof_bytes = 4 * (size_t)prow * 8;
@@ -352,8 +375,9 @@ int validate_all(const lbmpcd_params* p, int n, std::string& msg) {
             msg = "all instances must share dim, lb_fp, mpcd, part_fp and substeps";
             return LBMPCD_E_INVALID;
         }
-        if (p[i].wg_threads != p[0].wg_threads || p[i].collision != p[0].collision) {
-            msg = "all instances must share wg_threads and the collision rule";
+        if (p[i].wg_threads != p[0].wg_threads || p[i].collision != p[0].collision ||
+            (p[0].mpcd && p[i].reinject != p[0].reinject)) {
+            msg = "all instances must share wg_threads, the collision rule and the exchange rule";
             return LBMPCD_E_INVALID;
         }
         if (p[i].closure && n != 1) {
@@ -412,7 +436,7 @@ int finalize(lbmpcd_ctx* c) {
     L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
     L.in = c->part[c->pcur]; L.out = c->part[c->pcur];
     L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
-    L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
+    L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.tfine = c->tf; L.acc = c->acc; L.prof = c->prof;
     L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts;
     L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
     L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
@@ -520,6 +544,11 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     c->f[1] = c->ws + L.f1;
     c->ub = (double*)(c->ws + L.ub);
     c->uf = (double*)(c->ws + L.uf);
+    if (p[0].mpcd && p[0].reinject) {
+        c->tb = (double*)(c->ws + L.tb);
+        c->tf = (double*)(c->ws + L.tf);
+        c->ce_bit = 8;
+    }
     c->acc = (double*)(c->ws + L.acc);
     c->prof = (double*)(c->ws + L.prof);
     c->acc_bytes = L.acc_bytes;
@@ -591,6 +620,10 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     rc = rc ? rc : chk(launch_zero(c->prof, c->prof_bytes, s), "prof");
     rc = rc ? rc : chk(launch_zero(c->ub, 3 * 8 * (size_t)c->total_band, s), "ub");
     rc = rc ? rc : chk(launch_zero(c->uf, (size_t)c->dim * 8 * c->total_ufine, s), "uf");
+    if (c->tf) {
+        rc = rc ? rc : chk(launch_zero(c->tb, (size_t)CE_NT * 8 * c->total_band, s), "tb");
+        rc = rc ? rc : chk(launch_zero(c->tf, (size_t)CE_NT * 8 * c->total_ufine, s), "tf");
+    }
     rc = rc ? rc : chk(launch_lb_init(c->dim, c->lb_fp, c->d_desc, n_inst, c->total_nodes, c->f[0], s), "lb init");
     if (c->mpcd) {
         rc = rc ? rc : chk(launch_fill_sequential(c->d_desc, n_inst, c->total_tiles, c->fill[0], c->fill[1], s), "fill");
@@ -638,7 +671,7 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
             if (c->any_feedback)
                 HIPCHK(c, timed(c, 1, [&] {
                            return launch_band(c->dim, c->lb_fp, c->d_desc, c->n_inst, c->total_band,
-                                              c->f[c->fcur], c->acc, c->ub, 1, s);
+                                              c->f[c->fcur], c->acc, c->ub, nullptr, 1, s);
                        }));
             return 0;
         }
@@ -648,19 +681,20 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
         if (c->mpcd) {
             HIPCHK(c, timed(c, 1, [&] {
                        return launch_band(c->dim, c->lb_fp, c->d_desc, c->n_inst, c->total_band, c->f[c->fcur],
-                                          c->acc, c->ub, c->any_feedback ? 1 : 0, s);
+                                          c->acc, c->ub, c->tb, c->any_feedback ? 1 : 0, s);
                    }));
             HIPCHK(c, timed(c, 2, [&] {
-                       return launch_interp(c->dim, c->d_desc, c->n_inst, c->total_ufine, c->ub, c->uf, s);
+                       return launch_interp(c->dim, c->d_desc, c->n_inst, c->total_ufine, c->ub, c->uf, c->tb,
+                                            c->tf, s);
                    }));
             for (int sub = 0; sub < c->S; ++sub) {
                 ParticleLaunch L{};
                 L.dim = c->dim; L.part_fp = c->part_fp;
-                L.mode = (sub == 0 && !c->pending) ? 2 : (3 | c->coll_bit);
+                L.mode = ((sub == 0 && !c->pending) ? 2 : (3 | c->coll_bit)) | c->ce_bit;
                 L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
                 L.in = c->part[c->pcur]; L.out = c->part[c->pcur ^ 1];
                 L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
-                L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
+                L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.tfine = c->tf; L.acc = c->acc; L.prof = c->prof;
                 L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts;
                 L.coll_dt = sub > 0 ? 0 : -1;
                 L.coll_s = sub > 0 ? sub - 1 : c->S - 1;
@@ -762,6 +796,7 @@ int lbmpcd_field_bytes(const lbmpcd_ctx* c, int32_t field, int32_t inst, size_t*
         case LBMPCD_CELL_VCM: *bytes = (size_t)c->dim * d.ncells * 8; break;
         case LBMPCD_PROFILE: *bytes = (size_t)d.R * 4 * 8; break;
         case LBMPCD_UFINE: *bytes = (size_t)c->dim * d.Cx * d.R * d.Cz * 8; break;
+        case LBMPCD_TFINE: *bytes = (size_t)CE_NT * d.Cx * d.R * d.Cz * 8; break;
         case LBMPCD_STATS: *bytes = 8 * 8; break;
         case LBMPCD_CELL_START: *bytes = (size_t)d.ncells * 4; break;
         case LBMPCD_NODE_MPCD_U: *bytes = (size_t)c->dim * d.nslab * 8; break;
@@ -835,7 +870,7 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             // the state (and the other instances' pending collisions) is untouched
             L.in = c->part[c->pcur]; L.out = c->part[c->pcur ^ 1];
             L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
-            L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.acc = c->acc; L.prof = c->prof;
+            L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.tfine = c->tf; L.acc = c->acc; L.prof = c->prof;
             L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts; L.shifts = c->shifts;
             L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
             L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
@@ -845,16 +880,20 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
         case LBMPCD_PROFILE:
             HIPCHK(c, launch_profile_reduce(c->d_desc, inst, d.R, c->prof, (double*)dst, s));
             return 0;
-        case LBMPCD_UFINE: {
-            // expand the buffer rows to the full slab layout [dim][Cz][R][Cx]
+        case LBMPCD_UFINE:
+        case LBMPCD_TFINE: {
+            // expand the buffer rows to the full slab layout [ncomp][Cz][R][Cx]
+            const bool tens = field == LBMPCD_TFINE;
+            if (tens && !c->tf) return fail(c, LBMPCD_E_STATE, "TFINE needs the Chapman-Enskog exchange");
+            const int ncomp = tens ? CE_NT : c->dim;
+            const double* base = tens ? c->tf + d.ufine_off * CE_NT : c->uf + d.ufine_off * c->dim;
             HIPCHK(c, launch_zero(dst, nbytes, s));
             const size_t row = (size_t)d.Cx * 8;
-            for (int q = 0; q < c->dim; ++q)
+            for (int q = 0; q < ncomp; ++q)
                 for (int K = 0; K < d.Cz; ++K)
                     for (int Jb = 0; Jb < d.NB; ++Jb) {
                         const int J = Jb < d.buf_lo * d.r ? Jb : Jb + (d.R - d.NB);
-                        const double* src = c->uf + d.ufine_off * c->dim + (size_t)q * d.Cx * d.NB * d.Cz +
-                                            ((size_t)K * d.NB + Jb) * d.Cx;
+                        const double* src = base + (size_t)q * d.Cx * d.NB * d.Cz + ((size_t)K * d.NB + Jb) * d.Cx;
                         double* to = (double*)dst + (size_t)q * d.Cx * d.R * d.Cz + ((size_t)K * d.R + J) * d.Cx;
                         HIPCHK(c, hipMemcpyAsync(to, src, row, hipMemcpyDeviceToDevice, s));
                     }

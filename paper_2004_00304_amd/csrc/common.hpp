@@ -59,7 +59,17 @@ struct InstDesc {
     float ghf[3], gdtf[3], dtf, padf;  // binary32 roundings of gh, gdt, dt (binary32 particles)
     uint32_t key0, key1;
     int S, pad2;          // MPCD steps per LB step
+    // Chapman-Enskog exchange: T = ce_scale dev(-Pi_neq) / rho at the band nodes
+    int ce, pad3;         // 1: Chapman-Enskog draws in this instance's buffers
+    double ce_scale;      // nu_kin m / kT / (2 cs2 tau)
 };
+
+// Components of the Chapman-Enskog tensor per band node / buffer cell
+// (xx, yy, zz, xy, xz, yz; the z ones are zero in 2D).
+constexpr int CE_NT = 6;
+// acceptance-rejection: envelope 1 + CE_KAPPA b, at most CE_ATTEMPTS draws
+constexpr double CE_KAPPA = 30.0;
+constexpr int CE_ATTEMPTS = 32;
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32

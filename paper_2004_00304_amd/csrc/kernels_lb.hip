@@ -9,10 +9,12 @@
 //
 // k_band: per node of the rows the coupling needs; projects the sampled MPCD
 // velocity onto the equilibrium at interior slab nodes (feedback), clears the
-// sample sums, and stores the node velocity for the interpolation.
+// sample sums, and stores the node velocity for the interpolation; with the
+// Chapman-Enskog exchange also the node's tensor T = (nu_kin m/kT) dev S,
+// S the BGK strain rate from the non-equilibrium second moment.
 //
 // k_interp: per buffer fine cell, bi/trilinear interpolation of the node
-// velocity to the cell centre (Alg. 2).
+// velocity (and T) to the cell centre (Alg. 2).
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -122,7 +124,8 @@ __global__ void __launch_bounds__(WG) k_lb_step(const InstDesc* __restrict__ D, 
 template <int DIM, typename LT>
 __global__ void __launch_bounds__(WG) k_band(const InstDesc* __restrict__ D, int n_inst, long long total,
                                              LT* __restrict__ f, double* __restrict__ acc,
-                                             double* __restrict__ ub, int do_feedback) {
+                                             double* __restrict__ ub, double* __restrict__ tb,
+                                             int do_feedback) {
     using L = Lat<DIM>;
     constexpr int Q = L::Q;
     long long gid = (long long)blockIdx.x * WG + threadIdx.x;
@@ -171,9 +174,47 @@ __global__ void __launch_bounds__(WG) k_band(const InstDesc* __restrict__ D, int
     }
     const long long NBd = (long long)nx * d.nyb * d.nz;
     double* u = ub + d.band_off * 3;
-    u[b] = j0 / rho + 0.5 * d.g[0];
-    u[NBd + b] = j1 / rho + 0.5 * d.g[1];
-    u[2 * NBd + b] = j2 / rho + 0.5 * d.g[2];
+    const double ux = j0 / rho + 0.5 * d.g[0];
+    const double uy = j1 / rho + 0.5 * d.g[1];
+    const double uz = j2 / rho + 0.5 * d.g[2];
+    u[b] = ux;
+    u[NBd + b] = uy;
+    u[2 * NBd + b] = uz;
+    if (tb == nullptr || !d.ce) return;
+    // Chapman-Enskog tensor: non-equilibrium second moment about the
+    // physical velocity, its deviatoric part, scaled
+    double pxx = 0.0, pyy = 0.0, pzz = 0.0, pxy = 0.0, pxz = 0.0, pyz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double cx = (double)L::cx[i], cy = (double)L::cy[i], cz = (double)L::cz[i];
+        pxx += fl[i] * (cx * cx);
+        pyy += fl[i] * (cy * cy);
+        pxy += fl[i] * (cx * cy);
+        if constexpr (DIM == 3) {
+            pzz += fl[i] * (cz * cz);
+            pxz += fl[i] * (cx * cz);
+            pyz += fl[i] * (cy * cz);
+        }
+    }
+    const double cs2r = rho / 3.0;
+    double sxx = -(pxx - cs2r - rho * ux * ux) / rho;
+    double syy = -(pyy - cs2r - rho * uy * uy) / rho;
+    double szz = DIM == 3 ? -(pzz - cs2r - rho * uz * uz) / rho : 0.0;
+    const double sxy = -(pxy - rho * ux * uy) / rho;
+    const double sxz = DIM == 3 ? -(pxz - rho * ux * uz) / rho : 0.0;
+    const double syz = DIM == 3 ? -(pyz - rho * uy * uz) / rho : 0.0;
+    const double tr = (sxx + syy + szz) / (double)DIM;
+    sxx -= tr;
+    syy -= tr;
+    if constexpr (DIM == 3) szz -= tr;
+    const double c = d.ce_scale;
+    double* t = tb + d.band_off * CE_NT;
+    t[b] = c * sxx;
+    t[NBd + b] = c * syy;
+    t[2 * NBd + b] = c * szz;
+    t[3 * NBd + b] = c * sxy;
+    t[4 * NBd + b] = c * sxz;
+    t[5 * NBd + b] = c * syz;
 }
 
 // One interpolation axis: lower/upper node and weights.  Periodic axes wrap;
@@ -200,9 +241,35 @@ __device__ __forceinline__ void interp_axis(int Lx, int periodic, double X, int&
     }
 }
 
+// bi/trilinear value of node field fld (band layout) at the weights below;
+// a missing node (the wall) contributes zero
+template <int DIM>
+__device__ __forceinline__ double interp_value(const InstDesc& d, const double* fld, const int ix[2], const int iy[2],
+                                               const int iz[2], const double wx[2], const double wy[2],
+                                               const double wz[2]) {
+    double val[2] = {0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c) {
+        double row[2];
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) {
+            double a0 = 0.0, a1 = 0.0;
+            if (iy[bb] >= 0) {
+                long long base = ((long long)iz[c] * d.nyb + (iy[bb] - d.by0)) * d.nx;
+                a0 = fld[base + ix[0]];
+                a1 = fld[base + ix[1]];
+            }
+            row[bb] = wx[0] * a0 + wx[1] * a1;
+        }
+        val[c] = wy[0] * row[0] + wy[1] * row[1];
+    }
+    return (DIM == 3) ? wz[0] * val[0] + wz[1] * val[1] : val[0];
+}
+
 template <int DIM>
 __global__ void __launch_bounds__(WG) k_interp(const InstDesc* __restrict__ D, int n_inst, long long total,
-                                               const double* __restrict__ ub, double* __restrict__ uf) {
+                                               const double* __restrict__ ub, double* __restrict__ uf,
+                                               const double* __restrict__ tb, double* __restrict__ tf) {
     long long gid = (long long)blockIdx.x * WG + threadIdx.x;
     if (gid >= total) return;
     int ii = find_inst(D, n_inst, gid, [](const InstDesc& d) { return d.ufine_off; });
@@ -231,26 +298,12 @@ __global__ void __launch_bounds__(WG) k_interp(const InstDesc* __restrict__ D, i
     const long long NF = (long long)Cx * NB * d.Cz;
     double* out = uf + d.ufine_off * DIM;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        double val[2] = {0.0, 0.0};
+    for (int k = 0; k < DIM; ++k) out[k * NF + q] = interp_value<DIM>(d, u + k * NBd, ix, iy, iz, wx, wy, wz);
+    if (tf == nullptr || !d.ce) return;
+    const double* t = tb + d.band_off * CE_NT;
+    double* tout = tf + d.ufine_off * CE_NT;
 #pragma unroll
-        for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c) {
-            double row[2];
-#pragma unroll
-            for (int bb = 0; bb < 2; ++bb) {
-                double a0 = 0.0, a1 = 0.0;
-                if (iy[bb] >= 0) {
-                    long long base = ((long long)iz[c] * d.nyb + (iy[bb] - d.by0)) * d.nx;
-                    a0 = u[k * NBd + base + ix[0]];
-                    a1 = u[k * NBd + base + ix[1]];
-                }
-                row[bb] = wx[0] * a0 + wx[1] * a1;
-            }
-            val[c] = wy[0] * row[0] + wy[1] * row[1];
-        }
-        double v = (DIM == 3) ? wz[0] * val[0] + wz[1] * val[1] : val[0];
-        out[k * NF + q] = v;
-    }
+    for (int k = 0; k < CE_NT; ++k) tout[k * NF + q] = interp_value<DIM>(d, t + k * NBd, ix, iy, iz, wx, wy, wz);
 }
 
 // LB initial state: equilibrium at rho0 and the initial flow (physical
@@ -349,28 +402,28 @@ hipError_t launch_lb_step(int dim, int lb_fp, const InstDesc* D, int n_inst, lon
 }
 
 hipError_t launch_band(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f, double* acc,
-                       double* ub, int do_feedback, hipStream_t s) {
+                       double* ub, double* tb, int do_feedback, hipStream_t s) {
     if (total <= 0) return hipSuccess;
     dim3 g(blocks_for(total)), b(WG);
     if (dim == 2 && lb_fp == 64)
-        hipLaunchKernelGGL((k_band<2, double>), g, b, 0, s, D, n_inst, total, (double*)f, acc, ub, do_feedback);
+        hipLaunchKernelGGL((k_band<2, double>), g, b, 0, s, D, n_inst, total, (double*)f, acc, ub, tb, do_feedback);
     else if (dim == 2)
-        hipLaunchKernelGGL((k_band<2, float>), g, b, 0, s, D, n_inst, total, (float*)f, acc, ub, do_feedback);
+        hipLaunchKernelGGL((k_band<2, float>), g, b, 0, s, D, n_inst, total, (float*)f, acc, ub, tb, do_feedback);
     else if (lb_fp == 64)
-        hipLaunchKernelGGL((k_band<3, double>), g, b, 0, s, D, n_inst, total, (double*)f, acc, ub, do_feedback);
+        hipLaunchKernelGGL((k_band<3, double>), g, b, 0, s, D, n_inst, total, (double*)f, acc, ub, tb, do_feedback);
     else
-        hipLaunchKernelGGL((k_band<3, float>), g, b, 0, s, D, n_inst, total, (float*)f, acc, ub, do_feedback);
+        hipLaunchKernelGGL((k_band<3, float>), g, b, 0, s, D, n_inst, total, (float*)f, acc, ub, tb, do_feedback);
     return hipGetLastError();
 }
 
 hipError_t launch_interp(int dim, const InstDesc* D, int n_inst, long long total, const double* ub, double* uf,
-                         hipStream_t s) {
+                         const double* tb, double* tf, hipStream_t s) {
     if (total <= 0) return hipSuccess;
     dim3 g(blocks_for(total)), b(WG);
     if (dim == 2)
-        hipLaunchKernelGGL((k_interp<2>), g, b, 0, s, D, n_inst, total, ub, uf);
+        hipLaunchKernelGGL((k_interp<2>), g, b, 0, s, D, n_inst, total, ub, uf, tb, tf);
     else
-        hipLaunchKernelGGL((k_interp<3>), g, b, 0, s, D, n_inst, total, ub, uf);
+        hipLaunchKernelGGL((k_interp<3>), g, b, 0, s, D, n_inst, total, ub, uf, tb, tf);
     return hipGetLastError();
 }
 

@@ -11,10 +11,12 @@ namespace lbmpcd {
 // new LB step into shifts[n_inst][2][S][3] (slot = step parity) when S > 0.
 hipError_t launch_lb_step(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, const void* fin,
                           void* fout, long long* clock, double* shifts, int S, hipStream_t s);
+// With tb (tf) non-null the band kernel (interpolation) also writes the
+// Chapman-Enskog tensor of the instances that use that exchange.
 hipError_t launch_band(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f, double* acc,
-                       double* ub, int do_feedback, hipStream_t s);
+                       double* ub, double* tb, int do_feedback, hipStream_t s);
 hipError_t launch_interp(int dim, const InstDesc* D, int n_inst, long long total, const double* ub, double* uf,
-                         hipStream_t s);
+                         const double* tb, double* tf, hipStream_t s);
 hipError_t launch_lb_init(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f,
                           hipStream_t s);
 hipError_t launch_moments(int dim, int lb_fp, const InstDesc* D, int inst, long long N, const void* f,
@@ -36,7 +38,8 @@ inline PartPtrs<PT> typed(const PartBuf& b) {
 }
 
 struct ParticleLaunch {
-    int dim, part_fp, mode;       // mode bit 0: collide, bit 1: stream, bit 2: MPCD-AT instead of SRD
+    int dim, part_fp, mode;       // mode bit 0: collide, bit 1: stream, bit 2: MPCD-AT instead of SRD,
+                                  // bit 3: Chapman-Enskog exchange (with streaming)
     const InstDesc* D;
     int n_inst;
     long long tiles;              // workgroups (tiles of all instances)
@@ -45,6 +48,7 @@ struct ParticleLaunch {
     uint32_t* fill_out;
     const int* tile_inst;
     const double* ufine;
+    const double* tfine;          // [6][buffer cells] Chapman-Enskog tensor (mode bit 3)
     double* acc;
     double* prof;
     DevStats* stats;

@@ -15,13 +15,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmpcd.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 RHO, U, PI, POP, PART_POS, PART_VEL, CELL_ID, CELL_COUNT, CELL_VCM, PROFILE, UFINE, STATS, \
-    PART_VEL_PENDING, CELL_START, NODE_MPCD_U = range(15)
+    PART_VEL_PENDING, CELL_START, NODE_MPCD_U, TFINE = range(16)
 FIELD_NAMES = dict(rho=RHO, u=U, pi=PI, pop=POP, pos=PART_POS, vel=PART_VEL, cell_id=CELL_ID,
                    cell_count=CELL_COUNT, cell_vcm=CELL_VCM, profile=PROFILE, ufine=UFINE, stats=STATS,
-                   vel_pending=PART_VEL_PENDING, cell_start=CELL_START, node_mpcd_u=NODE_MPCD_U)
+                   vel_pending=PART_VEL_PENDING, cell_start=CELL_START, node_mpcd_u=NODE_MPCD_U,
+                   tfine=TFINE)
 ERRORS = {1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_OVERFLOW", 5: "E_STATE", 6: "E_UNSUPPORTED"}
 
 
@@ -44,6 +45,7 @@ class Params(C.Structure):
         ("init_flow", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint32),
         ("tile", C.c_int32 * 3), ("capacity_factor", C.c_double),
         ("tile_target", C.c_int32), ("wg_threads", C.c_int32), ("closure", C.c_int32),
+        ("reinject", C.c_int32), ("ce_nu_kin", C.c_double),
     ]
 
 
@@ -156,6 +158,8 @@ def params_struct(p: dict) -> Params:
     s.tile_target = p.get("tile_target", 0)
     s.wg_threads = p.get("wg_threads", 0)
     s.closure = p.get("closure", 0)
+    s.reinject = p.get("reinject", 0)
+    s.ce_nu_kin = p.get("ce_nu_kin", 0.0)
     return s
 
 
@@ -390,6 +394,15 @@ class Sim:
         R = (p["yhi"] - p["ylo"]) * r
         Cz = p["n"][2] * r if p["dim"] == 3 else 1
         return self.moments(UFINE, inst).cpu().numpy().reshape(p["dim"], Cz, R, p["n"][0] * r)
+
+    def tfine(self, inst=0) -> np.ndarray:
+        """Chapman-Enskog tensor of the buffer cells of the last exchange step,
+        [6][Cz][R][Cx] (xx, yy, zz, xy, xz, yz)."""
+        p = self.plist[inst]
+        r = p["refine"]
+        R = (p["yhi"] - p["ylo"]) * r
+        Cz = p["n"][2] * r if p["dim"] == 3 else 1
+        return self.moments(TFINE, inst).cpu().numpy().reshape(6, Cz, R, p["n"][0] * r)
 
     def stats(self, inst=0) -> dict:
         return self.moments(STATS, inst)

@@ -70,6 +70,10 @@ def compare_state(sim, orc, p, rtol, inst=0, check_cells=True, binning=None):
             uf_g = sim.ufine(inst)
             uf_o = orc.ufine()
             rep["ufine"] = scaled_err(uf_g, uf_o, max(np.abs(uf_o).max(), 1e-12))
+            if p.get("reinject", 0):
+                tf_g = sim.tfine(inst)
+                tf_o = orc.tfine()
+                rep["tfine"] = scaled_err(tf_g, tf_o, max(np.abs(tf_o).max(), 1e-12))
         st = sim.stats(inst)
         rep["dropped"] = st["dropped"]
         rep["misplaced"] = st["misplaced"]

@@ -59,6 +59,8 @@ def test_workspace_sizes(binding):
     (dict(buf_lo=5, buf_hi=5), 1), (dict(walls_y=1, ylo=0, buf_lo=1), 1), (dict(collision=2), 6),
     (dict(part_fp=16), 1), (dict(refine=0), 1), (dict(n=(8, 8, 2)), 1),
     (dict(walls_y=0, ylo=0, yhi=8), 6), (dict(substeps=300), 1),
+    (dict(reinject=2), 1), (dict(reinject=1, kT=0.0), 1), (dict(ce_nu_kin=-1.0), 1),
+    (dict(ce_nu_kin=float("inf")), 1),
 ])
 def test_invalid_params(binding, kw, code):
     with pytest.raises(binding.LbmpcdError) as e:
@@ -69,6 +71,21 @@ def test_invalid_params(binding, kw, code):
 def test_mixed_batch_rejected(binding):
     with pytest.raises(binding.LbmpcdError):
         binding.workspace_size([W.channel_2d(), W.small_3d()])
+    with pytest.raises(binding.LbmpcdError):
+        binding.workspace_size([W.channel_2d(), W.make(reinject=1)])
+
+
+def test_chapman_enskog_workspace(binding):
+    """The Chapman-Enskog exchange adds six doubles per band node and per
+    buffer cell, and nothing else."""
+    p = W.channel_2d()
+    base = binding.workspace_size(p)
+    ce = binding.workspace_size(W.make(reinject=1))
+    nx, ny, nz = p["n"]
+    band_nodes = nx * (p["yhi"] - p["ylo"] + 2) * nz  # the slab rows and one more on each side
+    buffer_cells = (p["buf_lo"] + p["buf_hi"]) * p["refine"] * nx * p["refine"]
+    # both regions are 256-byte aligned; without the exchange each still takes 256 bytes
+    assert ce - base == 6 * 8 * (buffer_cells + band_nodes) - 2 * 256
 
 
 def test_abi_version_checked(binding):

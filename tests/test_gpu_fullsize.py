@@ -13,7 +13,9 @@ binary32 values within 2e-6 of the thermal scale):
     pre-collision velocities vs the GPU's post-collision velocities and
     centre-of-mass velocities);
   - interpolation of the node velocities to every buffer fine cell;
-  - one MPCD step (exchange + streaming) of 200k sampled particles.
+  - one MPCD step (exchange + streaming) of 200k sampled particles; for the
+    3D channel with the Chapman-Enskog exchange the oracle draws with the
+    GPU's tensor of each particle's buffer cell.
 """
 import numpy as np
 import pytest
@@ -126,7 +128,12 @@ def _check_stream(torch, O, lbmpcd, p, sim, probe, ids2, r0, v0, t_last):
     J = np.clip(np.floor((r0[1] - p["ylo"]) * r).astype(int), 0, uf.shape[2] - 1)
     K = np.clip(np.floor(r0[2] * r).astype(int), 0, uf.shape[1] - 1) if dim == 3 else np.zeros_like(I)
     u = np.stack([uf[d, K, J, I] for d in range(dim)])
-    pr, vr = probe.exchange_stream(t, 0, ids2.cpu().numpy().astype(np.uint32), r0, v0, u)
+    tens = None
+    if p.get("reinject", 0):
+        tf = sim.tfine()
+        tens = np.stack([tf[m, K, J, I] for m in range(6)])
+        del tf
+    pr, vr = probe.exchange_stream(t, 0, ids2.cpu().numpy().astype(np.uint32), r0, v0, u, tens)
     dpos = np.abs(pr - pos1)
     for k, Lk in enumerate(p["n"][:dim]):
         if k != 1:
@@ -137,7 +144,12 @@ def _check_stream(torch, O, lbmpcd, p, sim, probe, ids2, r0, v0, t_last):
     assert np.abs(vr - vel1).max() / scale <= TOL32
 
 
-@pytest.mark.parametrize("maker,steps", [(W.channel_3d, 3), (W.thin_film_3d, 2)])
+def _channel_3d_ce():
+    return W.make(**{**W.channel_3d(), "reinject": 1})
+
+
+@pytest.mark.parametrize("maker,steps", [(W.channel_3d, 3), (W.thin_film_3d, 2), (_channel_3d_ce, 3)],
+                         ids=["channel_3d", "thin_film_3d", "channel_3d_ce"])
 def test_fullsize_sampled(env, maker, steps):
     torch, O, lbmpcd = env
     rng = np.random.default_rng(7)

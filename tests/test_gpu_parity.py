@@ -42,6 +42,17 @@ CASES = {
     "at_small_3d": (W.small_3d(collision=1), 5, RTOL64),
     "at_walled_2d": (W.walled_2d(collision=1), 6, RTOL64),
     "at_small_3d_fp32": (W.small_3d(part_fp=32, collision=1), 5, RTOL32),
+    # Chapman-Enskog exchange about a sheared LB (envelope ~1.3: about a
+    # quarter of the first attempts are rejected)
+    "ce_small_2d": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu_kin=2.0), 6, RTOL64),
+    "ce_small_2d_oneway": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu_kin=2.0, feedback=0),
+                           4, RTOL64),
+    "ce_small_3d": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu_kin=2.0), 5, RTOL64),
+    "ce_small_3d_fp32": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu_kin=2.0, part_fp=32),
+                         5, RTOL32),
+    "ce_at_small_2d": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), collision=1), 6, RTOL64),
+    "ce_at_small_3d": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu_kin=1.0, collision=1),
+                       5, RTOL64),
 }
 
 
@@ -176,3 +187,54 @@ def test_cell_start_and_node_average(env, kw):
     err = np.abs(un - ref).max() / scale
     banner(f"node averages: max err {err:.2e} of the thermal velocity; cells {start.size}")
     assert err <= RTOL64
+
+
+def test_chapman_enskog_at_zero_strain_is_maxwell_boltzmann(env):
+    """With the LB at rest (no force, one-way coupling) the tensor vanishes
+    to rounding, every first attempt is accepted, and the run draws exactly
+    the Maxwell-Boltzmann run's numbers: the two agree to the FP64 parity
+    tolerance (the cell sums are FP64 atomics in no fixed order, so two GPU
+    runs agree to rounding, not bit for bit; one different draw would be an
+    O(1) difference)."""
+    O, lbmpcd = env
+    p0 = W.small_3d(g=(0.0, 0.0, 0.0), feedback=0)
+    banner("chapman-enskog zero strain")
+    a = lbmpcd.Sim(p0)
+    b = lbmpcd.Sim(dict(p0, reinject=1))
+    a.step(3)
+    b.step(3)
+    assert np.abs(b.tfine()).max() < 1e-15
+    rep = compare_state(b, _Mirror(a), p0, RTOL64)
+    assert_parity(rep, RTOL64)
+
+
+class _Mirror:
+    """A GPU run presented with the oracle's accessors, for run-to-run
+    comparisons through compare_state."""
+
+    def __init__(self, sim):
+        self.s = sim
+
+    def f(self):
+        return self.s.f(0)
+
+    def moments(self):
+        return self.s.fields(0)
+
+    def binning(self):
+        return self.s.binning(0)
+
+    def particles(self):
+        return self.s.particles(0)
+
+    def ufine(self):
+        return self.s.ufine(0)
+
+
+def test_tfine_needs_the_chapman_enskog_exchange(env):
+    O, lbmpcd = env
+    sim = lbmpcd.Sim(W.small_2d())
+    sim.step(1)
+    with pytest.raises(lbmpcd.LbmpcdError) as e:
+        sim.tfine()
+    assert e.value.code == 5
