@@ -25,7 +25,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 PMC_FILE = os.path.join(ROOT, "profiles", "k_particles_channel_3d_pmc.json")
-KERNEL_SOURCES = ["paper_2004_00304_amd/csrc/kernels_mpcd.hip", "paper_2004_00304_amd/csrc/common.hpp"]
+KERNEL_SOURCES = ["paper_2004_00304_amd/csrc/particles.hpp", "paper_2004_00304_amd/csrc/kernels_mpcd.hip",
+                  "paper_2004_00304_amd/csrc/common.hpp"]
 
 
 def kernel_hash() -> str:
@@ -43,6 +44,8 @@ def workload(name: str) -> list:
         return W.ensemble(256)
     if name == "channel_3d_at":
         return [W.make(**{**W.channel_3d(), "collision": 1})]
+    if name == "channel_3d_ce":
+        return [W.make(**{**W.channel_3d(), "reinject": 1})]
     return [{"channel_3d": W.channel_3d, "channel_2d": W.channel_2d, "thin_film_3d": W.thin_film_3d}[name]()]
 
 
@@ -300,7 +303,8 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="channel_3d",
-                    choices=["channel_3d", "channel_3d_at", "channel_2d", "thin_film_3d", "ensemble", "closure"])
+                    choices=["channel_3d", "channel_3d_at", "channel_3d_ce", "channel_2d", "thin_film_3d",
+                             "ensemble", "closure"])
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with lbmpcd_autotune first (always on for the ensemble)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -371,6 +375,7 @@ def main():
               f"slab y[{p['ylo']},{p['yhi']}) buffers {p['buf_lo']}/{p['buf_hi']}, r {p['refine']}, "
               f"{p['ppc']} ppc ({tot['particles']} particles), S {p['substeps']}, "
               f"{'MPCD-AT' if p.get('collision', 0) == 1 else 'SRD ' + str(p['alpha_deg']) + ' deg'}, "
+              f"{'Chapman-Enskog' if p.get('reinject', 0) else 'Maxwell-Boltzmann'} exchange, "
               f"feedback {p['feedback']}")
     out = {
         "metric": "coupled steps/s: LB MLUPS + MPCD particle-updates/s, % HBM roofline",

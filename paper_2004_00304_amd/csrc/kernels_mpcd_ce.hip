@@ -2,6 +2,13 @@
 // with the Chapman-Enskog exchange (mode bit 8): stream (10), stream and
 // collide (11), and with the MPCD-AT collision (15).  A translation unit of
 // its own so that it compiles beside the Maxwell-Boltzmann set.
+//
+// Register budget: the exchange's acceptance test keeps the cell's tensor and
+// one more Philox block live per particle; at four waves per SIMD (128 VGPRs)
+// the eight-particle kernels spill, at three they do not, and the three-wave
+// build is the faster one on MI355X (4.7 against 7.3 ms per MPCD step of the
+// 3D channel).
+#define LBMPCD_PARTICLE_WAVES 3
 #include "particles.hpp"
 
 namespace lbmpcd {

@@ -121,6 +121,24 @@ __device__ __forceinline__ double ce_contract(const double T[6], const double z[
            2.0 * (T[3] * z[0] * z[1] + T[4] * z[0] * z[2] + T[5] * z[1] * z[2]);
 }
 
+// The attempts after the first (rare: the first is accepted with
+// probability about 1/A), out of line so that the particle kernel's unrolled
+// exchange carries one call instead of a copy of the loop per particle.
+struct CEDraw { double z0, z1, z2; };
+
+template <int DIM>
+__device__ __noinline__ CEDraw ce_retry(Key key, uint32_t id, uint32_t t, uint32_t sub, double T0, double T1,
+                                        double T2, double T3, double T4, double T5, double A, CEDraw first) {
+    const double T[6] = {T0, T1, T2, T3, T4, T5};
+    for (int k = 1; k < CE_ATTEMPTS; ++k) {
+        double zk[3];
+        ce_normals_at<DIM>(key, id, t, sub, 4u * (uint32_t)k, zk);
+        const U4 w = rng_block(key, id, t, sub, P_REINJ, 4u * (uint32_t)k + 2u);
+        if (A * u01(w.x, w.y) <= 1.0 - ce_contract<DIM>(T, zk)) return CEDraw{zk[0], zk[1], zk[2]};
+    }
+    return first;
+}
+
 template <int DIM>
 __device__ __forceinline__ void ce_redraw(Key key, uint32_t id, uint32_t t, uint32_t sub, const double* tf,
                                           long long NF, long long fc, double z[3]) {
@@ -137,19 +155,12 @@ __device__ __forceinline__ void ce_redraw(Key key, uint32_t id, uint32_t t, uint
     const double r1 = fabs(T[3]) + fabs(T[1]) + fabs(T[5]);
     const double r2 = fabs(T[4]) + fabs(T[5]) + fabs(T[2]);
     const double A = 1.0 + CE_KAPPA * fmax(r0, fmax(r1, r2));
-    U4 w = rng_block(key, id, t, sub, P_REINJ, 2u);
+    const U4 w = rng_block(key, id, t, sub, P_REINJ, 2u);
     if (A * u01(w.x, w.y) <= 1.0 - ce_contract<DIM>(T, z)) return;
-    for (int k = 1; k < CE_ATTEMPTS; ++k) {
-        double zk[3];
-        ce_normals_at<DIM>(key, id, t, sub, 4u * (uint32_t)k, zk);
-        w = rng_block(key, id, t, sub, P_REINJ, 4u * (uint32_t)k + 2u);
-        if (A * u01(w.x, w.y) <= 1.0 - ce_contract<DIM>(T, zk)) {
-            z[0] = zk[0];
-            z[1] = zk[1];
-            z[2] = zk[2];
-            return;
-        }
-    }
+    const CEDraw r = ce_retry<DIM>(key, id, t, sub, T[0], T[1], T[2], T[3], T[4], T[5], A, CEDraw{z[0], z[1], z[2]});
+    z[0] = r.z0;
+    z[1] = r.z1;
+    z[2] = r.z2;
 }
 
 // Read-only tables (descriptors, tile owners, grid shifts, fill counts of
