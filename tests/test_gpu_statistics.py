@@ -1,0 +1,140 @@
+"""Statistical checks of the HIP path on the GPU, at sizes the oracle cannot
+run: properties the paper states, checked through the C ABI.
+
+* Eq. 8 (Sec. 3.1): at equilibrium the velocity of a cell of N particles
+  fluctuates with standard deviation sqrt(kT/(m N)), and averaging N_s
+  independent samples divides it by sqrt(N_s).  Checked on the pending
+  collision's cell centre-of-mass velocities of a periodic box at rest, for
+  N = 10, 40, 160 and both collision rules.
+* The Chapman-Enskog exchange (the remedy the end of Sec. 2.3 names for
+  strong gradients) puts the kinetic stress of the LB strain rate into the
+  buffer: right after the exchange the thermal velocities of buffer
+  particles have <dv_x dv_y> m/kT = -2 T_xy of their cell; the
+  Maxwell-Boltzmann exchange has none.
+"""
+import numpy as np
+import pytest
+
+from paper_2004_00304_amd import workloads as W
+from tests.gpu_util import banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbmpcd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_00304_amd import lbmpcd as L
+    return L
+
+
+@pytest.mark.parametrize("collision", [1, 0], ids=["mpcd_at", "srd"])
+def test_eq8_velocity_noise(lbmpcd, collision):
+    kT, m = 1.0 / 3.0, 1.0
+    K, gap = 12, 20  # snapshots, LB steps between them (hydrodynamic modes decorrelate as exp(-nu k^2 t))
+    for N in (10, 40, 160):
+        p = W.periodic_2d(n=(32, 32, 1), ppc=N, collision=collision)
+        banner(f"eq8 collision={collision} N={N}")
+        sim = lbmpcd.Sim(p)
+        sim.step(20)
+        z2, vsum, nsum = [], None, None
+        for _ in range(K):
+            sim.step(gap)
+            b = sim.binning()
+            n = b["count"].astype(np.float64)
+            occ = n > 0
+            v = b["vcm"]
+            z2.append((v[:, occ] ** 2 * n[occ] * m / kT).ravel())
+            vsum = v * n if vsum is None else vsum + v * n
+            nsum = n if nsum is None else nsum + n
+        z2 = np.concatenate(z2)
+        # one sample: Var(v_cm) = kT / (m n)
+        se = np.sqrt(2.0 / len(z2))
+        banner(f"  N={N}: <v_cm^2 n m/kT> = {z2.mean():.4f} (se {se:.4f})")
+        assert abs(z2.mean() - 1.0) < 8 * se + 0.02
+        # N_s = K samples of the same cells: the average's variance falls by K
+        # (the grid shift moves a cell by less than its side, so the index
+        # stays the same place)
+        ok = nsum > 0
+        vbar = vsum[:, ok] / nsum[ok]
+        ratio = float((vbar ** 2 * nsum[ok] * m / kT).mean())
+        banner(f"  N={N}: time-averaged over {K}: <vbar^2 N K m/kT> = {ratio:.3f}")
+        assert 0.85 < ratio < 1.3
+
+
+def _ce_channel(reinject):
+    # one MPCD step per LB step, so the pending velocities are those of the
+    # exchange plus one streaming step; the LB starts on its exact steady state
+    return W.make(dim=3, n=(64, 32, 32), tau=0.8, ylo=8, yhi=24, buf_lo=2, buf_hi=2, refine=2, ppc=10,
+                  alpha_deg=120.0, substeps=1, g=(1e-4, 0.0, 0.0), init_flow=1, feedback=0,
+                  reinject=reinject, ce_nu_kin=2.0)
+
+
+def _buffer_stress_slope(lbmpcd, p, steps=3):
+    """Regression slope of the exchanged buffer particles' dv_x dv_y m/kT on
+    -2 T_xy of their cell, pooled over `steps` LB steps."""
+    import torch
+    dim, r = p["dim"], p["refine"]
+    Np = W.sizes(p)["particles"]
+    sim = lbmpcd.Sim(p)
+    sim.step(2)
+    R = (p["yhi"] - p["ylo"]) * r
+    lo, hi = p["buf_lo"] * r, R - p["buf_hi"] * r
+    num = den = 0.0
+    count = 0
+    for _ in range(steps):
+        pos0 = sim.get_state(lbmpcd.PART_POS).view(dim, Np).cpu().numpy()
+        sim.step(1)
+        vel = sim.get_state(lbmpcd.PART_VEL_PENDING).view(dim, Np).cpu().numpy()
+        uf = sim.ufine()
+        tf = sim.tfine() if p["reinject"] else None
+        J = np.floor((pos0[1] - p["ylo"]) * r).astype(int)
+        inb = (J < lo) | (J >= hi)
+        I = np.floor(pos0[0] * r).astype(int)[inb]
+        Kz = np.floor(pos0[2] * r).astype(int)[inb]
+        Jb = J[inb]
+        dvx = vel[0, inb] - uf[0, Kz, Jb, I] - p["g"][0] / p["substeps"]
+        dvy = vel[1, inb] - uf[1, Kz, Jb, I]
+        a = dvx * dvy * p["mass"] / p["kT"]
+        if tf is None:
+            # the Maxwell-Boltzmann run regresses on the tensor the other
+            # run uses: the same geometry and LB state
+            tf = _ce_tensor_of_same_state(lbmpcd, p)
+        b = -2.0 * tf[3, Kz, Jb, I]
+        num += float((a * b).sum())
+        den += float((b * b).sum())
+        count += int(inb.sum())
+        del pos0, vel
+    torch.cuda.empty_cache()
+    return num / den, 1.0 / np.sqrt(den), count
+
+
+_TENSOR = {}
+
+
+def _ce_tensor_of_same_state(lbmpcd, p):
+    """The buffer tensor of the Chapman-Enskog twin of p after its first
+    steps (the LB is one-way coupled and starts on the Poiseuille profile;
+    once its non-equilibrium part has formed, within a few collision times,
+    the tensor barely changes from step to step)."""
+    key = "ce"
+    if key not in _TENSOR:
+        q = dict(p, reinject=1)
+        sim = lbmpcd.Sim(q)
+        sim.step(3)
+        _TENSOR[key] = sim.tfine()
+    return _TENSOR[key]
+
+
+def test_chapman_enskog_buffer_carries_the_kinetic_stress(lbmpcd):
+    p = _ce_channel(1)
+    banner("chapman-enskog buffer stress")
+    slope, se, n = _buffer_stress_slope(lbmpcd, p)
+    banner(f"  CE: slope {slope:.3f} +- {se:.3f} over {n} exchanged particles")
+    assert abs(slope - 1.0) < max(5 * se, 0.05)
+    q = _ce_channel(0)
+    slope0, se0, n0 = _buffer_stress_slope(lbmpcd, q)
+    banner(f"  MB: slope {slope0:.3f} +- {se0:.3f} over {n0} exchanged particles")
+    assert abs(slope0) < max(5 * se0, 0.05)
