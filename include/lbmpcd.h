@@ -136,17 +136,21 @@ typedef struct lbmpcd_params {
                               Maxwell-Boltzmann draw about the interpolated LB velocity; 1 a
                               first-order Chapman-Enskog draw about it, the remedy Sec. 2.3
                               names for strong gradients: the Maxwellian times 1 - T:z z,
-                              z the thermal velocity in units of sqrt(kT/m), T = (nu m/kT)
+                              z the thermal velocity in units of sqrt(kT/m), T = (ce_nu m/kT)
                               dev S with S = -(sum f c c - rho I/3 - rho u u)/(2 rho tau/3)
                               the lattice's strain rate, interpolated like u; sampled by
                               acceptance-rejection against the Maxwellian (envelope
                               1 + 30 x the largest absolute row sum of T, at most 32
                               attempts, else the first attempt's draw).  Needs kT > 0;
                               all instances of a context share it */
-    double ce_nu_kin;      /* nu of the Chapman-Enskog stress (> 0), or 0: the kinetic part
-                              of the collision rule's viscosity (MPCD-AT: Eq. 7's first
-                              term; SRD: kT dt/m [N/((N-1+e^-N)(1-cos 2a)) - 1/2] in 2D,
-                              kT dt/m [5N/((N-1+e^-N)(4-2cos a-2cos 2a)) - 1/2] in 3D) */
+    double ce_nu;          /* stress coefficient of the Chapman-Enskog exchange (any finite
+                              value), or 0: the kinetic stress the MPCD fluid carries right
+                              after its collision, the instant of the exchange,
+                              nu_kin - kT dt/(2m), with nu_kin the kinetic viscosity of the
+                              collision rule (MPCD-AT: Eq. 7's first term, so the default is
+                              kT dt/m (N/(N-1+e^-N) - 1); SRD: kT dt/m [N/((N-1+e^-N)
+                              (1-cos 2a)) - 1/2] in 2D, kT dt/m [5N/((N-1+e^-N)(4-2cos a
+                              -2cos 2a)) - 1/2] in 3D, negative at large angles) */
 } lbmpcd_params;
 
 /*

@@ -263,7 +263,6 @@ double orc_nu_at(double kT, double mass, double dt, double a, double N) {
  * SRD literature's kinetic terms): 2D kT dt/m [N/((N-1+e^-N)(1-cos 2 alpha))
  * - 1/2], 3D kT dt/m [5N/((N-1+e^-N)(4-2cos alpha-2cos 2 alpha)) - 1/2]. */
 double orc_nu_kinetic(const orc_params* p) {
-    if (p->nu_kin > 0.0) return p->nu_kin;
     const double N = (double)p->ppc, q = N - 1.0 + exp(-N);
     const double kin = p->kT * (1.0 / p->substeps) / p->mass;
     if (p->collision == 1) return kin * (N / q - 0.5);
@@ -272,14 +271,27 @@ double orc_nu_kinetic(const orc_params* p) {
     return kin * (5.0 * N / (q * (4.0 - 2.0 * cos(al) - 2.0 * cos(2.0 * al))) - 0.5);
 }
 
+/* READING: the stress the exchange has to reproduce is the one the MPCD fluid
+ * carries at the instant of the exchange, right after a collision.  Over the
+ * streaming step that follows, ballistic motion through the shear adds
+ * kT dt/m per unit shear rate to the kinetic stress coefficient, and the
+ * kinetic viscosity is its average over the step; so right after the collision
+ * the coefficient is nu_kin - kT dt / (2m).  For MPCD-AT that is
+ * kT dt/m (N/(N-1+e^-N) - 1), of order 1/N; for SRD it is negative at
+ * large angles. */
+double orc_ce_nu(const orc_params* p) {
+    if (p->ce_nu != 0.0) return p->ce_nu;
+    return orc_nu_kinetic(p) - 0.5 * p->kT * (1.0 / p->substeps) / p->mass;
+}
+
 /* ------------------------------------------------------------------------
  * Chapman-Enskog exchange (READING; the paper names sampling from an Enskog
  * distribution, after Garcia and Alexander, as the remedy when velocity
  * gradients are strong, Sec. 2.3).  To first order in the gradients the
  * velocity distribution about u is the Maxwellian times 1 - T:zz, with z the
- * thermal velocity in units of sqrt(kT/m) and T = (nu_kin m / kT) dev S, S the
- * strain rate; its covariance is (kT/m)(I - 2T), i.e. the kinetic stress
- * 2 rho nu_kin dev S.  Heat flux is absent (isothermal fluid).  Samples come
+ * thermal velocity in units of sqrt(kT/m) and T = (nu_x m / kT) dev S, S the
+ * strain rate and nu_x the stress coefficient of orc_ce_nu; its covariance is
+ * (kT/m)(I - 2T), i.e. the kinetic stress 2 rho nu_x dev S.  Heat flux is absent (isothermal fluid).  Samples come
  * by acceptance-rejection against the Maxwellian: attempt k draws z from the
  * Philox blocks 4k and 4k+1 of the exchange stream (attempt 0 is the
  * Maxwell-Boltzmann draw itself) and a uniform u from block 4k+2, and accepts
@@ -405,7 +417,7 @@ static int validate(const orc_params* p) {
     if (!(p->mass > 0.0) || p->kT < 0.0) return 1;
     if (p->collision != 0 && p->collision != 1) return 1;
     if (p->reinject != 0 && p->reinject != 1) return 1;
-    if (p->reinject && (!(p->kT > 0.0) || !(p->nu_kin >= 0.0))) return 1;
+    if (p->reinject && (!(p->kT > 0.0) || !isfinite(p->ce_nu))) return 1;
     return 0;
 }
 
@@ -645,7 +657,7 @@ static void interpolate_from(const orc_state* s, int ncomp, const double* unode,
  * lattice from the non-equilibrium second moment of the post-stream
  * populations, S = -(sum f c c - rho cs2 I - rho u u) / (2 rho cs2 tau) with
  * the physical velocity u, its deviatoric part over the d axes, scaled by
- * nu_kin m / kT.  T[6] = (xx, yy, zz, xy, xz, yz); zero components in 2D. */
+ * nu_x m / kT (nu_x of orc_ce_nu).  T[6] = (xx, yy, zz, xy, xz, yz); zero components in 2D. */
 static void node_ce_tensor(const orc_state* s, int64_t n, double T[6]) {
     static const int ab[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
     const orc_params* p = &s->p;
@@ -665,7 +677,7 @@ static void node_ce_tensor(const orc_state* s, int64_t n, double T[6]) {
     S[0] -= tr;
     S[1] -= tr;
     if (p->dim == 3) S[2] -= tr;
-    double c = orc_nu_kinetic(p) * p->mass / p->kT;
+    double c = orc_ce_nu(p) * p->mass / p->kT;
     for (int m = 0; m < 6; ++m) T[m] = c * S[m];
 }
 

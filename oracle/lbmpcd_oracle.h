@@ -53,8 +53,9 @@ typedef struct orc_params {
     int32_t reinject;       /* exchange step: 0 Maxwell-Boltzmann (Sec. 2.3); 1 first-order
                                Chapman-Enskog about the LB strain rate (the remedy the paper
                                names for strong gradients, Sec. 2.3) */
-    double nu_kin;          /* kinetic viscosity that sets the Chapman-Enskog stress; 0: the
-                               kinetic part of the collision rule's viscosity */
+    double ce_nu;           /* viscosity coefficient of the Chapman-Enskog stress (finite);
+                               0: the kinetic stress the MPCD fluid carries right after its
+                               collision, the instant of the exchange: nu_kin - kT dt / (2m) */
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -139,10 +140,12 @@ void orc_at_collide(int32_t dim, int32_t n, double* vel, const double* vran, con
 /* kinematic viscosity of MPCD-AT (Eq. 7): kT dt / m [N / (N - 1 + e^-N) - 1/2]
  * + a^2 / (12 dt) (N - 1 + e^-N) / N */
 double orc_nu_at(double kT, double mass, double dt, double a, double N);
-/* kinetic part of the MPCD viscosity of the parameter set (the Chapman-Enskog
- * reinjection's default): MPCD-AT the first term of Eq. 7; SRD the kinetic
- * term of the SRD literature in 2D and 3D */
+/* kinetic part of the MPCD viscosity of the parameter set: MPCD-AT the first
+ * term of Eq. 7; SRD the kinetic term of the SRD literature in 2D and 3D */
 double orc_nu_kinetic(const orc_params* p);
+/* coefficient of the Chapman-Enskog exchange's stress: ce_nu, or by default
+ * orc_nu_kinetic(p) - kT dt / (2m) */
+double orc_ce_nu(const orc_params* p);
 /* Chapman-Enskog tensor T[6] (xx,yy,zz,xy,xz,yz) of every node from the
  * current populations: out[6][N] */
 void orc_ce_tensor(const orc_state* s, double* out);

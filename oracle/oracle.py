@@ -40,7 +40,7 @@ class _Params(C.Structure):
         ("mass", C.c_double), ("kT", C.c_double), ("alpha_deg", C.c_double),
         ("grid_shift", C.c_int32), ("feedback", C.c_int32), ("init_flow", C.c_int32),
         ("seed", C.c_uint64), ("instance", C.c_uint32), ("collision", C.c_int32),
-        ("reinject", C.c_int32), ("nu_kin", C.c_double),
+        ("reinject", C.c_int32), ("ce_nu", C.c_double),
     ]
 
 
@@ -91,6 +91,8 @@ def lib():
         L.orc_nu_at.restype = C.c_double
         L.orc_nu_kinetic.argtypes = [C.POINTER(_Params)]
         L.orc_nu_kinetic.restype = C.c_double
+        L.orc_ce_nu.argtypes = [C.POINTER(_Params)]
+        L.orc_ce_nu.restype = C.c_double
         L.orc_ce_tensor.argtypes = [P, P]
         L.orc_get_tfine.argtypes = [P, P]
         L.orc_ce_normals.argtypes = [C.POINTER(_Params), C.c_uint32, C.c_uint32, C.c_uint32, P, P]
@@ -119,7 +121,7 @@ def params_struct(p: dict) -> _Params:
     s.seed, s.instance = p["seed"], p["instance"]
     s.collision = int(p.get("collision", 0))
     s.reinject = int(p.get("reinject", 0))
-    s.nu_kin = float(p.get("ce_nu_kin", 0.0))
+    s.ce_nu = float(p.get("ce_nu", 0.0))
     return s
 
 
@@ -332,9 +334,16 @@ def nu_at(kT, mass, dt, a, N):
 
 
 def nu_kinetic(p: dict) -> float:
-    """Kinetic part of the MPCD viscosity of a parameter set (or its ce_nu_kin)."""
+    """Kinetic part of the MPCD viscosity of a parameter set."""
     ps = params_struct(p)
     return float(lib().orc_nu_kinetic(C.byref(ps)))
+
+
+def ce_nu(p: dict) -> float:
+    """Stress coefficient of the Chapman-Enskog exchange (ce_nu, or the
+    post-collision kinetic stress nu_kin - kT dt / (2m))."""
+    ps = params_struct(p)
+    return float(lib().orc_ce_nu(C.byref(ps)))
 
 
 def ce_normals(p: dict, ids, t: int, sub: int, T) -> tuple:

@@ -229,7 +229,7 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     if ((bw || tw) && p.g[1] != 0.0) { msg = "walls in the slab need g_y = 0"; return LBMPCD_E_INVALID; }
     if (!(p.mass > 0.0) || p.kT < 0.0) { msg = "mass must be positive, kT non-negative"; return LBMPCD_E_INVALID; }
     if (p.reinject != 0 && p.reinject != 1) { msg = "reinject must be 0 or 1"; return LBMPCD_E_INVALID; }
-    if (!(p.ce_nu_kin >= 0.0) || !std::isfinite(p.ce_nu_kin)) { msg = "ce_nu_kin must be finite and non-negative"; return LBMPCD_E_INVALID; }
+    if (!std::isfinite(p.ce_nu)) { msg = "ce_nu must be finite"; return LBMPCD_E_INVALID; }
     if (p.reinject && !(p.kT > 0.0)) { msg = "the Chapman-Enskog exchange needs kT > 0"; return LBMPCD_E_INVALID; }
     const bool ywrap = !p.walls_y && p.ylo == 0 && p.yhi == p.n[1] && p.buf_lo == 0 && p.buf_hi == 0;
     if (!p.walls_y && !ywrap && (p.ylo < 1 || p.yhi > p.n[1] - 1)) {
@@ -242,16 +242,24 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     return 0;
 }
 
-// Kinetic part of the MPCD viscosity, the stress the Chapman-Enskog exchange
-// reproduces: MPCD-AT Eq. 7's first term; SRD the kinetic terms of the SRD
-// literature (2D and 3D).  ce_nu_kin > 0 overrides it.
+// Kinetic part of the MPCD viscosity: MPCD-AT Eq. 7's first term; SRD the
+// kinetic terms of the SRD literature (2D and 3D).
 double nu_kinetic(const lbmpcd_params& p) {
-    if (p.ce_nu_kin > 0.0) return p.ce_nu_kin;
     const double N = (double)p.ppc, q = N - 1.0 + std::exp(-N), kin = p.kT / p.substeps / p.mass;
     if (p.collision == 1) return kin * (N / q - 0.5);
     const double al = p.alpha_deg * 3.14159265358979323846 / 180.0;
     if (p.dim == 2) return kin * (N / (q * (1.0 - std::cos(2.0 * al))) - 0.5);
     return kin * (5.0 * N / (q * (4.0 - 2.0 * std::cos(al) - 2.0 * std::cos(2.0 * al))) - 0.5);
+}
+
+// Stress coefficient of the Chapman-Enskog exchange: the kinetic stress the
+// MPCD fluid carries right after a collision, when the exchange redraws the
+// buffer.  Streaming through the shear adds kT dt/m per unit shear rate over
+// a step and nu_kin is the step average, so right after the collision it is
+// nu_kin - kT dt/(2m).  ce_nu != 0 overrides it.
+double ce_nu(const lbmpcd_params& p) {
+    if (p.ce_nu != 0.0) return p.ce_nu;
+    return nu_kinetic(p) - 0.5 * p.kT / p.substeps / p.mass;
 }
 
 struct Layout {
@@ -304,7 +312,7 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
         d.key1 = (uint32_t)(q.seed >> 32) ^ q.instance;
         d.S = q.mpcd ? q.substeps : 0;
         d.ce = (q.mpcd && q.reinject) ? 1 : 0;
-        d.ce_scale = d.ce ? nu_kinetic(q) * q.mass / q.kT / (2.0 * q.tau / 3.0) : 0.0;
+        d.ce_scale = d.ce ? ce_nu(q) * q.mass / q.kT / (2.0 * q.tau / 3.0) : 0.0;
         node += d.N;
         band += g.nband;
         ufine += g.nufine;

@@ -61,7 +61,7 @@ struct InstDesc {
     int S, pad2;          // MPCD steps per LB step
     // Chapman-Enskog exchange: T = ce_scale dev(-Pi_neq) / rho at the band nodes
     int ce, pad3;         // 1: Chapman-Enskog draws in this instance's buffers
-    double ce_scale;      // nu_kin m / kT / (2 cs2 tau)
+    double ce_scale;      // nu_x m / kT / (2 cs2 tau), nu_x the exchange's stress coefficient
 };
 
 // Components of the Chapman-Enskog tensor per band node / buffer cell

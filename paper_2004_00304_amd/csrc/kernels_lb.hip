@@ -10,7 +10,7 @@
 // k_band: per node of the rows the coupling needs; projects the sampled MPCD
 // velocity onto the equilibrium at interior slab nodes (feedback), clears the
 // sample sums, and stores the node velocity for the interpolation; with the
-// Chapman-Enskog exchange also the node's tensor T = (nu_kin m/kT) dev S,
+// Chapman-Enskog exchange also the node's tensor T = (nu_x m/kT) dev S,
 // S the BGK strain rate from the non-equilibrium second moment.
 //
 // k_interp: per buffer fine cell, bi/trilinear interpolation of the node

@@ -11,6 +11,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch first: the library then binds to the HIP runtime torch carries.  Loaded
+# the other way round the process would hold two HIP runtimes, and torch's
+# device pointers and streams would mean nothing to the library's.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmpcd.so")
@@ -45,7 +49,7 @@ class Params(C.Structure):
         ("init_flow", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint32),
         ("tile", C.c_int32 * 3), ("capacity_factor", C.c_double),
         ("tile_target", C.c_int32), ("wg_threads", C.c_int32), ("closure", C.c_int32),
-        ("reinject", C.c_int32), ("ce_nu_kin", C.c_double),
+        ("reinject", C.c_int32), ("ce_nu", C.c_double),
     ]
 
 
@@ -159,7 +163,7 @@ def params_struct(p: dict) -> Params:
     s.wg_threads = p.get("wg_threads", 0)
     s.closure = p.get("closure", 0)
     s.reinject = p.get("reinject", 0)
-    s.ce_nu_kin = p.get("ce_nu_kin", 0.0)
+    s.ce_nu = p.get("ce_nu", 0.0)
     return s
 
 

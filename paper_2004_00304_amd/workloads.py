@@ -21,8 +21,9 @@ _BASE = dict(
     part_fp=64, mass=1.0, kT=1.0 / 3.0, alpha_deg=130.0, collision=0, grid_shift=1,
     feedback=1, init_flow=0, seed=1, instance=0,
     # exchange step: 0 Maxwell-Boltzmann, 1 Chapman-Enskog about the LB strain
-    # rate with kinetic viscosity ce_nu_kin (0: the collision rule's own)
-    reinject=0, ce_nu_kin=0.0,
+    # rate with stress coefficient ce_nu (0: the post-collision kinetic stress
+    # of the collision rule)
+    reinject=0, ce_nu=0.0,
     # launch configuration of the HIP path (tile shape in cells, tile slot
     # capacity over expected occupancy); 0 = library default
     tile=(0, 0, 0), capacity_factor=0.0, tile_target=0, wg_threads=0, closure=0,

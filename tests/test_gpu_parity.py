@@ -44,14 +44,14 @@ CASES = {
     "at_small_3d_fp32": (W.small_3d(part_fp=32, collision=1), 5, RTOL32),
     # Chapman-Enskog exchange about a sheared LB (envelope ~1.3: about a
     # quarter of the first attempts are rejected)
-    "ce_small_2d": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu_kin=2.0), 6, RTOL64),
-    "ce_small_2d_oneway": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu_kin=2.0, feedback=0),
+    "ce_small_2d": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu=2.0), 6, RTOL64),
+    "ce_small_2d_oneway": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu=2.0, feedback=0),
                            4, RTOL64),
-    "ce_small_3d": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu_kin=2.0), 5, RTOL64),
-    "ce_small_3d_fp32": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu_kin=2.0, part_fp=32),
+    "ce_small_3d": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu=2.0), 5, RTOL64),
+    "ce_small_3d_fp32": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu=2.0, part_fp=32),
                          5, RTOL32),
     "ce_at_small_2d": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), collision=1), 6, RTOL64),
-    "ce_at_small_3d": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu_kin=1.0, collision=1),
+    "ce_at_small_3d": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu=1.0, collision=1),
                        5, RTOL64),
 }
 

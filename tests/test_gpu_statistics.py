@@ -69,7 +69,7 @@ def _ce_channel(reinject):
     # exchange plus one streaming step; the LB starts on its exact steady state
     return W.make(dim=3, n=(64, 32, 32), tau=0.8, ylo=8, yhi=24, buf_lo=2, buf_hi=2, refine=2, ppc=10,
                   alpha_deg=120.0, substeps=1, g=(1e-4, 0.0, 0.0), init_flow=1, feedback=0,
-                  reinject=reinject, ce_nu_kin=2.0)
+                  reinject=reinject, ce_nu=2.0)
 
 
 def _buffer_stress_slope(lbmpcd, p, steps=3):
@@ -138,3 +138,53 @@ def test_chapman_enskog_buffer_carries_the_kinetic_stress(lbmpcd):
     slope0, se0, n0 = _buffer_stress_slope(lbmpcd, q)
     banner(f"  MB: slope {slope0:.3f} +- {se0:.3f} over {n0} exchanged particles")
     assert abs(slope0) < max(5 * se0, 0.05)
+
+
+def _stress_coefficients(lbmpcd, collision, alpha, N, g=3e-4, steps=60):
+    """-<dv_x v_y> / (du/dy) in units of kT dt/m, right after the collision
+    and right before it, in a walled stand-alone MPCD channel whose LB (used
+    only for the start) has the MPCD viscosity."""
+    base = dict(n=(64, 32, 1), ylo=0, yhi=32, walls_y=1, buf_lo=0, buf_hi=0, refine=2, substeps=4, ppc=N,
+                collision=collision, alpha_deg=alpha, g=(g, 0.0, 0.0), feedback=0, init_flow=1)
+    p = W.make(**base)
+    nu_m = lbmpcd.viscosity(p)[1]
+    p = W.make(**{**base, "tau": 0.5 + 3 * nu_m})
+    sim = lbmpcd.Sim(p)
+    sim.step(200)
+    H, kT, m, dt = float(p["n"][1]), p["kT"], p["mass"], 1.0 / p["substeps"]
+    Np = W.sizes(p)["particles"]
+    acc = {"post": [0.0, 0.0], "pre": [0.0, 0.0]}
+    for _ in range(steps):
+        sim.step(1)
+        pos = sim.get_state(lbmpcd.PART_POS).view(2, Np).cpu().numpy()
+        vs = {"pre": sim.get_state(lbmpcd.PART_VEL_PENDING).view(2, Np).cpu().numpy(),
+              "post": sim.get_state(lbmpcd.PART_VEL).view(2, Np).cpu().numpy()}
+        y = pos[1]
+        keep = (y > 2.0) & (y < H - 2.0)  # away from the walls' virtual particles
+        y = y[keep]
+        u = g * y * (H - y) / (2 * nu_m)
+        dudy = g * (H - 2 * y) / (2 * nu_m)
+        for k, v in vs.items():
+            a = -(v[0, keep] - u) * v[1, keep]
+            acc[k][0] += float((a * dudy).sum())
+            acc[k][1] += float((dudy * dudy).sum())
+    unit = kT * dt / m
+    se = kT / m / np.sqrt(acc["post"][1]) / unit
+    return p, acc["post"][0] / acc["post"][1] / unit, acc["pre"][0] / acc["pre"][1] / unit, se
+
+
+@pytest.mark.parametrize("collision,alpha", [(1, 130.0), (0, 90.0)], ids=["mpcd_at", "srd90"])
+def test_kinetic_stress_right_after_the_collision(lbmpcd, collision, alpha):
+    """The Chapman-Enskog exchange's default coefficient is the kinetic stress
+    a sheared MPCD fluid carries right after its collision (the exchange's
+    instant): nu_kin - kT dt/(2m); streaming then adds kT dt/m per unit
+    shear before the next collision.  Measured on the particles of a walled
+    stand-alone channel, relative to the analytic Poiseuille velocity."""
+    from oracle import oracle as O
+    p, c_post, c_pre, se = _stress_coefficients(lbmpcd, collision, alpha, 20)
+    unit = p["kT"] / p["substeps"] / p["mass"]
+    want = O.ce_nu(p) / unit
+    banner(f"stress after/before collision ({collision}, {alpha}): {c_post:.3f} / {c_pre:.3f} +- {se:.3f}; "
+           f"predicted {want:.3f} / {want + 1:.3f}")
+    assert abs(c_post - want) < 4 * se
+    assert abs(c_pre - (want + 1.0)) < 4 * se

@@ -13,7 +13,9 @@ What fixes each part, independently of the oracle's own code:
   moments must agree within their standard errors; acceptance-rejection with
   envelope A takes A attempts on average;
 * T = 0 is the Maxwell-Boltzmann exchange itself, draw for draw;
-* the kinetic viscosity is Eq. 7 without its collisional term.
+* the kinetic viscosity is Eq. 7 without its collisional term, and the
+  exchange's default stress coefficient is that less kT dt / (2m), the
+  kinetic stress right after a collision (for MPCD-AT of order 1/N).
 """
 import numpy as np
 import pytest
@@ -25,7 +27,7 @@ from paper_2004_00304_amd import workloads as W
 def _lb_channel(dim, tau, g, ny=16):
     n = (8, ny, 4) if dim == 3 else (8, ny, 1)
     return W.make(dim=dim, n=n, tau=tau, g=(g, 0.0, 0.0), mpcd=0, init_flow=1, feedback=0,
-                  reinject=1, alpha_deg=120.0 if dim == 3 else 130.0)
+                  reinject=1, alpha_deg=120.0 if dim == 3 else 130.0, ce_nu=0.7)
 
 
 @pytest.mark.parametrize("dim,tau", [(2, 0.7), (2, 1.0), (3, 0.8)])
@@ -38,7 +40,8 @@ def test_strain_of_the_discrete_poiseuille_state(dim, tau):
     nu = (tau - 0.5) / 3.0
     y = np.arange(ny) + 0.5
     dudy = g * (ny - 2 * y) / (2 * nu)
-    c = O.nu_kinetic(p) * p["mass"] / p["kT"]
+    c = O.ce_nu(p) * p["mass"] / p["kT"]
+    assert c == 0.7 * p["mass"] / p["kT"]
     want_xy = c * 0.5 * dudy  # S_xy = du/dy / 2; the trace of S vanishes
     scale = np.abs(want_xy).max()
     got_xy = T[3]  # [nz][ny][nx]
@@ -117,7 +120,7 @@ def test_nonzero_strain_changes_only_buffer_draws():
     """With a sheared LB the Chapman-Enskog exchange rejects some Maxwellian
     draws; the tensor of the buffer cells is the interpolated node tensor."""
     base = dict(dim=2, n=(16, 16, 1), ylo=4, yhi=12, ppc=5, g=(1e-4, 0.0, 0.0), init_flow=1,
-                feedback=0, tau=0.8, ce_nu_kin=2.0)
+                feedback=0, tau=0.8, ce_nu=2.0)
     b = O.Oracle(W.make(**base, reinject=1))
     b.step(1)
     tf = b.tfine()
@@ -144,4 +147,14 @@ def test_kinetic_viscosity_is_eq7_without_the_collisional_term():
         coll = a * a / (12.0 * dt) * q / N
         full = O.nu_at(p["kT"], p["mass"], dt, a, N)
         assert abs(O.nu_kinetic(p) + coll - full) <= 1e-15 * full
-    assert O.nu_kinetic(W.make(ce_nu_kin=0.25)) == 0.25
+        # the exchange's default: the kinetic stress right after the collision
+        unit = p["kT"] * dt / p["mass"]
+        assert abs(O.ce_nu(p) - (O.nu_kinetic(p) - 0.5 * unit)) <= 1e-16
+        assert abs(O.ce_nu(p) - unit * (N / q - 1.0)) <= 1e-15 * unit
+    # SRD at 90 degrees in 2D: nu_kin = kT dt/m (N/(2q) - 1/2), so the
+    # post-collision coefficient is close to -kT dt/(2m)
+    p = W.make(collision=0, alpha_deg=90.0, ppc=1000)
+    unit = p["kT"] / p["substeps"] / p["mass"]
+    assert abs(O.ce_nu(p) / unit + 0.5) < 1e-3
+    assert O.ce_nu(W.make(ce_nu=0.25)) == 0.25
+    assert O.ce_nu(W.make(ce_nu=-0.25)) == -0.25
