@@ -79,3 +79,34 @@ def test_near_wall_coupling(lbmpcd, a):
     p = W.paper_near_wall(a)
     u = run_profile(lbmpcd, p, 500, 3000)
     check(lbmpcd, p, u, 0.02, 0.03, f"near wall, a {a}")
+
+
+def _profile_error(lbmpcd, p, warm=500, steps=8000):
+    u = run_profile(lbmpcd, p, warm, steps)
+    r = p["refine"]
+    yb = p["yhi"] - p["buf_hi"]
+    J = np.arange(0, yb * r)
+    y = (J + 0.5) / r
+    nu_m = lbmpcd.viscosity(p)[1]
+    um = lb_poiseuille(p, yb) * y / yb + p["g"][0] * y * (yb - y) / (2 * nu_m)
+    return float(np.linalg.norm(u[J] - um) / np.linalg.norm(um))
+
+
+def test_near_wall_chapman_enskog_exchange(lbmpcd):
+    """The exchange at the end of Sec. 2.3 draws from a Chapman-Enskog
+    distribution when gradients are strong.  With the stress the MPCD fluid
+    carries right after its collision (the exchange's instant), SRD at 90
+    degrees -- whose post-collision stress is large and negative -- near the
+    wall at a = 1/2 comes closer to the analytic profile than with the
+    Maxwell-Boltzmann exchange; for the paper's MPCD-AT at N = 1000 that
+    stress is ~1e-4 and the two exchanges agree."""
+    srd = W.make(**{**W.paper_near_wall(0.5), "collision": 0, "alpha_deg": 90.0, "ppc": 100})
+    e_mb = _profile_error(lbmpcd, srd)
+    e_ce = _profile_error(lbmpcd, dict(srd, reinject=1))
+    banner(f"near wall a 1/2, SRD 90: Maxwell-Boltzmann {e_mb:.4f}, Chapman-Enskog {e_ce:.4f}")
+    assert e_ce < 0.025 and e_ce < 0.75 * e_mb
+    at = W.paper_near_wall(0.5)
+    e_mb = _profile_error(lbmpcd, at)
+    e_ce = _profile_error(lbmpcd, dict(at, reinject=1))
+    banner(f"near wall a 1/2, MPCD-AT: Maxwell-Boltzmann {e_mb:.4f}, Chapman-Enskog {e_ce:.4f}")
+    assert e_ce < 0.02 and abs(e_ce - e_mb) < 0.005
