@@ -42,6 +42,15 @@ CASES = {
     "at_small_3d": (W.small_3d(collision=1), 5, RTOL64),
     "at_walled_2d": (W.walled_2d(collision=1), 6, RTOL64),
     "at_small_3d_fp32": (W.small_3d(part_fp=32, collision=1), 5, RTOL32),
+    # edge cases: a refinement that is not a power of two (cell index by
+    # division), a = 1, one particle per cell (empty and singleton cells), one
+    # MPCD step per LB step, a domain smaller than one tile
+    "refine3_2d": (W.small_2d(refine=3), 5, RTOL64),
+    "refine3_3d_fp32": (W.small_3d(refine=3, part_fp=32), 4, RTOL32),
+    "refine1_2d": (W.small_2d(refine=1, ppc=20), 5, RTOL64),
+    "ppc1_3d": (W.small_3d(ppc=1), 5, RTOL64),
+    "substeps1_2d": (W.small_2d(substeps=1), 6, RTOL64),
+    "tiny_2d": (W.small_2d(n=(4, 12, 1), ylo=4, yhi=8, buf_lo=1, buf_hi=1), 6, RTOL64),
     # Chapman-Enskog exchange about a sheared LB (envelope ~1.3: about a
     # quarter of the first attempts are rejected)
     "ce_small_2d": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu=2.0), 6, RTOL64),
@@ -238,3 +247,18 @@ def test_tfine_needs_the_chapman_enskog_exchange(env):
     with pytest.raises(lbmpcd.LbmpcdError) as e:
         sim.tfine()
     assert e.value.code == 5
+
+
+def test_tile_overflow_is_reported(env):
+    """Tiles sized to their initial occupancy plus 64 slots (capacity factor
+    1, 31 particles per cell, 8x8-cell tiles: 1984 particles in 2048 slots)
+    overflow once the counts fluctuate (about 1.4 standard deviations); the
+    kernels drop the excess in bounds (every reader clamps a tile's fill to
+    its capacity) and the library reports E_OVERFLOW with the count."""
+    O, lbmpcd = env
+    banner("tile overflow")
+    sim = lbmpcd.Sim(W.small_2d(ppc=31, tile=(8, 8, 0), capacity_factor=1.0))
+    with pytest.raises(lbmpcd.LbmpcdError) as e:
+        sim.step(10)
+        sim.sync()
+    assert e.value.code == 4 and "dropped" in str(e.value), str(e.value)
