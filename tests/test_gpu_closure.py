@@ -193,9 +193,9 @@ def oneway(**kw):
     return channel(**base)
 
 
-def _train_closure(lbmpcd, torch, configs, warm=300, windows=2, window=320):
+def _train_closure(lbmpcd, torch, channels, warm=300, windows=2, window=320):
     X, Y = [], []
-    for p in configs:
+    for p in channels:
         s = lbmpcd.Sim(p)
         s.step(warm)  # past the MPCD transient from the Poiseuille start
         for _ in range(windows):
@@ -206,7 +206,7 @@ def _train_closure(lbmpcd, torch, configs, warm=300, windows=2, window=320):
         s.close()
     X = torch.cat(X)
     Y = torch.cat(Y)
-    trainer = lbmpcd.Sim(configs[0])
+    trainer = lbmpcd.Sim(channels[0])
     # the loss of the freshly initialised network (a pass with a vanishing step)
     first = trainer.closure_train(X, Y, epochs=1, batch=1024, lr=1e-30, seed=7)
     losses = np.concatenate([trainer.closure_train(X, Y, epochs=60, batch=1024, lr=2e-3),

@@ -1,5 +1,5 @@
 """Pin of the oracle's Philox4x32-10 against an independent implementation:
-rocRAND's PHILOX4_32_10 generator (run as a library on the GPU machine).  With
+rocRAND's PHILOX4_32_10 generator (run as a library on the GPU).  With
 seed s its output stream is, word by word, Philox4x32-10 with key
 (s_lo, s_hi) applied to the 128-bit counters 0, 1, 2, ... (Salmon et al.,
 SC'11, the same construction the oracle follows)."""

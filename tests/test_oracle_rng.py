@@ -2,7 +2,7 @@
 and the Box-Muller transform that the paper's exchange step names.  The
 published known-answer vectors are not available here; Philox is pinned by
 the properties a keyed bijection with full diffusion must have, and by the
-rocRAND library's own Philox4x32-10 stream on a GPU machine (tests/test_gpu_rng.py)."""
+rocRAND library's own Philox4x32-10 stream on the GPU (tests/test_gpu_rng.py)."""
 import numpy as np
 import pytest
 from scipy import stats
