@@ -300,8 +300,8 @@ def pmc_summary(fetch_csv: str, write_csv: str, command: str) -> None:
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="channel_3d",
                     choices=["channel_3d", "channel_3d_at", "channel_3d_ce", "channel_2d", "thin_film_3d",
                              "ensemble", "closure"])
