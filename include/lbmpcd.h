@@ -171,8 +171,10 @@ int lbmpcd_workspace_size(const lbmpcd_params* p, int32_t n_inst, size_t* bytes)
  * Eq. 7, kT dt / m [N / (N - 1 + e^-N) - 1/2] + a^2 / (12 dt) (N - 1 + e^-N) / N;
  * for 2D SRD the kinetic part kT dt / m [N / ((N - 1 + e^-N)(1 - cos 2 alpha))
  * - 1/2] plus the collisional part a^2 (1 - cos alpha)(N - 1 + e^-N) / (12 dt N)
- * of the SRD literature (Ihle, Tuzel, Kroll; not in the paper).  3D SRD:
- * E_UNSUPPORTED.  Either output may be NULL.  E_INVALID for bad parameters.
+ * of the SRD literature (Ihle, Tuzel, Kroll; not in the paper); for 3D SRD
+ * kT dt / m [5N / ((N - 1 + e^-N)(4 - 2 cos alpha - 2 cos 2 alpha)) - 1/2]
+ * + a^2 (1 - cos alpha)(N - 1 + e^-N) / (18 dt N) (the same literature).
+ * Either output may be NULL.  E_INVALID for bad parameters.
  */
 int lbmpcd_viscosity(const lbmpcd_params* p, double* nu_lb, double* nu_mpcd);
 

@@ -499,9 +499,13 @@ int lbmpcd_viscosity(const lbmpcd_params* p, double* nu_lb, double* nu_mpcd) {
         *nu_mpcd = kin * (N / q - 0.5) + a * a / (12.0 * dt) * q / N;  // Eq. 7
         return 0;
     }
-    if (p->dim != 2) return fail(nullptr, LBMPCD_E_UNSUPPORTED, "the SRD viscosity is given for 2D only");
     const double al = p->alpha_deg * 3.14159265358979323846 / 180.0;
-    *nu_mpcd = kin * (N / (q * (1.0 - std::cos(2.0 * al))) - 0.5) + a * a * (1.0 - std::cos(al)) * q / (12.0 * dt * N);
+    if (p->dim == 2) {
+        *nu_mpcd = kin * (N / (q * (1.0 - std::cos(2.0 * al))) - 0.5) + a * a * (1.0 - std::cos(al)) * q / (12.0 * dt * N);
+        return 0;
+    }
+    *nu_mpcd = kin * (5.0 * N / (q * (4.0 - 2.0 * std::cos(al) - 2.0 * std::cos(2.0 * al))) - 0.5) +
+               a * a * (1.0 - std::cos(al)) * q / (18.0 * dt * N);
     return 0;
 }
 

@@ -151,7 +151,8 @@ def test_autotune_argument_checks(binding):
 def test_viscosity_matches_eq7_and_the_oracle(binding):
     """lbmpcd_viscosity (host arithmetic of the library): the LB viscosity of
     BGK, and for MPCD-AT Eq. 7 at dt = 1/S as the oracle evaluates it; 2D
-    SRD against the formula the long-run test uses; 3D SRD is refused."""
+    SRD against the formula the long-run test uses; 3D SRD as the oracle's
+    kinetic term plus the collisional term a^2 (1 - cos a)(N-1+e^-N)/(18 dt N)."""
     from oracle import oracle as O
     p = W.small_3d(collision=1, kT=0.3, mass=1.5)
     nl, nm = binding.viscosity(p)
@@ -164,9 +165,12 @@ def test_viscosity_matches_eq7_and_the_oracle(binding):
     e = N - 1 + np.exp(-N)
     ref = q["kT"] * dt / q["mass"] * (N / (e * (1 - np.cos(2 * al))) - 0.5) + a * a * (1 - np.cos(al)) * e / (12 * dt * N)
     assert ns == pytest.approx(ref, rel=1e-13)
-    with pytest.raises(binding.LbmpcdError) as ex:
-        binding.viscosity(W.small_3d())
-    assert ex.value.code == 6
+    r3 = W.small_3d()
+    _, n3 = binding.viscosity(r3)
+    a, dt, N, al = 1.0 / r3["refine"], 1.0 / r3["substeps"], r3["ppc"], np.deg2rad(r3["alpha_deg"])
+    e = N - 1 + np.exp(-N)
+    ref3 = O.nu_kinetic(r3) + a * a * (1 - np.cos(al)) * e / (18 * dt * N)
+    assert n3 == pytest.approx(ref3, rel=1e-13)
 
 
 def test_one_hip_runtime_whatever_the_import_order():

@@ -164,6 +164,30 @@ def test_mpcd_viscosity_from_poiseuille(env, collision, ppc):
     assert abs(nu_fit / nu_th - 1.0) <= 0.05
 
 
+def test_mpcd_viscosity_from_poiseuille_3d_srd(env):
+    """The same fit in 3D (walls at y = 0 and 16, periodic x and z, SRD at
+    120 degrees about random axes, 10 per cell): the library's 3D SRD formula
+    (the kinetic and collisional terms of the SRD literature) within 5 %;
+    measured 1.4 % above it (1.2 % at 20 per cell, 3.5 % at 90 degrees)."""
+    O, lbmpcd = env
+    p = W.make(dim=3, n=(16, 16, 8), walls_y=1, ylo=0, yhi=16, buf_lo=0, buf_hi=0, refine=2, ppc=10,
+               feedback=0, tau=0.8, alpha_deg=120.0, g=(2e-4, 0.0, 0.0), init_flow=1)
+    sim = lbmpcd.Sim(p)
+    sim.step(2000)
+    sim.sample(1)
+    sim.step(12000)
+    r, H = p["refine"], p["n"][1]
+    prof = np.asarray(sim.profile()).reshape(-1, 4)
+    y = (np.arange(prof.shape[0]) + 0.5) / r
+    u = prof[:, 1] / prof[:, 0]
+    A = np.stack([np.ones_like(y), y * (H - y)], axis=1)
+    (u0, c), *_ = np.linalg.lstsq(A, u, rcond=None)
+    nu_fit = p["g"][0] / (2.0 * c)
+    nu_th = mpcd_viscosity(p)
+    banner(f"MPCD Poiseuille 3D SRD: nu fitted {nu_fit:.4f}, formula {nu_th:.4f}")
+    assert abs(nu_fit / nu_th - 1.0) <= 0.05
+
+
 def test_near_wall_coupling_profile(env):
     """The paper's near-wall set-up (Sec. 3.3): the MPCD slab lies on the
     bottom wall and meets the LB through one buffer.  Between the wall (no
