@@ -154,11 +154,15 @@ def test_parity_set_state_roundtrip(env):
     assert_parity(rep, RTOL64)
 
 
-def test_batched_instances_match_standalone(env):
+@pytest.mark.parametrize("kw", [dict(), dict(reinject=1, init_flow=1, g=(1e-4, 0.0, 0.0))],
+                         ids=["maxwell_boltzmann", "chapman_enskog"])
+def test_batched_instances_match_standalone(env, kw):
     """A batch of uneven channels in one context equals each channel run
-    alone through the oracle (instance i keyed by (seed, i))."""
+    alone through the oracle (instance i keyed by (seed, i)); with the
+    Chapman-Enskog exchange each instance has its own tensor scale."""
     O, lbmpcd = env
-    ps = [W.small_2d(n=(24 + 8 * i, 20 + 2 * i, 1), ylo=6, yhi=14, ppc=5 + i, instance=i) for i in range(3)]
+    ps = [W.small_2d(n=(24 + 8 * i, 20 + 2 * i, 1), ylo=6, yhi=14, ppc=5 + i, instance=i,
+                     **(dict(kw, ce_nu=0.5 + i) if kw else {})) for i in range(3)]
     sim = lbmpcd.Sim(ps)
     sim.step(4)
     bins = [sim.binning(i) for i in range(len(ps))]
