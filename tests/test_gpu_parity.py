@@ -62,6 +62,11 @@ CASES = {
     "ce_at_small_2d": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), collision=1), 6, RTOL64),
     "ce_at_small_3d": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu=1.0, collision=1),
                        5, RTOL64),
+    # slab on the bottom wall, one buffer towards the LB (virtual wall
+    # particles, specular reflection at the LB face), SRD at 90 degrees with
+    # its own (negative) post-collision stress coefficient
+    "ce_near_wall_2d": (W.make(n=(16, 24, 1), ylo=0, yhi=10, buf_lo=0, buf_hi=2, refine=2, ppc=8,
+                               alpha_deg=90.0, reinject=1, init_flow=1, g=(2e-4, 0, 0), feedback=0), 6, RTOL64),
 }
 
 
