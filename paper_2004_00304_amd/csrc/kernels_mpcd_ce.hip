@@ -4,11 +4,8 @@
 // its own so that it compiles beside the Maxwell-Boltzmann set.
 //
 // Register budget: the exchange's acceptance test keeps the cell's tensor and
-// one more Philox block live per particle; at four waves per SIMD (128 VGPRs)
-// the eight-particle kernels spill, at three they do not, and the three-wave
-// build is the faster one on MI355X (4.7 against 7.3 ms per MPCD step of the
-// 3D channel).
-#define LBMPCD_PARTICLE_WAVES 3
+// one more Philox block live per particle, so these modes are built for three
+// waves per SIMD (particle_waves in particles.hpp).
 #include "particles.hpp"
 
 namespace lbmpcd {

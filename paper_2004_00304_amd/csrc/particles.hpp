@@ -191,14 +191,20 @@ constexpr size_t LDS_COLL = (size_t)MAX_NCT * 4 + (size_t)MAX_NCT * 9 * sizeof(d
 constexpr uint32_t DROP_SLOT = 0x7FFFFFFFu;  // never a slot: the slot total stays below it
 static_assert(4 * (4 + 3 * NHASH + 2) <= (int)LDS_HDR, "LDS header too small");
 
-// Minimum resident waves per SIMD the register allocation must allow.
-#ifndef LBMPCD_PARTICLE_WAVES
-#define LBMPCD_PARTICLE_WAVES 4
-#endif
+// Minimum resident waves per SIMD the register allocation must allow.  With
+// binary32 particles (eight per thread) and in the Chapman-Enskog modes the
+// kernel spills at four (128 VGPRs) and runs faster at three (on MI355X:
+// 3.45 against 3.49 ms per MPCD step of the 3D channel with SRD, 4.93 against
+// 5.78 with MPCD-AT, 4.70 against 7.3 with the Chapman-Enskog exchange); with
+// binary64 particles (the batched 2D ensemble) four is as fast.
+template <typename PT, int MODE>
+constexpr int particle_waves() {
+    return (sizeof(PT) == 4 || (MODE & 8) != 0) ? 3 : 4;
+}
 
 // One workgroup per tile.
 template <int DIM, typename PT, int NT, int PPT, int MODE>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(LBMPCD_PARTICLE_WAVES)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(particle_waves<PT, MODE>())))
 k_particles(PArgs<PT> A) {
     constexpr bool COLL = (MODE & 1) != 0;
     constexpr bool STREAM = (MODE & 2) != 0;
