@@ -346,11 +346,20 @@ def main():
     sim.step(args.warmup)
     sim.sync()
     sim.timing(1)
+    # the timed steps in five chunks, each bracketed by events on the library's
+    # stream: the spread of the chunks shows how steady the rate is
+    chunks = [args.steps // 5 + (1 if i < args.steps % 5 else 0) for i in range(5)]
+    chunks = [n for n in chunks if n > 0]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(chunks) + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps)
+    evs[0].record(sim.stream)
+    for i, n in enumerate(chunks):
+        sim.step(n)
+        evs[i + 1].record(sim.stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    chunk_ms = [evs[i].elapsed_time(evs[i + 1]) / n for i, n in enumerate(chunks)]
     sim.timing(0)
     kt = sim.timing_read()
     sim.sync()
@@ -399,6 +408,8 @@ def main():
         "mpcd_particle_updates_per_s": tot["particles"] * p["substeps"] * sps,
         "coupled_hbm_frac": tot["total_bytes"] * sps / 1e9 / HBM_PEAK_GBS,
         "kernels_ms_per_launch": {k: v["ms"] / max(v["launches"], 1) for k, v in kt.items()},
+        "chunk_ms_per_step": chunk_ms,
+        "median_chunk_ms_per_step": float(sorted(chunk_ms)[len(chunk_ms) // 2]),
         "roofline": {
             "bound": "hbm",
             "kernel": "k_particles (fused MPCD step)",

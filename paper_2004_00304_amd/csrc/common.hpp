@@ -12,7 +12,11 @@ namespace lbmpcd {
 constexpr int WG = 256;           // threads per workgroup of every kernel
 constexpr int NCOPY = 64;         // replicas of the profile accumulators
 constexpr int MAX_NCT = 128;      // cells per particle tile
-constexpr int MAX_WIN = 32;       // LDS bins of the feedback sample window
+constexpr int MAX_WIN = 96;       // LDS bins of the feedback sample window: the nodes a tile's
+                                  // particles can sample, (Tx/r + 2)(Ty/r + 2)(Tz/r + 2) rounded
+                                  // up, for every default tile shape at r >= 2 (36 for the thin
+                                  // film's 4x4x8 cells at r = 4, 96 for 4x4x8 at r = 2); larger
+                                  // windows fall back to global atomics per sample
 constexpr int MAX_WJ = 16;        // LDS rows of the profile sample window
 constexpr uint32_t BAD_SLOT = 0xFFFFFFFFu;
 
