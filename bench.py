@@ -409,6 +409,7 @@ def main():
         "coupled_hbm_frac": tot["total_bytes"] * sps / 1e9 / HBM_PEAK_GBS,
         "kernels_ms_per_launch": {k: v["ms"] / max(v["launches"], 1) for k, v in kt.items()},
         "chunk_ms_per_step": chunk_ms,
+        "sample_window_misses": st["window_misses"],
         "median_chunk_ms_per_step": float(sorted(chunk_ms)[len(chunk_ms) // 2]),
         "roofline": {
             "bound": "hbm",

@@ -76,9 +76,11 @@ enum lbmpcd_field {
                               state is not changed)                               */
     LBMPCD_PROFILE = 9,    /* double[R][4]: per fine row sum n, sum v_x, v_y, v_z  */
     LBMPCD_UFINE = 10,     /* double[dim][nz*r][R][nx*r]: buffer-cell LB velocity  */
-    LBMPCD_STATS = 11,     /* int64[8]: lb steps, sampled steps, dropped particles,
+    LBMPCD_STATS = 11,     /* int64[9]: lb steps, sampled steps, dropped particles,
                               misplaced particles, far moves, max tile fill,
-                              particles, cells                                     */
+                              particles, cells, samples that missed their tile's LDS
+                              window and went to global atomics (a slow path: 0
+                              for the default tiles at refinement >= 2)            */
     LBMPCD_PART_VEL_PENDING = 12, /* double[dim][Np] by id: velocities before the
                               collision of the last MPCD step (get only)          */
     LBMPCD_CELL_START = 13, /* int32[ncells]: where each cell of the last binning

@@ -809,7 +809,7 @@ int lbmpcd_field_bytes(const lbmpcd_ctx* c, int32_t field, int32_t inst, size_t*
         case LBMPCD_PROFILE: *bytes = (size_t)d.R * 4 * 8; break;
         case LBMPCD_UFINE: *bytes = (size_t)c->dim * d.Cx * d.R * d.Cz * 8; break;
         case LBMPCD_TFINE: *bytes = (size_t)CE_NT * d.Cx * d.R * d.Cz * 8; break;
-        case LBMPCD_STATS: *bytes = 8 * 8; break;
+        case LBMPCD_STATS: *bytes = 9 * 8; break;
         case LBMPCD_CELL_START: *bytes = (size_t)d.ncells * 4; break;
         case LBMPCD_NODE_MPCD_U: *bytes = (size_t)c->dim * d.nslab * 8; break;
         default: return LBMPCD_E_INVALID;
@@ -928,8 +928,8 @@ int lbmpcd_moments(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t
         DevStats s;
         HIPCHK(c, hipMemcpyAsync(&s, c->stats, sizeof(s), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        int64_t v[8] = {c->t, c->sampled_steps, (int64_t)s.dropped, (int64_t)s.misplaced, (int64_t)s.far_moves,
-                        (int64_t)s.max_fill, c->desc[inst].Np, c->desc[inst].ncells};
+        int64_t v[9] = {c->t, c->sampled_steps, (int64_t)s.dropped, (int64_t)s.misplaced, (int64_t)s.far_moves,
+                        (int64_t)s.max_fill, c->desc[inst].Np, c->desc[inst].ncells, (int64_t)s.window_misses};
         if (on_dev) HIPCHK(c, hipMemcpy(dst, v, sizeof(v), hipMemcpyHostToDevice));
         else std::memcpy(dst, v, sizeof(v));
         return 0;

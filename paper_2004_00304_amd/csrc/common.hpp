@@ -198,6 +198,7 @@ struct DevStats {
     unsigned long long far_moves;   // particles moving beyond the neighbour tiles
     unsigned int max_fill;          // largest tile occupancy seen
     unsigned int pad;
+    unsigned long long window_misses;  // samples outside their tile's LDS window (global atomics)
 };
 
 // Particle arrays of one buffer: positions, velocities, ids (slot-indexed).

@@ -211,7 +211,7 @@ k_particles(PArgs<PT> A) {
     constexpr bool AT = (MODE & 4) != 0;  // MPCD-AT collision (Eq. 6) instead of SRD (Eq. 4)
     constexpr bool CE = (MODE & 8) != 0;  // Chapman-Enskog exchange instead of Maxwell-Boltzmann
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t* wstat = (uint32_t*)smem;          // [4] far moves, misplaced
+    uint32_t* wstat = (uint32_t*)smem;          // [4] far moves, misplaced, samples outside the LDS windows
     uint32_t* hkey = wstat + 4;                 // [NHASH] destination tiles (local index)
     uint32_t* hcnt = hkey + NHASH;              // [NHASH + 1] particles per destination
     uint32_t* gbase = hcnt + NHASH + 1;         // [NHASH + 1] reserved run start
@@ -579,6 +579,7 @@ k_particles(PArgs<PT> A) {
                         double* gb = A.acc + (d.acc_off + sidx) * 4;
 #pragma unroll
                         for (int q = 0; q < DIM + 1; ++q) gl_add(&gb[q], vals[q]);
+                        atomicAdd(&wstat[2], 1u);
                     }
                 }
                 if (A.do_prof) {
@@ -590,6 +591,7 @@ k_particles(PArgs<PT> A) {
                         double* gb = A.prof + (d.prof_off + (long long)copy * d.R + J) * 4;
 #pragma unroll
                         for (int q = 0; q < DIM + 1; ++q) gl_add(&gb[q], vals[q]);
+                        atomicAdd(&wstat[2], 1u);
                     }
                 }
             }
@@ -748,6 +750,7 @@ k_particles(PArgs<PT> A) {
             A.fill_in[T] = 0u;
             if (wstat[0]) atomicAdd(&A.stats->far_moves, (unsigned long long)wstat[0]);
             if (wstat[1]) atomicAdd(&A.stats->misplaced, (unsigned long long)wstat[1]);
+            if (wstat[2]) atomicAdd(&A.stats->window_misses, (unsigned long long)wstat[2]);
         }
     }
 }

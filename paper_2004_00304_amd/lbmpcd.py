@@ -317,11 +317,11 @@ class Sim:
         torch = self.torch
         field = FIELD_NAMES.get(field, field) if isinstance(field, str) else field
         if field == STATS:
-            out = np.zeros(8, np.int64)
-            _check(_lib.lbmpcd_moments(self._h, STATS, inst, out.ctypes.data_as(C.c_void_p), 64, 0),
+            out = np.zeros(9, np.int64)
+            _check(_lib.lbmpcd_moments(self._h, STATS, inst, out.ctypes.data_as(C.c_void_p), 72, 0),
                    self._h)
             keys = ("lb_steps", "sampled_steps", "dropped", "misplaced", "far_moves", "max_fill",
-                    "particles", "cells")
+                    "particles", "cells", "window_misses")
             return dict(zip(keys, (int(x) for x in out)))
         dtype = torch.int32 if field in (CELL_ID, CELL_COUNT, CELL_START) else torch.float64
         if field == POP:

@@ -271,3 +271,26 @@ def test_tile_overflow_is_reported(env):
         sim.step(10)
         sim.sync()
     assert e.value.code == 4 and "dropped" in str(e.value), str(e.value)
+
+
+def test_sample_window_misses_are_counted(env):
+    """Samples that fall outside their tile's LDS window go to global atomics
+    and are counted.  With the default tiles at r = 2 and 4 the window holds
+    every node the tile's particles reach except across the slab, so the
+    misses are particles re-wrapped from one face to the other (far moves);
+    at r = 1 the 3D window of a 4x4x4-cell tile spans 6x6x6 nodes, more than
+    the table holds, and every sample takes the global path (the results do
+    not depend on the path: parity cases refine1_2d and small_3d)."""
+    O, lbmpcd = env
+    banner("sample window misses")
+    for p in (W.small_3d(), W.small_2d()):
+        sim = lbmpcd.Sim(p)
+        sim.step(2)
+        st = sim.stats()
+        assert st["window_misses"] <= st["far_moves"] + 0.02 * st["particles"] * st["lb_steps"], st
+    p = W.small_3d(refine=1, ppc=20)
+    sim = lbmpcd.Sim(p)
+    sim.step(2)
+    st = sim.stats()
+    # one sample per particle per LB step (feedback on)
+    assert st["window_misses"] == 2 * st["particles"], st
