@@ -12,8 +12,10 @@
  * are joined by the coupling procedure of Alg. 1 and Alg. 2: after each LB
  * step the LB velocity is interpolated to the fine cells of the buffer and
  * the buffer particles are redrawn from the Maxwell-Boltzmann distribution
- * about it (Box-Muller); optionally the MPCD averages are projected back onto
- * LB equilibria in the slab interior.
+ * about it (Box-Muller), or (reinject = 1) from the first-order
+ * Chapman-Enskog distribution that the end of Sec. 2.3 names for strong
+ * gradients; optionally the MPCD averages are projected back onto LB
+ * equilibria in the slab interior.
  *
  * Conventions (lattice units, dx = dt_LB = 1):
  *   - node (i,j,k) sits at (i+1/2, j+1/2, k+1/2); walls at y = 0 and y = ny;
