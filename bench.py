@@ -64,17 +64,29 @@ def totals(plist: list) -> dict:
     return out
 
 
-def measured_traffic(per_launch_particles: int):
-    """HBM bytes per launch of the particle kernel from the committed rocprofv3
-    PMC summary (FETCH_SIZE, WRITE_SIZE scaled by a plain copy of known size),
-    or None when the summary is absent or the kernel changed since."""
+def _pmc():
+    """The committed rocprofv3 PMC summary (FETCH_SIZE, WRITE_SIZE scaled by a
+    plain copy of known size), or None when it is absent or the kernel
+    changed since it was taken."""
     if not os.path.exists(PMC_FILE):
         return None
     with open(PMC_FILE) as f:
         pmc = json.load(f)
     if pmc.get("kernel_hash") != kernel_hash():
         return None
-    return pmc.get("bytes_per_launch")
+    return pmc
+
+
+def measured_traffic(per_launch_particles: int):
+    """HBM bytes per launch of the particle kernel from the PMC summary."""
+    pmc = _pmc()
+    return pmc.get("bytes_per_launch") if pmc else None
+
+
+def measured_step_traffic():
+    """HBM bytes per coupled LB step (all its kernels) from the PMC summary."""
+    pmc = _pmc()
+    return pmc.get("step_bytes_per_lb_step") if pmc else None
 
 
 def cpu_baseline_ensemble(plist: list, seconds_cap: float = 15.0) -> dict:
@@ -276,6 +288,15 @@ def pmc_summary(fetch_csv: str, write_csv: str, command: str) -> None:
     names = sorted({k.split("(")[0].replace("void ", "").replace("lbmpcd::", "") for k in f if is_fused(k)})
     fetch_b = sum(pf) / len(pf) * 1024 * fscale
     write_b = sum(pw) / len(pw) * 1024 * wscale
+
+    # the coupled step: S particle launches plus one LB step, band and
+    # interpolation launch (the particle kernel's figures above, the others'
+    # averages over their dispatches)
+    def mean_bytes(tag):
+        fk = [v for k, vs in f.items() if tag in k for v in vs]
+        wk = [v for k, vs in w.items() if tag in k for v in vs]
+        return (sum(fk) / len(fk) * fscale + sum(wk) / len(wk) * wscale) * 1024 if fk and wk else 0.0
+    other = {t: mean_bytes(t) for t in ("k_lb_step", "k_band", "k_interp")}
     p = W.channel_3d()
     alg = W.algorithmic_bytes_per_lb_step(p)["per_particle_update"] * W.sizes(p)["particles"]
     out = {
@@ -291,6 +312,8 @@ def pmc_summary(fetch_csv: str, write_csv: str, command: str) -> None:
         "bytes_per_launch": fetch_b + write_b,
         "algorithmic_bytes_per_launch": alg,
         "traffic_over_algorithmic": (fetch_b + write_b) / alg,
+        "other_kernels_bytes_per_lb_step": other,
+        "step_bytes_per_lb_step": p["substeps"] * (fetch_b + write_b) + sum(other.values()),
     }
     with open(PMC_FILE, "w") as fo:
         json.dump(out, fo, indent=1)
@@ -374,6 +397,7 @@ def main():
     per_launch = tot["launch_bytes"]
     achieved = per_launch / (part_ms * 1e-3) / 1e9
     traffic = measured_traffic(tot["particles"]) if args.workload == "channel_3d" else None
+    step_traffic = measured_step_traffic() if args.workload == "channel_3d" else None
     if args.workload == "ensemble":
         wl = (f"ensemble: 256 2D channels (D2Q9, widths 16-128, lengths 32-256, strip W/4 with 1-row "
               f"buffers, r 4, 5-20 ppc, FP64), {tot['nodes']} nodes, {tot['particles']} particles, "
@@ -407,6 +431,9 @@ def main():
         "lb_mlups": tot["nodes"] * sps / 1e6,
         "mpcd_particle_updates_per_s": tot["particles"] * p["substeps"] * sps,
         "coupled_hbm_frac": tot["total_bytes"] * sps / 1e9 / HBM_PEAK_GBS,
+        # counter-measured HBM traffic of the whole coupled step (rocprofv3
+        # FETCH_SIZE + WRITE_SIZE of every kernel of an LB step) per second
+        "coupled_counter_frac": (step_traffic * sps / 1e9 / HBM_PEAK_GBS) if step_traffic else None,
         "kernels_ms_per_launch": {k: v["ms"] / max(v["launches"], 1) for k, v in kt.items()},
         "chunk_ms_per_step": chunk_ms,
         "sample_window_misses": st["window_misses"],
