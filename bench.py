@@ -9,7 +9,15 @@ axis, 4 MPCD steps per LB step, random grid shift, feedback on.  Synthetic,
 seeded: positions uniform in cells, Maxwell-Boltzmann velocities.
 
 One "step" is one coupled LB step (LB collide-stream, feedback projection,
-interpolation to the buffer cells, 4 fused MPCD steps).  Prints one JSON line.
+interpolation to the buffer cells, 4 fused MPCD steps).  Prints one JSON line:
+the contract's fields; `roofline` for the fused particle kernel (algorithmic
+bytes per launch over its HIP-event time, against 8 TB/s; `traffic` from the
+committed rocprofv3 PMC summary while the kernel source is unchanged);
+`coupled_hbm_frac` (algorithmic) and `coupled_counter_frac` (counter-measured)
+for the whole step; the timed steps in five chunks; the sample-window misses;
+and `cpu_baseline`, the oracle timed on one host core on a cut of the workload.
+Other workloads: --workload channel_3d_at | channel_3d_ce | thin_film_3d |
+channel_2d | ensemble | closure.
 """
 from __future__ import annotations
 
