@@ -418,6 +418,7 @@ static int validate(const orc_params* p) {
     if (p->collision != 0 && p->collision != 1) return 1;
     if (p->reinject != 0 && p->reinject != 1) return 1;
     if (p->reinject && (!(p->kT > 0.0) || !isfinite(p->ce_nu))) return 1;
+    if (p->reinject && !isfinite(orc_ce_nu(p))) return 1;  /* SRD at alpha = 0 without ce_nu */
     return 0;
 }
 

@@ -202,6 +202,8 @@ int geometry(const lbmpcd_params& p, Geometry& g, std::string& msg) {
     return 0;
 }
 
+double ce_nu(const lbmpcd_params& p);
+
 int validate_one(const lbmpcd_params& p, std::string& msg) {
     if (p.abi_version != LBMPCD_ABI_VERSION) { msg = "abi_version mismatch"; return LBMPCD_E_INVALID; }
     if (p.struct_size != sizeof(lbmpcd_params)) { msg = "struct_size mismatch"; return LBMPCD_E_INVALID; }
@@ -239,6 +241,10 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     Geometry g;
     if (geometry(p, g, msg)) return LBMPCD_E_INVALID;
     if (g.Np >= (1LL << 32) - 1) { msg = "too many particles for 32-bit ids"; return LBMPCD_E_INVALID; }
+    if (p.reinject && !std::isfinite(ce_nu(p))) {
+        msg = "the default Chapman-Enskog coefficient is not finite for this collision rule (SRD at alpha = 0); set ce_nu";
+        return LBMPCD_E_INVALID;
+    }
     return 0;
 }
 

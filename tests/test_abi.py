@@ -60,7 +60,7 @@ def test_workspace_sizes(binding):
     (dict(part_fp=16), 1), (dict(refine=0), 1), (dict(n=(8, 8, 2)), 1),
     (dict(walls_y=0, ylo=0, yhi=8), 6), (dict(substeps=300), 1),
     (dict(reinject=2), 1), (dict(reinject=1, kT=0.0), 1), (dict(ce_nu=float("nan")), 1),
-    (dict(ce_nu=float("inf")), 1),
+    (dict(ce_nu=float("inf")), 1), (dict(reinject=1, alpha_deg=0.0), 1),
 ])
 def test_invalid_params(binding, kw, code):
     with pytest.raises(binding.LbmpcdError) as e:

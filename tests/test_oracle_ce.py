@@ -158,3 +158,11 @@ def test_kinetic_viscosity_is_eq7_without_the_collisional_term():
     assert abs(O.ce_nu(p) / unit + 0.5) < 1e-3
     assert O.ce_nu(W.make(ce_nu=0.25)) == 0.25
     assert O.ce_nu(W.make(ce_nu=-0.25)) == -0.25
+
+
+def test_degenerate_default_coefficient_is_refused():
+    """SRD at alpha = 0 has no finite kinetic viscosity: the default
+    coefficient is refused, an explicit ce_nu is accepted."""
+    with pytest.raises(ValueError):
+        O.Oracle(W.make(n=(8, 16, 1), ylo=4, yhi=12, reinject=1, alpha_deg=0.0))
+    O.Oracle(W.make(n=(8, 16, 1), ylo=4, yhi=12, reinject=1, alpha_deg=0.0, ce_nu=0.1))
