@@ -59,6 +59,8 @@ CASES = {
     "ce_small_3d": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu=2.0), 5, RTOL64),
     "ce_small_3d_fp32": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu=2.0, part_fp=32),
                          5, RTOL32),
+    # driven along z: the yz component of the tensor carries the shear
+    "ce_small_3d_gz": (W.small_3d(reinject=1, init_flow=1, g=(0, 0, 1e-4), ce_nu=2.0), 5, RTOL64),
     "ce_at_small_2d": (W.small_2d(reinject=1, init_flow=1, g=(1e-4, 0, 0), collision=1), 6, RTOL64),
     "ce_at_small_3d": (W.small_3d(reinject=1, init_flow=1, g=(1e-4, 0, 0), ce_nu=1.0, collision=1),
                        5, RTOL64),

@@ -54,6 +54,24 @@ def test_strain_of_the_discrete_poiseuille_state(dim, tau):
     assert np.abs(tr).max() <= 1e-15 * max(scale, 1e-300) + 1e-22
 
 
+def test_strain_yz_of_a_channel_driven_along_z():
+    """The same closed form with the body force along z pins the yz
+    component of the tensor (the walls are at y = 0 and ny)."""
+    g, ny, tau = 1e-5, 16, 0.8
+    p = W.make(dim=3, n=(4, ny, 8), tau=tau, g=(0.0, 0.0, g), mpcd=0, init_flow=1, feedback=0,
+               reinject=1, alpha_deg=120.0, ce_nu=0.7)
+    o = O.Oracle(p)
+    o.step(6000)
+    T = o.ce_tensor()
+    nu = (tau - 0.5) / 3.0
+    y = np.arange(ny) + 0.5
+    want = 0.7 * p["mass"] / p["kT"] * 0.5 * g * (ny - 2 * y) / (2 * nu)
+    scale = np.abs(want).max()
+    assert np.abs(T[5] - want[None, :, None]).max() <= 1e-7 * scale
+    for m in (0, 1, 2, 3, 4):
+        assert np.abs(T[m]).max() <= 2e-3 * scale, m
+
+
 def _traceless(dim, rng, amp):
     A = rng.uniform(-amp, amp, (3, 3))
     A = 0.5 * (A + A.T)
