@@ -296,3 +296,24 @@ def test_sample_window_misses_are_counted(env):
     st = sim.stats()
     # one sample per particle per LB step (feedback on)
     assert st["window_misses"] == 2 * st["particles"], st
+
+
+def test_chapman_enskog_xz_shear_parity(env):
+    """The xz component of the Chapman-Enskog tensor: both sides start from
+    the same populations of a shear wave u_x(z) (set through lbmpcd_set_state
+    and the oracle's set_f) and run the coupled step with the exchange."""
+    O, lbmpcd = env
+    from tests.test_oracle_ce import shear_wave_f
+    p = W.small_3d(reinject=1, g=(0.0, 0.0, 0.0), ce_nu=2.0, feedback=0)
+    f = shear_wave_f(p, 0.02)
+    banner("chapman-enskog xz shear parity")
+    sim = lbmpcd.Sim(p)
+    orc = O.Oracle(_params(p))
+    sim.set_state(lbmpcd.POP, f)
+    orc.set_f(f)
+    sim.step(4)
+    orc.step(4)
+    rep = compare_state(sim, orc, p, RTOL64)
+    banner(f"xz shear: {rep}")
+    assert_parity(rep, RTOL64)
+    assert np.abs(orc.tfine()[4]).max() > 1e-3
