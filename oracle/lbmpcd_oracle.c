@@ -50,6 +50,17 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* Philox4x32-10 of the consecutive 128-bit counters first, first + 1, ...
+ * (n of them, below 2^64) under one key: out[4n], the stream a counter-mode
+ * generator seeded with the key produces. */
+void orc_philox_stream(const uint32_t key[2], uint64_t first, uint64_t n, uint32_t* out) {
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t c = first + i;
+        uint32_t ctr[4] = {(uint32_t)c, (uint32_t)(c >> 32), 0u, 0u};
+        orc_philox4x32_10(ctr, key, out + 4 * i);
+    }
+}
+
 /* uniform in [0,1) from the top 53 bits of a 64-bit word (hi:lo) */
 double orc_u01(uint32_t lo, uint32_t hi) {
     uint64_t x = ((uint64_t)hi << 32) | (uint64_t)lo;

@@ -121,6 +121,9 @@ void orc_collide_cell(const orc_state* s, int32_t c, uint32_t t, uint32_t sub, c
 /* ---- building blocks, exported for the pins ---------------------------- */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_u01(uint32_t lo, uint32_t hi);
+/* Philox4x32-10 of the counters first .. first + n - 1 (as 128-bit integers)
+ * under one key: out[4n] */
+void orc_philox_stream(const uint32_t key[2], uint64_t first, uint64_t n, uint32_t* out);
 /* lattice tables: returns Q; c is Q*3 ints, w is Q doubles, opp is Q ints */
 int  orc_lattice(int32_t dim, int32_t* c, double* w, int32_t* opp);
 void orc_feq(int32_t dim, double rho, const double u[3], double* feq);

@@ -76,6 +76,7 @@ def lib():
         L.orc_get_binning.argtypes = [P, P, P, P, P, P]
         L.orc_get_profile.argtypes = [P, P, P]
         L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_philox_stream.argtypes = [P, C.c_uint64, C.c_uint64, P]
         L.orc_u01.argtypes = [C.c_uint32, C.c_uint32]
         L.orc_u01.restype = C.c_double
         L.orc_lattice.argtypes = [C.c_int32, P, P, P]
@@ -266,6 +267,14 @@ def philox(ctr, key) -> np.ndarray:
     k = np.asarray(key, np.uint32)
     out = np.empty(4, np.uint32)
     lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def philox_stream(key, first: int, n: int) -> np.ndarray:
+    """Philox4x32-10 of the consecutive counters first .. first + n - 1: [n][4]."""
+    k = np.asarray(key, np.uint32)
+    out = np.empty((n, 4), np.uint32)
+    lib().orc_philox_stream(_ptr(k), int(first), int(n), _ptr(out))
     return out
 
 
