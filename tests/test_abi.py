@@ -184,3 +184,17 @@ def test_one_hip_runtime_whatever_the_import_order():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True,
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert out.stdout.strip() == "1", out.stdout + out.stderr
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The HIP library is the only compute path: a copy of the package
+    without liblbmpcd.so refuses to import instead of falling back."""
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2004_00304_amd")
+    shutil.copytree(src, tmp_path / "paper_2004_00304_amd",
+                    ignore=shutil.ignore_patterns("*.so", "_build", "__pycache__", "csrc"))
+    r = subprocess.run([sys.executable, "-c", "from paper_2004_00304_amd import lbmpcd"], cwd=tmp_path,
+                       capture_output=True, text=True)
+    assert r.returncode != 0 and "is not built" in r.stderr, r.stderr[-500:]
