@@ -198,3 +198,17 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", "from paper_2004_00304_amd import lbmpcd"], cwd=tmp_path,
                        capture_output=True, text=True)
     assert r.returncode != 0 and "is not built" in r.stderr, r.stderr[-500:]
+
+
+def test_product_never_touches_the_oracle():
+    """The oracle is test infrastructure: no source of the package (Python,
+    HIP, C++) imports, includes or loads it."""
+    root = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2004_00304_amd")
+    hits = []
+    for dirpath, _, files in os.walk(root):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn), encoding="utf-8").read()
+                if re.search(r"import\\s+oracle|from\\s+oracle|lbmpcd_oracle|orc_", text):
+                    hits.append(fn)
+    assert not hits, hits
