@@ -209,6 +209,6 @@ def test_product_never_touches_the_oracle():
         for fn in files:
             if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, fn), encoding="utf-8").read()
-                if re.search(r"import\\s+oracle|from\\s+oracle|lbmpcd_oracle|orc_", text):
+                if re.search(r"import\s+oracle|from\s+oracle|lbmpcd_oracle|orc_", text):
                     hits.append(fn)
     assert not hits, hits
