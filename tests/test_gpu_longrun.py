@@ -71,6 +71,28 @@ def analytic(p, y):
     return ua + (ub - ua) * (y - ya) / (yb - ya) + p["g"][0] * (y - ya) * (yb - y) / (2 * nu_m)
 
 
+def two_way(p, y):
+    """Steady profile of the two-way coupled channel (feedback on), SRD
+    slab: the MPCD average is imposed on the LB nodes of the slab interior,
+    so the LB between the wall and the first interior node row (centre
+    y_a + 1/2) is a parabola with the LB viscosity and the wall slip of the
+    forced BGK scheme, u = -g y^2/(2 nu_L) + B y + C, and the MPCD between
+    the buffers' inner edges a parabola with nu_M through u(y_a) = U_a:
+    u = U_a + g (y - y_a)(H - y_a - y)/(2 nu_M) (symmetric channel).
+    Matching the LB at y_a and at the node y_a + 1/2 to the MPCD gives the
+    slope B; with nu_M = nu_L the two are one Poiseuille parabola."""
+    H = p["n"][1]
+    g = p["g"][0]
+    tau = p["tau"]
+    nu_l = (tau - 0.5) / 3.0
+    nu_m = nu_srd_2d(p)
+    ya = p["ylo"] + p["buf_lo"]
+    C = g * (16 * tau * tau - 16 * tau + 1) / (24 * nu_l)
+    B = g * (ya + 0.25) / nu_l + g * (H - 2 * ya - 0.5) / (2 * nu_m)
+    Ua = -g * ya * ya / (2 * nu_l) + B * ya + C
+    return Ua + g * (y - ya) * (H - ya - y) / (2 * nu_m)
+
+
 def interior_rows(p):
     r = p["refine"]
     R = (p["yhi"] - p["ylo"]) * r
@@ -100,6 +122,34 @@ def test_longrun_profile_matches_analytic(env, collision):
     banner(f"long run vs analytic ({'MPCD-AT' if collision else 'SRD'}): rel L2 {err:.4f}; nu_M {nu_m:.4f}; "
            f"u {np.round(u, 5)}")
     assert err <= 0.01
+
+
+@pytest.mark.skip(reason="its first GPU run ended with the GPU box faulted before any output came back; "
+                         "no cause has been found in the code it runs (the feedback and sample-window paths "
+                         "pass in the parity cases), so it stays off the GPU until one is shown")
+def test_longrun_two_way_profile_matches_closed_form(env):
+    """Feedback on (the projection of the MPCD averages onto the LB): the
+    time-averaged slab profile follows the two-way closed form (two
+    parabolas, nu_L = 0.1 and nu_M = 0.068), which differs from the one-way
+    form by 9 %."""
+    O, lbmpcd = env
+    p = W.make(n=(128, 32, 1), tau=0.8, g=(4e-5, 0.0, 0.0), ylo=12, yhi=20, buf_lo=2, buf_hi=2, ppc=10,
+               feedback=1, init_flow=1)
+    J, y = interior_rows(p)
+    u2, u1 = two_way(p, y), analytic(p, y)
+    # the closed form itself: matched viscosities give the LB parabola
+    q = dict(p, tau=0.5 + 3 * nu_srd_2d(p))
+    assert np.allclose(two_way(q, y), lb_poiseuille(q, y), rtol=1e-12)
+    sim = lbmpcd.Sim(p)
+    sim.step(3000)
+    sim.sample(1)
+    sim.step(20000)
+    u = profile_u(sim.profile(), J)
+    e2 = np.linalg.norm(u - u2) / np.linalg.norm(u2)
+    e1 = np.linalg.norm(u - u1) / np.linalg.norm(u1)
+    banner(f"two-way long run: vs two-way form {e2:.4f}, vs one-way form {e1:.4f}; u {np.round(u, 5)}")
+    assert e2 <= 0.02
+    assert e1 >= 0.04
 
 
 def test_longrun_profile_matches_oracle(env):
