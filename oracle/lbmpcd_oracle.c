@@ -388,6 +388,7 @@ struct orc_state {
     double* tnode;      /* [6][N] Chapman-Enskog tensor of every node */
     double* tfine;      /* [6][Cz][R][Cx] interpolated to the buffer fine cells */
     double* acc;        /* [(iz*R+J)*nx+ix][4] */
+    double* fbu;        /* [((iz*(yhi-ylo))+y-ylo)*nx+ix][3] running mean the feedback projects */
     double* prof;       /* [R][4] */
     int64_t prof_steps;
     int sampling;
@@ -395,6 +396,7 @@ struct orc_state {
     double shift[3];    /* grid shift of the last MPCD step */
     double dt, cos_a, sin_a, a;
     double* scratch;    /* per-cell velocity gather */
+    int64_t bad;        /* invalid particles / band nodes found in the last LB step */
 };
 
 static int64_t node_index(const orc_state* s, int x, int y, int z) {
@@ -430,6 +432,7 @@ static int validate(const orc_params* p) {
     if (p->reinject != 0 && p->reinject != 1) return 1;
     if (p->reinject && (!(p->kT > 0.0) || !isfinite(p->ce_nu))) return 1;
     if (p->reinject && !isfinite(orc_ce_nu(p))) return 1;  /* SRD at alpha = 0 without ce_nu */
+    if (p->fb_window < 0) return 1;
     return 0;
 }
 
@@ -438,7 +441,7 @@ void orc_destroy(orc_state* s) {
     free(s->f); free(s->ftmp);
     for (int k = 0; k < 3; ++k) { free(s->pos[k]); free(s->vel[k]); }
     free(s->cell_of); free(s->count); free(s->start); free(s->order);
-    free(s->vcm); free(s->ufine); free(s->unode); free(s->acc); free(s->prof);
+    free(s->vcm); free(s->ufine); free(s->unode); free(s->acc); free(s->prof); free(s->fbu);
     free(s->tnode); free(s->tfine);
     free(s->scratch);
     free(s);
@@ -524,14 +527,23 @@ int orc_create(const orc_params* p, orc_state** out) {
         s->tfine = (double*)calloc((size_t)(6 * s->Cx * s->R * s->Cz), sizeof(double));
         s->acc = (double*)calloc((size_t)(4 * p->nx * s->R * p->nz), sizeof(double));
         s->prof = (double*)calloc((size_t)(4 * s->R), sizeof(double));
+        s->fbu = (double*)calloc((size_t)(3 * p->nx * (p->yhi - p->ylo) * p->nz), sizeof(double));
         s->scratch = (double*)malloc(sizeof(double) * 3 * 4096);
         for (int k = 0; k < 3; ++k)
             if (!s->pos[k] || !s->vel[k]) { orc_destroy(s); return 2; }
         if (!s->cell_of || !s->order || !s->count || !s->start || !s->vcm || !s->ufine ||
-            !s->acc || !s->prof || !s->scratch || !s->tnode || !s->tfine) {
+            !s->acc || !s->prof || !s->scratch || !s->tnode || !s->tfine || !s->fbu) {
             orc_destroy(s);
             return 2;
         }
+        /* the running mean of the feedback starts at the initial velocity of
+         * every slab node */
+        for (int z = 0; z < p->nz; ++z)
+            for (int y = p->ylo; y < p->yhi; ++y)
+                for (int x = 0; x < p->nx; ++x)
+                    for (int k = 0; k < 3; ++k)
+                        s->fbu[3 * (((int64_t)z * (p->yhi - p->ylo) + (y - p->ylo)) * p->nx + x) + k] =
+                            p->init_flow ? poiseuille(p, p->g[k], y + 0.5) : 0.0;
         /* READING: exactly ppc particles in every fine cell, uniform inside the
          * cell, ids in cell order; Maxwell-Boltzmann velocities of variance
          * kT/m about the initial flow. */
@@ -613,12 +625,21 @@ static void node_moments(const orc_state* s, int64_t n, double* rho, double u[3]
 
 /* READING (feedback, not in the paper, which couples one way only): at LB
  * nodes of the slab that are not buffer nodes, replace the post-stream
- * populations by the equilibrium at the LB density and at the mean MPCD
- * velocity sampled over the node during the previous LB step, so that the
- * node's physical velocity equals the MPCD average. */
+ * populations by the equilibrium at the LB density and at a time average of
+ * the MPCD velocity sampled over the node, so that the node's physical
+ * velocity equals that average.  The average is a running mean over the LB
+ * steps: every LB step that sampled the node moves it towards the step's
+ * sample mean by the weight 1/W (W = fb_window LB steps, 50 by default); it
+ * starts at the node's initial velocity.  The paper averages MPCD profiles
+ * over many samples because a single sample is dominated by thermal noise
+ * (Sec. 3.1); a node of r^d cells holds a few hundred particles, whose mean
+ * carries a noise of the size of the flow itself, and projecting it
+ * instantaneously (W = 1) drives the LB unstable. */
+#define FB_WINDOW_DEFAULT 50
 static void feedback_override(orc_state* s) {
     const orc_params* p = &s->p;
     int r = p->refine;
+    const double lam = 1.0 / (double)(p->fb_window > 0 ? p->fb_window : FB_WINDOW_DEFAULT);
     for (int z = 0; z < p->nz; ++z)
         for (int y = p->ylo + p->buf_lo; y < p->yhi - p->buf_hi; ++y)
             for (int x = 0; x < p->nx; ++x) {
@@ -630,10 +651,14 @@ static void feedback_override(orc_state* s) {
                 }
                 if (cnt <= 0.0) continue;
                 int64_t n = node_index(s, x, y, z);
+                double* e = s->fbu + 3 * (((int64_t)z * (p->yhi - p->ylo) + (y - p->ylo)) * p->nx + x);
                 double rho = 0.0;
                 for (int i = 0; i < s->Q; ++i) rho += s->f[i * s->N + n];
                 double u[3], feq[19];
-                for (int k = 0; k < 3; ++k) u[k] = sv[k] / cnt - 0.5 * p->g[k];
+                for (int k = 0; k < 3; ++k) {
+                    e[k] = (1.0 - lam) * e[k] + lam * (sv[k] / cnt);
+                    u[k] = e[k] - 0.5 * p->g[k];
+                }
                 orc_feq(p->dim, rho, u, feq);
                 for (int i = 0; i < s->Q; ++i) s->f[i * s->N + n] = feq[i];
             }
@@ -694,10 +719,18 @@ static void node_ce_tensor(const orc_state* s, int64_t n, double T[6]) {
 }
 
 static void interpolate_buffers(orc_state* s) {
+    const orc_params* p = &s->p;
+    const int by0 = p->ylo > 0 ? p->ylo - 1 : 0, by1 = p->yhi < p->ny ? p->yhi + 1 : p->ny;
     for (int64_t n = 0; n < s->N; ++n) {
         double rho, u[3];
         node_moments(s, n, &rho, u);
         for (int k = 0; k < 3; ++k) s->unode[k * s->N + n] = u[k];
+        /* READING: a node of the rows the coupling reads (the slab and one
+         * row either side) with non-positive or non-finite density or a
+         * non-finite velocity is an invalid state */
+        const int y = (int)((n / p->nx) % p->ny);
+        if (y >= by0 && y < by1 && !(rho > 0.0 && isfinite(rho) && isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2])))
+            s->bad++;
     }
     interpolate_from(s, s->p.dim, s->unode, s->ufine);
     if (s->p.reinject) {
@@ -822,7 +855,7 @@ static double wrap_periodic(const orc_state* s, double x, double lo, double L) {
  * LB-facing slab face the particle is re-wrapped periodically across the
  * slab (paper: no particles are injected, mass is conserved), or, when the
  * opposite face is a wall, reflected specularly. */
-static void stream_one(const orc_state* s, double r[3], double v[3]) {
+static int stream_one(const orc_state* s, double r[3], double v[3]) {
     const orc_params* p = &s->p;
     double dt = s->dt;
     double r0[3], v0[3];
@@ -874,13 +907,30 @@ static void stream_one(const orc_state* s, double r[3], double v[3]) {
     }
     r1[0] = wrap_periodic(s, r1[0], 0.0, (double)p->nx);
     if (p->dim == 3) r1[2] = wrap_periodic(s, r1[2], 0.0, (double)p->nz);
+    /* READING (the paper has no such case): a particle that left the domain
+     * by more than one period in one MPCD step, or whose position or velocity
+     * is not finite, is an invalid state of the run (a diverged LB field
+     * handing out such velocities, say).  It is parked at the lower corner of
+     * the slab with zero velocity, so that every index derived from it stays
+     * in range, and the step reports the state as invalid. */
+    int bad = !(r1[0] >= 0.0 && r1[0] < (double)p->nx);
+    if (p->dim == 3) bad |= !(r1[2] >= 0.0 && r1[2] < (double)p->nz);
+    bad |= !(r1[1] >= (s->ywrap ? 0.0 : ylo) && r1[1] < (s->ywrap ? (double)p->ny : yhi));
+    for (int d = 0; d < p->dim; ++d) bad |= !isfinite(v1[d]);
+    if (bad) {
+        for (int d = 0; d < 3; ++d) v1[d] = 0.0;
+        r1[0] = 0.0;
+        r1[1] = s->ywrap ? 0.0 : ylo;
+        r1[2] = 0.0;
+    }
     for (int d = 0; d < p->dim; ++d) { r[d] = r1[d]; v[d] = v1[d]; }
+    return bad;
 }
 
 static void stream_particle(orc_state* s, int64_t k) {
     double r[3], v[3];
     for (int d = 0; d < 3; ++d) { r[d] = s->pos[d][k]; v[d] = s->vel[d][k]; }
-    stream_one(s, r, v);
+    s->bad += stream_one(s, r, v);
     for (int d = 0; d < s->p.dim; ++d) { s->pos[d][k] = r[d]; s->vel[d][k] = v[d]; }
 }
 
@@ -934,6 +984,9 @@ static int32_t cell_of_pos(const orc_state* s, const double r[3], const double s
     if (ix >= s->Cx) ix -= s->Cx;
     int iy = bin_coord(s, r[1], (double)p->ylo, sh[1]);
     if (s->ywrap && iy >= s->R) iy -= s->R;
+    /* a binary32 sum y - ylo + shift can round up to the slab height plus
+     * a full cell; the particle belongs to the last row of the grid */
+    if (iy > s->CyB - 1) iy = s->CyB - 1;
     int iz = 0;
     if (p->dim == 3) {
         iz = bin_coord(s, r[2], 0.0, sh[2]);
@@ -958,19 +1011,24 @@ static void collide_one(const orc_state* s, int32_t c, uint32_t t, uint32_t sub,
     const orc_params* p = &s->p;
     int d = p->dim;
     int iy = (c / s->Cx) % s->CyB;
-    double pv[3] = {0.0, 0.0, 0.0}, mv = 0.0;
+    /* READING (the wall rule of Lamura et al., which the paper cites): a
+     * wall-cut cell holding n < N0 particles is filled up with N0 - n virtual
+     * particles at rest in the wall frame, each with a Maxwell-Boltzmann
+     * velocity of variance kT/m per component.  Only their velocity sum
+     * enters the centre of mass: a normal deviate of variance
+     * (N0 - n) kT/m per component, i.e. momentum sqrt((N0 - n) m kT) xi.
+     * The collision routines work with unit-mass velocity sums, so this sum
+     * is passed as is, with the mass N0 - n in particle units. */
+    double pvu[3] = {0.0, 0.0, 0.0}, mv = 0.0;
     int cut = (sh[1] > 0.0) && ((s->bot_wall && iy == 0) || (s->top_wall && iy == s->R));
     if (cut && n < p->ppc) {
         double z[3];
         rng_normals(p, (uint32_t)c, t, sub, P_WALL, z);
         int nv = p->ppc - n;
         double sdv = sqrt((double)nv * p->kT / p->mass);
-        for (int k = 0; k < d; ++k) pv[k] = sdv * z[k];
+        for (int k = 0; k < d; ++k) pvu[k] = sdv * z[k];
         mv = (double)nv;
     }
-    /* virtual momentum enters in units of m; the collision routines use
-     * unit mass so the momentum is divided by m */
-    double pvu[3] = {pv[0] / p->mass, pv[1] / p->mass, pv[2] / p->mass};
     if (p->collision == 1) {
         /* MPCD-AT: one Gaussian velocity per particle (READING: variance
          * kT/m per component, as for the exchange step), keyed by the
@@ -1052,6 +1110,7 @@ static void mpcd_substep(orc_state* s, uint32_t t, uint32_t sub) {
 int orc_step(orc_state* s, int32_t n_lb_steps) {
     const orc_params* p = &s->p;
     for (int32_t it = 0; it < n_lb_steps; ++it) {
+        s->bad = 0;
         lb_collide_stream(s);
         if (p->mpcd) {
             if (p->feedback) feedback_override(s);
@@ -1061,6 +1120,7 @@ int orc_step(orc_state* s, int32_t n_lb_steps) {
             if (s->sampling) s->prof_steps++;
         }
         s->t++;
+        if (s->bad) return 5; /* invalid state (non-finite or runaway particles or band nodes) */
     }
     return 0;
 }
@@ -1153,6 +1213,10 @@ void orc_refresh_ufine(orc_state* s) {
     if (s->p.mpcd) interpolate_buffers(s);
 }
 
+void orc_get_fb_u(const orc_state* s, double* out) {
+    memcpy(out, s->fbu, sizeof(double) * 3 * (size_t)s->p.nx * (s->p.yhi - s->p.ylo) * s->p.nz);
+}
+
 void orc_get_step_acc(const orc_state* s, double* acc) {
     memcpy(acc, s->acc, sizeof(double) * 4 * (size_t)s->p.nx * s->R * s->p.nz);
 }
@@ -1185,7 +1249,7 @@ void orc_exchange_stream(const orc_state* s, uint32_t t, uint32_t sub, int64_t n
         }
         for (int m = 0; m < 6; ++m) T[m] = tens ? tens[m * n + k] : 0.0;
         if (buffer_cell(s, r) >= 0) reinject_one(s, ids[k], t, sub, uu, tens ? T : NULL, v);
-        stream_one(s, r, v);
+        (void)stream_one(s, r, v);
         for (int d = 0; d < s->p.dim; ++d) {
             pos[d * n + k] = r[d];
             vel[d * n + k] = v[d];

@@ -17,7 +17,12 @@
  * the same float-valued binning decisions as a binary32 particle store.
  *
  * Errors: functions returning int return 0 on success and a positive code on
- * failure (1 = invalid parameters, 2 = out of memory).
+ * failure (1 = invalid parameters, 2 = out of memory, 5 = invalid state: orc_step
+ * stops after an LB step in which a particle left the domain by more than one
+ * period, or had a non-finite position or velocity, or a node of the rows the
+ * coupling reads had a non-positive or non-finite density or a non-finite
+ * velocity; such particles are parked at the slab's lower corner at rest, so
+ * every index stays in range).
  */
 #ifndef LBMPCD_ORACLE_H
 #define LBMPCD_ORACLE_H
@@ -56,6 +61,9 @@ typedef struct orc_params {
     double ce_nu;           /* viscosity coefficient of the Chapman-Enskog stress (finite);
                                0: the kinetic stress the MPCD fluid carries right after its
                                collision, the instant of the exchange: nu_kin - kT dt / (2m) */
+    int32_t fb_window;      /* feedback: LB steps W of the running mean of the node samples
+                               that is projected (weight 1/W per LB step); 0 = 50; 1 = the
+                               last LB step's sample alone */
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -93,6 +101,8 @@ void orc_get_ufine(const orc_state* s, double* ufine);
 void orc_get_profile(const orc_state* s, double* acc, int64_t* n_lb_steps_sampled);
 /* per-LB-step sample accumulators of the slab [(iz*R + J)*nx + ix][4] */
 void orc_get_step_acc(const orc_state* s, double* acc);
+/* running mean of the node samples that the feedback projects: [nz][yhi-ylo][nx][3] */
+void orc_get_fb_u(const orc_state* s, double* out);
 /* grid shift of the last MPCD step */
 void orc_get_shift(const orc_state* s, double sh[3]);
 /* recompute the buffer fine-cell velocities from the current populations */

@@ -40,7 +40,7 @@ class _Params(C.Structure):
         ("mass", C.c_double), ("kT", C.c_double), ("alpha_deg", C.c_double),
         ("grid_shift", C.c_int32), ("feedback", C.c_int32), ("init_flow", C.c_int32),
         ("seed", C.c_uint64), ("instance", C.c_uint32), ("collision", C.c_int32),
-        ("reinject", C.c_int32), ("ce_nu", C.c_double),
+        ("reinject", C.c_int32), ("ce_nu", C.c_double), ("fb_window", C.c_int32),
     ]
 
 
@@ -66,7 +66,8 @@ def lib():
         for name in ("orc_num_cells", "orc_num_fine_rows"):
             getattr(L, name).argtypes = [P]
             getattr(L, name).restype = C.c_int32
-        for name in ("orc_get_f", "orc_set_f", "orc_get_fstar", "orc_get_ufine", "orc_get_step_acc"):
+        for name in ("orc_get_f", "orc_set_f", "orc_get_fstar", "orc_get_ufine", "orc_get_step_acc",
+                     "orc_get_fb_u"):
             getattr(L, name).argtypes = [P, P]
         L.orc_get_moments.argtypes = [P, P, P, P]
         L.orc_get_shift.argtypes = [P, P]
@@ -123,6 +124,7 @@ def params_struct(p: dict) -> _Params:
     s.collision = int(p.get("collision", 0))
     s.reinject = int(p.get("reinject", 0))
     s.ce_nu = float(p.get("ce_nu", 0.0))
+    s.fb_window = int(p.get("fb_window", 0))
     return s
 
 
@@ -252,6 +254,13 @@ class Oracle:
         n = C.c_int64()
         self._L.orc_get_profile(self._h, _ptr(acc), C.byref(n))
         return acc, int(n.value)
+
+    def fb_u(self) -> np.ndarray:
+        """Running mean of the node samples that the feedback projects, [3][nz][yhi-ylo][nx]."""
+        nx, _, nz = self.p["n"]
+        out = np.empty((nz, self.p["yhi"] - self.p["ylo"], nx, 3), np.float64)
+        self._L.orc_get_fb_u(self._h, _ptr(out))
+        return np.moveaxis(out, -1, 0).copy()
 
     def step_acc(self) -> np.ndarray:
         nx, _, nz = self.p["n"]

@@ -24,6 +24,9 @@ _BASE = dict(
     # rate with stress coefficient ce_nu (0: the post-collision kinetic stress
     # of the collision rule)
     reinject=0, ce_nu=0.0,
+    # feedback: LB steps of the running mean of the node samples that is
+    # projected onto the LB equilibria (0 = the library default, 50)
+    fb_window=0,
     # launch configuration of the HIP path (tile shape in cells, tile slot
     # capacity over expected occupancy); 0 = library default
     tile=(0, 0, 0), capacity_factor=0.0, tile_target=0, wg_threads=0, closure=0,

@@ -315,11 +315,12 @@ def test_one_way_coupling_leaves_lb_untouched(oracle_lib):
 
 
 def test_feedback_sets_node_velocity_to_particle_mean(oracle_lib):
-    """Feedback reading: with cells equal to LB nodes (r = 1, no shift, S = 1)
-    a collision keeps each node's particle momentum, so after the next LB
-    step every interior node's velocity equals the mean velocity of its
-    particles at the end of the previous step."""
-    p = W.small_2d(refine=1, grid_shift=0, substeps=1, ppc=30, g=(0, 0, 0), feedback=1)
+    """Feedback reading with a window of one LB step: with cells equal to LB
+    nodes (r = 1, no shift, S = 1) a collision keeps each node's particle
+    momentum, so after the next LB step every interior node's velocity
+    equals the mean velocity of its particles at the end of the previous
+    step."""
+    p = W.small_2d(refine=1, grid_shift=0, substeps=1, ppc=30, g=(0, 0, 0), feedback=1, fb_window=1)
     o = oracle_lib.Oracle(p)
     o.step(2)
     pos, vel = o.particles()
@@ -337,6 +338,43 @@ def test_feedback_sets_node_velocity_to_particle_mean(oracle_lib):
             # step; with S = 1 and a cell-aligned grid the collision keeps the
             # node's momentum, so the post-collision particle mean equals it
             assert np.allclose(u[:2, 0, y, x], vel[:, sel].mean(1), atol=1e-13)
+
+
+@pytest.mark.parametrize("window,init_flow", [(4, 0), (7, 1)])
+def test_feedback_running_mean(oracle_lib, window, init_flow):
+    """Feedback reading with a window of W LB steps: after n LB steps an
+    interior node carries the weighted sum
+    (1 - 1/W)^(n-1) u0 + sum_k (1/W)(1 - 1/W)^(n-1-k) ubar_k over the sample
+    means ubar_k of LB steps k = 1 .. n-1 (the projection of LB step n uses
+    the samples of step n - 1; the first step has none), u0 the node's
+    initial velocity; the node's velocity equals it, and so does the running
+    mean the oracle reports."""
+    g = (1e-4, 0.0, 0.0) if init_flow else (0.0, 0.0, 0.0)
+    p = W.small_2d(refine=1, grid_shift=0, substeps=1, ppc=30, g=g, feedback=1, fb_window=window,
+                   init_flow=init_flow)
+    o = oracle_lib.Oracle(p)
+    lam = 1.0 / window
+    nx, ylo, yhi = p["n"][0], p["ylo"], p["yhi"]
+    rows = range(ylo + p["buf_lo"], yhi - p["buf_hi"])
+    means = []
+    n = 9
+    for _ in range(n):
+        o.step(1)
+        acc = o.step_acc()[0]  # [R][nx][4], r = 1: one fine row per node row
+        means.append(acc[:, :, 1:3] / acc[:, :, :1])
+    _, u, _ = o.moments()
+    fb = o.fb_u()
+    for y in rows:
+        J = y - ylo
+        yc = y + 0.5
+        H, nu, tau = p["n"][1], (p["tau"] - 0.5) / 3.0, p["tau"]
+        u0 = (g[0] * yc * (H - yc) / (2 * nu) + g[0] * (16 * tau * tau - 16 * tau + 1) / (24 * nu)) if init_flow else 0.0
+        exp = np.zeros((nx, 2))
+        exp[:, 0] = (1 - lam) ** (n - 1) * u0
+        for k in range(1, n):
+            exp += lam * (1 - lam) ** (n - 1 - k) * means[k - 1][J]
+        assert np.allclose(fb[:2, 0, J, :].T, exp, rtol=0, atol=1e-13)
+        assert np.allclose(u[:2, 0, y, :].T, exp, rtol=0, atol=1e-13)
 
 
 def test_profile_counts(oracle_lib):
