@@ -14,7 +14,8 @@
  * the buffer particles are redrawn from the Maxwell-Boltzmann distribution
  * about it (Box-Muller), or (reinject = 1) from the first-order
  * Chapman-Enskog distribution that the end of Sec. 2.3 names for strong
- * gradients; optionally the MPCD averages are projected back onto LB
+ * gradients; optionally (feedback 1, not in the paper, which couples one
+ * way) a running time average of the MPCD velocity is projected back onto LB
  * equilibria in the slab interior.
  *
  * Conventions (lattice units, dx = dt_LB = 1):
@@ -38,7 +39,13 @@
  * Errors: every int-returning call returns 0 (LBMPCD_OK) or a positive code
  * below; no exception or abort crosses the ABI.  lbmpcd_last_error gives a
  * message.  Device-side overflow or state corruption is latched and reported
- * by the next synchronising call (lbmpcd_sync, moments, get_state).
+ * by the next synchronising call (lbmpcd_sync, moments, get_state):
+ * E_OVERFLOW when a tile overflowed; E_STATE when a particle moved more than
+ * one period in one MPCD step or its position or velocity became non-finite
+ * (it is parked at the slab's lower corner at rest, so every index the
+ * kernels derive stays in range), when a node of the rows next to the slab
+ * had rho <= 0 or non-finite moments, or when particles were found outside
+ * their tile.  After a latched error lbmpcd_step returns it and does nothing.
  * A context is not thread-safe; use one context per stream.
  */
 #ifndef LBMPCD_H
@@ -51,7 +58,7 @@
 extern "C" {
 #endif
 
-#define LBMPCD_ABI_VERSION 4u
+#define LBMPCD_ABI_VERSION 5u
 
 enum lbmpcd_status {
     LBMPCD_OK = 0,
@@ -78,11 +85,12 @@ enum lbmpcd_field {
                               state is not changed)                               */
     LBMPCD_PROFILE = 9,    /* double[R][4]: per fine row sum n, sum v_x, v_y, v_z  */
     LBMPCD_UFINE = 10,     /* double[dim][nz*r][R][nx*r]: buffer-cell LB velocity  */
-    LBMPCD_STATS = 11,     /* int64[9]: lb steps, sampled steps, dropped particles,
+    LBMPCD_STATS = 11,     /* int64[10]: lb steps, sampled steps, dropped particles,
                               misplaced particles, far moves, max tile fill,
                               particles, cells, samples that missed their tile's LDS
                               window and went to global atomics (a slow path: 0
-                              for the default tiles at refinement >= 2)            */
+                              for the default tiles at refinement >= 2), invalid
+                              particles and band nodes (see Errors above)          */
     LBMPCD_PART_VEL_PENDING = 12, /* double[dim][Np] by id: velocities before the
                               collision of the last MPCD step (get only)          */
     LBMPCD_CELL_START = 13, /* int32[ncells]: where each cell of the last binning
@@ -91,13 +99,19 @@ enum lbmpcd_field {
                               keeps particles grouped by tile, not in that order) */
     LBMPCD_NODE_MPCD_U = 14, /* double[dim][nx*(yhi-ylo)*nz]: mean velocity of the
                               particles sampled in each slab node (x fastest, then
-                              y - ylo, then z) in the last LB step, the average
-                              the feedback projects; needs feedback 1 (E_STATE
-                              otherwise); 0 where no particle was sampled          */
-    LBMPCD_TFINE = 15      /* double[6][nz*r][R][nx*r]: the Chapman-Enskog tensor T of
+                              y - ylo, then z) in the last LB step, the sample the
+                              feedback's running mean takes in next; needs
+                              feedback 1 (E_STATE otherwise); 0 where no particle
+                              was sampled                                          */
+    LBMPCD_TFINE = 15,     /* double[6][nz*r][R][nx*r]: the Chapman-Enskog tensor T of
                               each buffer cell (xx yy zz xy xz yz; zero outside the
                               buffers) of the last exchange step; needs reinject 1
                               (E_STATE otherwise)                                  */
+    LBMPCD_NODE_FB_U = 16  /* double[dim][nx*(yhi-ylo)*nz]: the running mean of the
+                              MPCD velocity per slab node (layout of NODE_MPCD_U)
+                              that the feedback projects; interior nodes only (the
+                              buffer nodes keep their initial velocity); needs
+                              feedback 1 (E_STATE otherwise)                       */
 };
 
 typedef struct lbmpcd_params {
@@ -124,7 +138,9 @@ typedef struct lbmpcd_params {
                               component) less the cell mean of those; all instances of a
                               context share it */
     int32_t grid_shift;    /* 1: random grid shift every MPCD step */
-    int32_t feedback;      /* 1: project MPCD averages onto LB equilibria */
+    int32_t feedback;      /* 1: project a running time average of the MPCD velocity
+                              onto the LB equilibria of the slab's interior nodes
+                              (not the buffers); 0: the paper's one-way coupling */
     int32_t init_flow;     /* 0: rest, 1: discrete Poiseuille profile (needs walls) */
     uint64_t seed;         /* Philox key (low, high ^ instance) */
     uint32_t instance;     /* instance number inside the key */
@@ -155,6 +171,17 @@ typedef struct lbmpcd_params {
                               kT dt/m (N/(N-1+e^-N) - 1); SRD: kT dt/m [N/((N-1+e^-N)
                               (1-cos 2a)) - 1/2] in 2D, kT dt/m [5N/((N-1+e^-N)(4-2cos a
                               -2cos 2a)) - 1/2] in 3D, negative at large angles) */
+    int32_t fb_window;     /* feedback: W in LB steps.  Every LB step the running mean of
+                              an interior slab node moves towards the mean velocity of
+                              the particles sampled in the node in the previous LB step
+                              by the weight 1/W (e <- (1 - 1/W) e + (1/W) u_sample); it
+                              starts at the node's initial velocity, and the node's
+                              post-stream populations become the equilibrium at the LB
+                              density and that velocity.  0: W = 50.  1: the last sample
+                              alone, which drives the LB unstable: a node of r^d cells
+                              holds a few hundred particles, whose mean carries thermal
+                              noise of the size of the flow (the paper averages its
+                              MPCD profiles over many samples, Sec. 3.1). */
 } lbmpcd_params;
 
 /*

@@ -39,6 +39,7 @@ struct lbmpcd_ctx {
     double* tb = nullptr;         // [6][band nodes] Chapman-Enskog tensor (reinject 1)
     double* tf = nullptr;         // [6][buffer cells] the same, interpolated
     double* acc = nullptr;
+    double* fbu = nullptr;      // [3][total_slab] running means the feedback projects
     double* prof = nullptr;
     double* shifts = nullptr;   // [n_inst][2][S][3] grid shifts drawn by the LB kernel
     DevStats* stats = nullptr;
@@ -232,6 +233,7 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     if (!(p.mass > 0.0) || p.kT < 0.0) { msg = "mass must be positive, kT non-negative"; return LBMPCD_E_INVALID; }
     if (p.reinject != 0 && p.reinject != 1) { msg = "reinject must be 0 or 1"; return LBMPCD_E_INVALID; }
     if (!std::isfinite(p.ce_nu)) { msg = "ce_nu must be finite"; return LBMPCD_E_INVALID; }
+    if (p.fb_window < 0) { msg = "fb_window must be >= 0"; return LBMPCD_E_INVALID; }
     if (p.reinject && !(p.kT > 0.0)) { msg = "the Chapman-Enskog exchange needs kT > 0"; return LBMPCD_E_INVALID; }
     const bool ywrap = !p.walls_y && p.ylo == 0 && p.yhi == p.n[1] && p.buf_lo == 0 && p.buf_hi == 0;
     if (!p.walls_y && !ywrap && (p.ylo < 1 || p.yhi > p.n[1] - 1)) {
@@ -268,8 +270,11 @@ double ce_nu(const lbmpcd_params& p) {
     return nu_kinetic(p) - 0.5 * p.kT / p.substeps / p.mass;
 }
 
+// LB steps of the feedback's running mean when fb_window is 0
+constexpr int FB_WINDOW_DEFAULT = 50;
+
 struct Layout {
-    size_t desc, tile_inst, f0, f1, ub, uf, tb, tf, acc, prof, fill0, fill1, stats, clock, shifts, scratch, end;
+    size_t desc, tile_inst, f0, f1, ub, uf, tb, tf, acc, fbu, prof, fill0, fill1, stats, clock, shifts, scratch, end;
     size_t cl_P, cl_Pb, cl_Pf, cl_G, cl_m, cl_v, cl_stats, cl_sums, cl_loss, cl_facc, cl_nm, cl_uc, cl_inf;
     size_t part[2];       // particle buffer: 2 dim component arrays of cstride bytes, then ids
     size_t cstride;
@@ -319,6 +324,7 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
         d.S = q.mpcd ? q.substeps : 0;
         d.ce = (q.mpcd && q.reinject) ? 1 : 0;
         d.ce_scale = d.ce ? ce_nu(q) * q.mass / q.kT / (2.0 * q.tau / 3.0) : 0.0;
+        d.fb_lam = 1.0 / (double)(q.fb_window > 0 ? q.fb_window : FB_WINDOW_DEFAULT);
         node += d.N;
         band += g.nband;
         ufine += g.nufine;
@@ -349,6 +355,7 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
     L.tf = take(ce ? (size_t)CE_NT * ufine * 8 : 0);
     L.acc_bytes = 4 * (size_t)slab * 8;
     L.acc = take(L.acc_bytes);
+    L.fbu = take(3 * (size_t)slab * 8);
     L.prof_bytes = 4 * (size_t)prow * 8;
     L.prof = take(L.prof_bytes);
     L.fill0 = take(4 * (size_t)tiles);
@@ -466,6 +473,11 @@ int check_device_errors(lbmpcd_ctx* c) {
     if (s.dropped) {
         c->sticky = LBMPCD_E_OVERFLOW;
         c->err = std::to_string(s.dropped) + " particles dropped by tile overflow (raise capacity_factor)";
+    } else if (s.bad_state) {
+        c->sticky = LBMPCD_E_STATE;
+        c->err = std::to_string(s.bad_state) +
+                 " invalid particles or band nodes (a particle moved more than a period in one MPCD step or "
+                 "turned non-finite, or a node next to the slab had rho <= 0 or non-finite moments)";
     } else if (s.misplaced) {
         c->sticky = LBMPCD_E_STATE;
         c->err = std::to_string(s.misplaced) + " particles found outside their tile";
@@ -568,6 +580,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
         c->ce_bit = 8;
     }
     c->acc = (double*)(c->ws + L.acc);
+    c->fbu = (double*)(c->ws + L.fbu);
     c->prof = (double*)(c->ws + L.prof);
     c->acc_bytes = L.acc_bytes;
     c->prof_bytes = L.prof_bytes;
@@ -642,7 +655,9 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
         rc = rc ? rc : chk(launch_zero(c->tb, (size_t)CE_NT * 8 * c->total_band, s), "tb");
         rc = rc ? rc : chk(launch_zero(c->tf, (size_t)CE_NT * 8 * c->total_ufine, s), "tf");
     }
-    rc = rc ? rc : chk(launch_lb_init(c->dim, c->lb_fp, c->d_desc, n_inst, c->total_nodes, c->f[0], s), "lb init");
+    rc = rc ? rc : chk(launch_zero(c->fbu, 3 * 8 * (size_t)c->total_slab, s), "fbu");
+    rc = rc ? rc : chk(launch_lb_init(c->dim, c->lb_fp, c->d_desc, n_inst, c->total_nodes, c->f[0],
+                                      c->mpcd ? c->fbu : nullptr, c->total_slab, s), "lb init");
     if (c->mpcd) {
         rc = rc ? rc : chk(launch_fill_sequential(c->d_desc, n_inst, c->total_tiles, c->fill[0], c->fill[1], s), "fill");
         rc = rc ? rc : chk(launch_part_init(c->dim, c->part_fp, c->d_desc, n_inst, c->total_particles, c->part[0], s), "particles");
@@ -689,7 +704,8 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
             if (c->any_feedback)
                 HIPCHK(c, timed(c, 1, [&] {
                            return launch_band(c->dim, c->lb_fp, c->d_desc, c->n_inst, c->total_band,
-                                              c->f[c->fcur], c->acc, c->ub, nullptr, 1, s);
+                                              c->f[c->fcur], c->acc, c->fbu, c->total_slab, c->ub, nullptr,
+                                              c->stats, 1, s);
                        }));
             return 0;
         }
@@ -699,7 +715,8 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
         if (c->mpcd) {
             HIPCHK(c, timed(c, 1, [&] {
                        return launch_band(c->dim, c->lb_fp, c->d_desc, c->n_inst, c->total_band, c->f[c->fcur],
-                                          c->acc, c->ub, c->tb, c->any_feedback ? 1 : 0, s);
+                                          c->acc, c->fbu, c->total_slab, c->ub, c->tb, c->stats,
+                                          c->any_feedback ? 1 : 0, s);
                    }));
             HIPCHK(c, timed(c, 2, [&] {
                        return launch_interp(c->dim, c->d_desc, c->n_inst, c->total_ufine, c->ub, c->uf, c->tb,
@@ -815,9 +832,10 @@ int lbmpcd_field_bytes(const lbmpcd_ctx* c, int32_t field, int32_t inst, size_t*
         case LBMPCD_PROFILE: *bytes = (size_t)d.R * 4 * 8; break;
         case LBMPCD_UFINE: *bytes = (size_t)c->dim * d.Cx * d.R * d.Cz * 8; break;
         case LBMPCD_TFINE: *bytes = (size_t)CE_NT * d.Cx * d.R * d.Cz * 8; break;
-        case LBMPCD_STATS: *bytes = 9 * 8; break;
+        case LBMPCD_STATS: *bytes = 10 * 8; break;
         case LBMPCD_CELL_START: *bytes = (size_t)d.ncells * 4; break;
-        case LBMPCD_NODE_MPCD_U: *bytes = (size_t)c->dim * d.nslab * 8; break;
+        case LBMPCD_NODE_MPCD_U:
+        case LBMPCD_NODE_FB_U: *bytes = (size_t)c->dim * d.nslab * 8; break;
         default: return LBMPCD_E_INVALID;
     }
     return 0;
@@ -878,6 +896,12 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             if (!d.feedback) return fail(c, LBMPCD_E_STATE, "node sample averages are kept only with feedback 1");
             HIPCHK(c, launch_node_mean(c->acc + d.acc_off * 4, d.nslab, c->dim, (double*)dst, s));
             return 0;
+        case LBMPCD_NODE_FB_U:
+            if (!d.feedback) return fail(c, LBMPCD_E_STATE, "the feedback's running mean exists only with feedback 1");
+            for (int k = 0; k < c->dim; ++k)
+                HIPCHK(c, hipMemcpyAsync((double*)dst + (size_t)k * d.nslab, c->fbu + (size_t)k * c->total_slab + d.acc_off,
+                                         (size_t)d.nslab * 8, hipMemcpyDeviceToDevice, s));
+            return 0;
         case LBMPCD_CELL_VCM: {
             if (!c->pending) return fail(c, LBMPCD_E_STATE, "cell velocities exist only right after lbmpcd_step");
             HIPCHK(c, launch_zero(dst, nbytes, s));
@@ -934,8 +958,9 @@ int lbmpcd_moments(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t
         DevStats s;
         HIPCHK(c, hipMemcpyAsync(&s, c->stats, sizeof(s), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        int64_t v[9] = {c->t, c->sampled_steps, (int64_t)s.dropped, (int64_t)s.misplaced, (int64_t)s.far_moves,
-                        (int64_t)s.max_fill, c->desc[inst].Np, c->desc[inst].ncells, (int64_t)s.window_misses};
+        int64_t v[10] = {c->t, c->sampled_steps, (int64_t)s.dropped, (int64_t)s.misplaced, (int64_t)s.far_moves,
+                         (int64_t)s.max_fill, c->desc[inst].Np, c->desc[inst].ncells, (int64_t)s.window_misses,
+                         (int64_t)s.bad_state};
         if (on_dev) HIPCHK(c, hipMemcpy(dst, v, sizeof(v), hipMemcpyHostToDevice));
         else std::memcpy(dst, v, sizeof(v));
         return 0;

@@ -66,6 +66,7 @@ struct InstDesc {
     // Chapman-Enskog exchange: T = ce_scale dev(-Pi_neq) / rho at the band nodes
     int ce, pad3;         // 1: Chapman-Enskog draws in this instance's buffers
     double ce_scale;      // nu_x m / kT / (2 cs2 tau), nu_x the exchange's stress coefficient
+    double fb_lam;        // feedback: weight of an LB step's node sample in the running mean (1/fb_window)
 };
 
 // Components of the Chapman-Enskog tensor per band node / buffer cell
@@ -199,6 +200,8 @@ struct DevStats {
     unsigned int max_fill;          // largest tile occupancy seen
     unsigned int pad;
     unsigned long long window_misses;  // samples outside their tile's LDS window (global atomics)
+    unsigned long long bad_state;   // particles that left the domain by more than a period or
+                                    // turned non-finite, band nodes with rho <= 0 or non-finite moments
 };
 
 // Particle arrays of one buffer: positions, velocities, ids (slot-indexed).
@@ -219,6 +222,18 @@ __device__ __forceinline__ int bin_coord(PT x, PT lo, PT sh, PT r) {
     t = t + sh;
     t = t * r;
     return (int)floor(t);
+}
+
+// Row of the shifted grid of a slab position, periodic across the slab when
+// the slab is the whole periodic box.  A binary32 sum y - ylo + shift can
+// round up to the slab height plus a full cell at the top face; such a
+// particle belongs to the grid's last row.
+template <typename PT, typename Desc>
+__device__ __forceinline__ int bin_row(const Desc& d, PT y, PT sh, PT r) {
+    int iy = bin_coord<PT>(y, (PT)d.ylo, sh, r);
+    if (d.ywrap && iy >= d.R) iy -= d.R;
+    if (iy > d.CyB - 1) iy = d.CyB - 1;
+    return iy;
 }
 
 // Random grid shift of MPCD step (t, sub): uniform in [0, a) per axis.

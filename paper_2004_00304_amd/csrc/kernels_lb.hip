@@ -7,11 +7,14 @@
 // opposite direction of the same node where the link crosses a wall
 // (half-way bounce-back).  HBM-bound: one read and one write of Q values.
 //
-// k_band: per node of the rows the coupling needs; projects the sampled MPCD
-// velocity onto the equilibrium at interior slab nodes (feedback), clears the
-// sample sums, and stores the node velocity for the interpolation; with the
-// Chapman-Enskog exchange also the node's tensor T = (nu_x m/kT) dev S,
-// S the BGK strain rate from the non-equilibrium second moment.
+// k_band: per node of the rows the coupling needs; at interior slab nodes
+// (feedback) moves the node's running mean of the MPCD velocity towards the
+// last LB step's sample mean and projects the populations onto the
+// equilibrium at that mean, clears the sample sums, and stores the node
+// velocity for the interpolation; with the Chapman-Enskog exchange also the
+// node's tensor T = (nu_x m/kT) dev S, S the BGK strain rate from the
+// non-equilibrium second moment.  A band node with rho <= 0 or non-finite
+// moments is counted as an invalid state.
 //
 // k_interp: per buffer fine cell, bi/trilinear interpolation of the node
 // velocity (and T) to the cell centre (Alg. 2).
@@ -121,11 +124,14 @@ __global__ void __launch_bounds__(WG) k_lb_step(const InstDesc* __restrict__ D, 
 }
 
 // Feedback projection, sample reset and node velocity of the band rows.
+// fbu[k * fb_stride + slab node] holds the running mean of the MPCD velocity
+// that the feedback projects.
 template <int DIM, typename LT>
 __global__ void __launch_bounds__(WG) k_band(const InstDesc* __restrict__ D, int n_inst, long long total,
                                              LT* __restrict__ f, double* __restrict__ acc,
+                                             double* __restrict__ fbu, long long fb_stride,
                                              double* __restrict__ ub, double* __restrict__ tb,
-                                             int do_feedback) {
+                                             DevStats* __restrict__ stats, int do_feedback) {
     using L = Lat<DIM>;
     constexpr int Q = L::Q;
     long long gid = (long long)blockIdx.x * WG + threadIdx.x;
@@ -149,13 +155,23 @@ __global__ void __launch_bounds__(WG) k_band(const InstDesc* __restrict__ D, int
         double* a = acc + (d.acc_off + s) * 4;
         double cnt = a[0], s0 = a[1], s1 = a[2], s2 = a[3];
         a[0] = 0.0; a[1] = 0.0; a[2] = 0.0; a[3] = 0.0;
-        if (y >= d.ylo + d.buf_lo && y < d.yhi - d.buf_hi && cnt > 0.0) {
+        if (d.feedback && y >= d.ylo + d.buf_lo && y < d.yhi - d.buf_hi && cnt > 0.0) {
             double rho = 0.0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) rho += fl[i];
-            double u0 = s0 / cnt - 0.5 * d.g[0];
-            double u1 = s1 / cnt - 0.5 * d.g[1];
-            double u2 = (DIM == 3 ? s2 / cnt : 0.0) - 0.5 * d.g[2];
+            // running mean over LB steps of the node's sample means (weight
+            // fb_lam per step; fb_lam = 1 projects the last sample alone)
+            double* e = fbu + d.acc_off + s;
+            const double lam = d.fb_lam;
+            const double e0 = (1.0 - lam) * e[0] + lam * (s0 / cnt);
+            const double e1 = (1.0 - lam) * e[fb_stride] + lam * (s1 / cnt);
+            const double e2 = (1.0 - lam) * e[2 * fb_stride] + lam * (DIM == 3 ? s2 / cnt : 0.0);
+            e[0] = e0;
+            e[fb_stride] = e1;
+            e[2 * fb_stride] = e2;
+            double u0 = e0 - 0.5 * d.g[0];
+            double u1 = e1 - 0.5 * d.g[1];
+            double u2 = e2 - 0.5 * d.g[2];
             feq_of<DIM>(rho, u0, u1, u2, fl);
 #pragma unroll
             for (int i = 0; i < Q; ++i) fp[i * N + n] = (LT)fl[i];
@@ -177,6 +193,8 @@ __global__ void __launch_bounds__(WG) k_band(const InstDesc* __restrict__ D, int
     const double ux = j0 / rho + 0.5 * d.g[0];
     const double uy = j1 / rho + 0.5 * d.g[1];
     const double uz = j2 / rho + 0.5 * d.g[2];
+    if (!(rho > 0.0 && isfinite(rho) && isfinite(ux) && isfinite(uy) && isfinite(uz)))
+        atomicAdd(&stats->bad_state, 1ull);
     u[b] = ux;
     u[NBd + b] = uy;
     u[2 * NBd + b] = uz;
@@ -315,7 +333,7 @@ __device__ __forceinline__ double poiseuille(const InstDesc& d, double gk, doubl
 
 template <int DIM, typename LT>
 __global__ void __launch_bounds__(WG) k_lb_init(const InstDesc* __restrict__ D, int n_inst, long long total,
-                                                LT* __restrict__ f) {
+                                                LT* __restrict__ f, double* __restrict__ fbu, long long fb_stride) {
     using L = Lat<DIM>;
     long long gid = (long long)blockIdx.x * WG + threadIdx.x;
     if (gid >= total) return;
@@ -333,6 +351,13 @@ __global__ void __launch_bounds__(WG) k_lb_init(const InstDesc* __restrict__ D, 
     LT* fp = f + d.node_off * L::Q;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) fp[i * d.N + n] = (LT)feq[i];
+    // the feedback's running mean starts at the node's initial velocity
+    if (fbu != nullptr && d.mpcd && y >= d.ylo && y < d.yhi) {
+        const int x = (int)(n % d.nx), z = (int)(n / ((long long)d.nx * d.ny));
+        const long long sn = d.acc_off + ((long long)z * (d.yhi - d.ylo) + (y - d.ylo)) * d.nx + x;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fbu[k * fb_stride + sn] = u[k] + 0.5 * d.g[k];
+    }
 }
 
 // Moments of the post-stream populations of one instance: rho, physical u,
@@ -402,17 +427,22 @@ hipError_t launch_lb_step(int dim, int lb_fp, const InstDesc* D, int n_inst, lon
 }
 
 hipError_t launch_band(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f, double* acc,
-                       double* ub, double* tb, int do_feedback, hipStream_t s) {
+                       double* fbu, long long fb_stride, double* ub, double* tb, DevStats* stats, int do_feedback,
+                       hipStream_t s) {
     if (total <= 0) return hipSuccess;
     dim3 g(blocks_for(total)), b(WG);
     if (dim == 2 && lb_fp == 64)
-        hipLaunchKernelGGL((k_band<2, double>), g, b, 0, s, D, n_inst, total, (double*)f, acc, ub, tb, do_feedback);
+        hipLaunchKernelGGL((k_band<2, double>), g, b, 0, s, D, n_inst, total, (double*)f, acc, fbu, fb_stride, ub, tb,
+                           stats, do_feedback);
     else if (dim == 2)
-        hipLaunchKernelGGL((k_band<2, float>), g, b, 0, s, D, n_inst, total, (float*)f, acc, ub, tb, do_feedback);
+        hipLaunchKernelGGL((k_band<2, float>), g, b, 0, s, D, n_inst, total, (float*)f, acc, fbu, fb_stride, ub, tb,
+                           stats, do_feedback);
     else if (lb_fp == 64)
-        hipLaunchKernelGGL((k_band<3, double>), g, b, 0, s, D, n_inst, total, (double*)f, acc, ub, tb, do_feedback);
+        hipLaunchKernelGGL((k_band<3, double>), g, b, 0, s, D, n_inst, total, (double*)f, acc, fbu, fb_stride, ub, tb,
+                           stats, do_feedback);
     else
-        hipLaunchKernelGGL((k_band<3, float>), g, b, 0, s, D, n_inst, total, (float*)f, acc, ub, tb, do_feedback);
+        hipLaunchKernelGGL((k_band<3, float>), g, b, 0, s, D, n_inst, total, (float*)f, acc, fbu, fb_stride, ub, tb,
+                           stats, do_feedback);
     return hipGetLastError();
 }
 
@@ -428,17 +458,17 @@ hipError_t launch_interp(int dim, const InstDesc* D, int n_inst, long long total
 }
 
 hipError_t launch_lb_init(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f,
-                          hipStream_t s) {
+                          double* fbu, long long fb_stride, hipStream_t s) {
     if (total <= 0) return hipSuccess;
     dim3 g(blocks_for(total)), b(WG);
     if (dim == 2 && lb_fp == 64)
-        hipLaunchKernelGGL((k_lb_init<2, double>), g, b, 0, s, D, n_inst, total, (double*)f);
+        hipLaunchKernelGGL((k_lb_init<2, double>), g, b, 0, s, D, n_inst, total, (double*)f, fbu, fb_stride);
     else if (dim == 2)
-        hipLaunchKernelGGL((k_lb_init<2, float>), g, b, 0, s, D, n_inst, total, (float*)f);
+        hipLaunchKernelGGL((k_lb_init<2, float>), g, b, 0, s, D, n_inst, total, (float*)f, fbu, fb_stride);
     else if (lb_fp == 64)
-        hipLaunchKernelGGL((k_lb_init<3, double>), g, b, 0, s, D, n_inst, total, (double*)f);
+        hipLaunchKernelGGL((k_lb_init<3, double>), g, b, 0, s, D, n_inst, total, (double*)f, fbu, fb_stride);
     else
-        hipLaunchKernelGGL((k_lb_init<3, float>), g, b, 0, s, D, n_inst, total, (float*)f);
+        hipLaunchKernelGGL((k_lb_init<3, float>), g, b, 0, s, D, n_inst, total, (float*)f, fbu, fb_stride);
     return hipGetLastError();
 }
 

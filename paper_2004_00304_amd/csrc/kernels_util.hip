@@ -97,8 +97,7 @@ __global__ void __launch_bounds__(WG) k_gather(const InstDesc* __restrict__ D, i
         const PT rr = (PT)d.r;
         int ix = bin_coord<PT>(P.pos[0][g], (PT)0, sh[0], rr);
         if (ix >= d.Cx) ix -= d.Cx;
-        int iy = bin_coord<PT>(P.pos[1][g], (PT)d.ylo, sh[1], rr);
-        if (d.ywrap && iy >= d.R) iy -= d.R;
+        const int iy = bin_row<PT>(d, P.pos[1][g], sh[1], rr);
         int iz = 0;
         if (DIM == 3) {
             iz = bin_coord<PT>(P.pos[2][g], (PT)0, sh[2], rr);
@@ -126,8 +125,7 @@ __global__ void __launch_bounds__(WG) k_cell_count(const InstDesc* __restrict__ 
     const PT rr = (PT)d.r;
     int ix = bin_coord<PT>(P.pos[0][g], (PT)0, sh[0], rr);
     if (ix >= d.Cx) ix -= d.Cx;
-    int iy = bin_coord<PT>(P.pos[1][g], (PT)d.ylo, sh[1], rr);
-    if (d.ywrap && iy >= d.R) iy -= d.R;
+    const int iy = bin_row<PT>(d, P.pos[1][g], sh[1], rr);
     int iz = 0;
     if (DIM == 3) {
         iz = bin_coord<PT>(P.pos[2][g], (PT)0, sh[2], rr);

@@ -12,13 +12,16 @@ namespace lbmpcd {
 hipError_t launch_lb_step(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, const void* fin,
                           void* fout, long long* clock, double* shifts, int S, hipStream_t s);
 // With tb (tf) non-null the band kernel (interpolation) also writes the
-// Chapman-Enskog tensor of the instances that use that exchange.
+// Chapman-Enskog tensor of the instances that use that exchange.  fbu holds
+// the feedback's running means, [3][fb_stride] over the slab nodes of all
+// instances.
 hipError_t launch_band(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f, double* acc,
-                       double* ub, double* tb, int do_feedback, hipStream_t s);
+                       double* fbu, long long fb_stride, double* ub, double* tb, DevStats* stats, int do_feedback,
+                       hipStream_t s);
 hipError_t launch_interp(int dim, const InstDesc* D, int n_inst, long long total, const double* ub, double* uf,
                          const double* tb, double* tf, hipStream_t s);
 hipError_t launch_lb_init(int dim, int lb_fp, const InstDesc* D, int n_inst, long long total, void* f,
-                          hipStream_t s);
+                          double* fbu, long long fb_stride, hipStream_t s);
 hipError_t launch_moments(int dim, int lb_fp, const InstDesc* D, int inst, long long N, const void* f,
                           double* rho, double* u, double* pi, hipStream_t s);
 

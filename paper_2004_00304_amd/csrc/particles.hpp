@@ -211,7 +211,8 @@ k_particles(PArgs<PT> A) {
     constexpr bool AT = (MODE & 4) != 0;  // MPCD-AT collision (Eq. 6) instead of SRD (Eq. 4)
     constexpr bool CE = (MODE & 8) != 0;  // Chapman-Enskog exchange instead of Maxwell-Boltzmann
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t* wstat = (uint32_t*)smem;          // [4] far moves, misplaced, samples outside the LDS windows
+    uint32_t* wstat = (uint32_t*)smem;          // [4] far moves, misplaced, samples outside the LDS windows,
+                                                // invalid particles
     uint32_t* hkey = wstat + 4;                 // [NHASH] destination tiles (local index)
     uint32_t* hcnt = hkey + NHASH;              // [NHASH + 1] particles per destination
     uint32_t* gbase = hcnt + NHASH + 1;         // [NHASH + 1] reserved run start
@@ -326,8 +327,7 @@ k_particles(PArgs<PT> A) {
             if (!valid[k]) continue;
             int ix = bin_coord<PT>(px[k][0], (PT)0, sh[0], rr);
             if (ix >= d.Cx) ix -= d.Cx;
-            int iy = bin_coord<PT>(px[k][1], (PT)d.ylo, sh[1], rr);
-            if (d.ywrap && iy >= d.R) iy -= d.R;
+            const int iy = bin_row<PT>(d, px[k][1], sh[1], rr);
             int iz = 0;
             if constexpr (DIM == 3) {
                 iz = bin_coord<PT>(px[k][2], (PT)0, sh[2], rr);
@@ -361,6 +361,9 @@ k_particles(PArgs<PT> A) {
             const uint32_t nc = ccnt[j];
             if (nc == 0u || ix >= d.Cx || iy >= d.CyB || iz >= d.Cz) continue;
             const uint32_t cg = (uint32_t)(ix + d.Cx * (iy + d.CyB * iz));
+            // wall-cut cell below its nominal occupancy: nv virtual particles
+            // with Maxwell-Boltzmann velocities (variance kT/m each), whose
+            // velocity sum, of variance nv kT/m, enters the centre of mass
             double pvv[3] = {0.0, 0.0, 0.0}, mv = 0.0;
             const bool cut = ((double)sh[1] > 0.0) && ((d.bot_wall && iy == 0) || (d.top_wall && iy == d.R));
             if (cut && (int)nc < d.ppc) {
@@ -369,7 +372,7 @@ k_particles(PArgs<PT> A) {
                 const int nv = d.ppc - (int)nc;
                 const double sdv = sqrt((double)nv * d.kT / d.mass);
 #pragma unroll
-                for (int q = 0; q < DIM; ++q) pvv[q] = sdv * z[q] / d.mass;
+                for (int q = 0; q < DIM; ++q) pvv[q] = sdv * z[q];
                 mv = (double)nv;
             }
 #pragma unroll
@@ -549,6 +552,25 @@ k_particles(PArgs<PT> A) {
             }
             r1[0] = wrap_periodic<PT>(r1[0], (PT)0, nxp);
             if constexpr (DIM == 3) r1[2] = wrap_periodic<PT>(r1[2], (PT)0, nzp);
+            // A particle that left the domain by more than one period in this
+            // step, or whose position or velocity is not finite, is an invalid
+            // state (a diverged LB field hands out such velocities): it is
+            // parked at the slab's lower corner at rest, so that every cell,
+            // tile and slot index below stays in range, and counted (the next
+            // synchronising call reports E_STATE).
+            bool bad = !(r1[0] >= (PT)0 && r1[0] < nxp);
+            if constexpr (DIM == 3) bad |= !(r1[2] >= (PT)0 && r1[2] < nzp);
+            bad |= ywrap ? !(r1[1] >= (PT)0 && r1[1] < nyp) : !(r1[1] >= ylo_p && r1[1] < yhi_p);
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) bad |= !isfinite(v1[q]);
+            if (bad) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) v1[q] = (PT)0;
+                r1[0] = (PT)0;
+                r1[1] = ywrap ? (PT)0 : ylo_p;
+                r1[2] = (PT)0;
+                atomicAdd(&wstat[3], 1u);
+            }
 #pragma unroll
             for (int q = 0; q < 3; ++q) { px[k][q] = r1[q]; pv[k][q] = v1[q]; }
         }
@@ -603,8 +625,7 @@ k_particles(PArgs<PT> A) {
             if (!valid[k]) continue;
             int ix = bin_coord<PT>(px[k][0], (PT)0, sh[0], rr);
             if (ix >= d.Cx) ix -= d.Cx;
-            int iy = bin_coord<PT>(px[k][1], (PT)d.ylo, sh[1], rr);
-            if (d.ywrap && iy >= d.R) iy -= d.R;
+            const int iy = bin_row<PT>(d, px[k][1], sh[1], rr);
             int iz = 0;
             if constexpr (DIM == 3) {
                 iz = bin_coord<PT>(px[k][2], (PT)0, sh[2], rr);
@@ -612,6 +633,12 @@ k_particles(PArgs<PT> A) {
             }
             const int ntx = ix >> d.lTx, nty = iy >> d.lTy, ntz = iz >> d.lTz;
             dest[k] = (uint32_t)(ntx + d.ntx * (nty + d.nty * ntz));
+            if (dest[k] >= (uint32_t)d.ntiles) {
+                // unreachable for positions inside the domain (checked above);
+                // kept so that no slot index can leave the channel's tiles
+                dest[k] = lt;
+                atomicAdd(&wstat[3], 1u);
+            }
             int dx = ntx - tx, dy = nty - ty, dz = ntz - tz;
             if (d.ntx > 2) { if (dx == d.ntx - 1) dx = -1; else if (dx == 1 - d.ntx) dx = 1; }
             if (DIM == 3 && d.ntz > 2) { if (dz == d.ntz - 1) dz = -1; else if (dz == 1 - d.ntz) dz = 1; }
@@ -751,6 +778,7 @@ k_particles(PArgs<PT> A) {
             if (wstat[0]) atomicAdd(&A.stats->far_moves, (unsigned long long)wstat[0]);
             if (wstat[1]) atomicAdd(&A.stats->misplaced, (unsigned long long)wstat[1]);
             if (wstat[2]) atomicAdd(&A.stats->window_misses, (unsigned long long)wstat[2]);
+            if (wstat[3]) atomicAdd(&A.stats->bad_state, (unsigned long long)wstat[3]);
         }
     }
 }

@@ -19,14 +19,14 @@ import torch  # noqa: F401
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmpcd.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 RHO, U, PI, POP, PART_POS, PART_VEL, CELL_ID, CELL_COUNT, CELL_VCM, PROFILE, UFINE, STATS, \
-    PART_VEL_PENDING, CELL_START, NODE_MPCD_U, TFINE = range(16)
+    PART_VEL_PENDING, CELL_START, NODE_MPCD_U, TFINE, NODE_FB_U = range(17)
 FIELD_NAMES = dict(rho=RHO, u=U, pi=PI, pop=POP, pos=PART_POS, vel=PART_VEL, cell_id=CELL_ID,
                    cell_count=CELL_COUNT, cell_vcm=CELL_VCM, profile=PROFILE, ufine=UFINE, stats=STATS,
                    vel_pending=PART_VEL_PENDING, cell_start=CELL_START, node_mpcd_u=NODE_MPCD_U,
-                   tfine=TFINE)
+                   tfine=TFINE, node_fb_u=NODE_FB_U)
 ERRORS = {1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_OVERFLOW", 5: "E_STATE", 6: "E_UNSUPPORTED"}
 
 
@@ -49,7 +49,7 @@ class Params(C.Structure):
         ("init_flow", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint32),
         ("tile", C.c_int32 * 3), ("capacity_factor", C.c_double),
         ("tile_target", C.c_int32), ("wg_threads", C.c_int32), ("closure", C.c_int32),
-        ("reinject", C.c_int32), ("ce_nu", C.c_double),
+        ("reinject", C.c_int32), ("ce_nu", C.c_double), ("fb_window", C.c_int32),
     ]
 
 
@@ -164,6 +164,7 @@ def params_struct(p: dict) -> Params:
     s.closure = p.get("closure", 0)
     s.reinject = p.get("reinject", 0)
     s.ce_nu = p.get("ce_nu", 0.0)
+    s.fb_window = p.get("fb_window", 0)
     return s
 
 
@@ -317,11 +318,11 @@ class Sim:
         torch = self.torch
         field = FIELD_NAMES.get(field, field) if isinstance(field, str) else field
         if field == STATS:
-            out = np.zeros(9, np.int64)
-            _check(_lib.lbmpcd_moments(self._h, STATS, inst, out.ctypes.data_as(C.c_void_p), 72, 0),
+            out = np.zeros(10, np.int64)
+            _check(_lib.lbmpcd_moments(self._h, STATS, inst, out.ctypes.data_as(C.c_void_p), 80, 0),
                    self._h)
             keys = ("lb_steps", "sampled_steps", "dropped", "misplaced", "far_moves", "max_fill",
-                    "particles", "cells", "window_misses")
+                    "particles", "cells", "window_misses", "bad_state")
             return dict(zip(keys, (int(x) for x in out)))
         dtype = torch.int32 if field in (CELL_ID, CELL_COUNT, CELL_START) else torch.float64
         if field == POP:
@@ -388,6 +389,13 @@ class Sim:
         p = self.plist[inst]
         return self.moments(NODE_MPCD_U, inst).cpu().numpy().reshape(p["dim"], p["n"][2], p["yhi"] - p["ylo"],
                                                                       p["n"][0])
+
+    def node_fb_u(self, inst=0) -> np.ndarray:
+        """Running mean of the MPCD velocity per slab node that the feedback projects,
+        [dim][nz][ny_slab][nx]."""
+        p = self.plist[inst]
+        return self.moments(NODE_FB_U, inst).cpu().numpy().reshape(p["dim"], p["n"][2], p["yhi"] - p["ylo"],
+                                                                    p["n"][0])
 
     def profile(self, inst=0) -> np.ndarray:
         return self.moments(PROFILE, inst).cpu().numpy().reshape(-1, 4)

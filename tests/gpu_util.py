@@ -36,17 +36,25 @@ def periodic_err(a, b, L):
 def compare_state(sim, orc, p, rtol, inst=0, check_cells=True, binning=None):
     """Element-wise comparison of every field both sides define.  `binning`
     is the HIP path's binning when it was read before (cell velocities exist
-    only until the particles are read)."""
+    only until the particles are read).
+
+    Scales: each field's own magnitude; with binary32 populations the fields
+    derived from them (u, Pi, the buffer velocities, the feedback's running
+    mean) are compared in lattice units (at least rho0 c = 1), because the
+    binary32 store bounds their error absolutely: Q populations of about
+    rho/Q each, rounded to 2^-24 relative, give at most Q 2^-24 rho ~ 1.1e-6
+    (D3Q19) in u, however small u is."""
     rep = {}
+    floor = 1.0 if p.get("lb_fp", 64) == 32 else 1e-12
     f_g = sim.f(inst)
     f_o = orc.f()
     rep["pop"] = scaled_err(f_g, f_o)
     rho_g, u_g, pi_g = sim.fields(inst)
     rho_o, u_o, pi_o = orc.moments()
     rep["rho"] = scaled_err(rho_g, rho_o)
-    uscale = max(np.abs(u_o).max(), 1e-12)
+    uscale = max(np.abs(u_o).max(), floor)
     rep["u"] = scaled_err(u_g, u_o, uscale)
-    rep["pi"] = scaled_err(pi_g, pi_o, max(np.abs(pi_o).max(), 1e-300))
+    rep["pi"] = scaled_err(pi_g, pi_o, max(np.abs(pi_o).max(), floor if floor > 1e-12 else 1e-300))
     if p["mpcd"]:
         vcm_g = None
         if check_cells:
@@ -69,14 +77,19 @@ def compare_state(sim, orc, p, rtol, inst=0, check_cells=True, binning=None):
         if p["buf_lo"] + p["buf_hi"] > 0:
             uf_g = sim.ufine(inst)
             uf_o = orc.ufine()
-            rep["ufine"] = scaled_err(uf_g, uf_o, max(np.abs(uf_o).max(), 1e-12))
+            rep["ufine"] = scaled_err(uf_g, uf_o, max(np.abs(uf_o).max(), floor))
             if p.get("reinject", 0):
                 tf_g = sim.tfine(inst)
                 tf_o = orc.tfine()
                 rep["tfine"] = scaled_err(tf_g, tf_o, max(np.abs(tf_o).max(), 1e-12))
+        if p["feedback"] and hasattr(orc, "fb_u"):
+            fb_g = sim.node_fb_u(inst)
+            fb_o = orc.fb_u()[: p["dim"]]
+            rep["fb_u"] = scaled_err(fb_g, fb_o, max(np.abs(fb_o).max(), floor))
         st = sim.stats(inst)
         rep["dropped"] = st["dropped"]
         rep["misplaced"] = st["misplaced"]
+        rep["bad_state"] = st["bad_state"]
         del vcm_g
     return rep
 
@@ -84,7 +97,7 @@ def compare_state(sim, orc, p, rtol, inst=0, check_cells=True, binning=None):
 def assert_parity(rep, rtol):
     bad = []
     for k, v in rep.items():
-        if k in ("cell_mismatch", "count_mismatch", "dropped", "misplaced"):
+        if k in ("cell_mismatch", "count_mismatch", "dropped", "misplaced", "bad_state"):
             if v != 0:
                 bad.append((k, v))
         elif v > rtol:

@@ -30,6 +30,16 @@ CASES = {
     "small_3d_lb32": (W.small_3d(lb_fp=32, part_fp=32), 4, 2e-6),
     "walled_2d": (W.walled_2d(), 6, RTOL64),
     "walled_2d_fp32": (W.walled_2d(part_fp=32, ppc=5), 6, RTOL32),
+    # particle mass other than 1: the virtual wall particles' velocity sum
+    # (variance (N0 - n) kT/m) and every kT/m of the exchange
+    "walled_2d_mass2": (W.walled_2d(mass=2.0, kT=0.5), 6, RTOL64),
+    "walled_2d_fp32_mass05": (W.walled_2d(part_fp=32, ppc=5, mass=0.5, kT=0.2), 6, RTOL32),
+    "at_walled_2d_mass2": (W.walled_2d(collision=1, mass=2.0), 6, RTOL64),
+    "small_2d_mass3": (W.small_2d(mass=3.0), 5, RTOL64),
+    # the feedback's running mean: a window of one LB step (the last sample
+    # alone) and of seven, from the Poiseuille start
+    "fb_window1_2d": (W.small_2d(fb_window=1), 6, RTOL64),
+    "fb_window7_3d_flow": (W.small_3d(fb_window=7, init_flow=1, g=(1e-4, 0, 0)), 6, RTOL64),
     "periodic_2d": (W.periodic_2d(), 6, RTOL64),
     "no_shift": (W.small_2d(grid_shift=0), 4, RTOL64),
     "poiseuille_init": (W.small_2d(init_flow=1, g=(2e-5, 0, 0)), 4, RTOL64),
@@ -161,15 +171,21 @@ def test_parity_set_state_roundtrip(env):
     assert_parity(rep, RTOL64)
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(reinject=1, init_flow=1, g=(1e-4, 0.0, 0.0))],
-                         ids=["maxwell_boltzmann", "chapman_enskog"])
+@pytest.mark.parametrize("kw", [dict(), dict(reinject=1, init_flow=1, g=(1e-4, 0.0, 0.0)), dict(mixed=1)],
+                         ids=["maxwell_boltzmann", "chapman_enskog", "mixed_feedback"])
 def test_batched_instances_match_standalone(env, kw):
     """A batch of uneven channels in one context equals each channel run
     alone through the oracle (instance i keyed by (seed, i)); with the
-    Chapman-Enskog exchange each instance has its own tensor scale."""
+    Chapman-Enskog exchange each instance has its own tensor scale; in the
+    mixed batch the middle channel couples one way and the others project
+    with windows of their own."""
     O, lbmpcd = env
-    ps = [W.small_2d(n=(24 + 8 * i, 20 + 2 * i, 1), ylo=6, yhi=14, ppc=5 + i, instance=i,
-                     **(dict(kw, ce_nu=0.5 + i) if kw else {})) for i in range(3)]
+    if kw.get("mixed"):
+        ps = [W.small_2d(n=(24 + 8 * i, 20 + 2 * i, 1), ylo=6, yhi=14, ppc=5 + i, instance=i, init_flow=1,
+                         g=(1e-4, 0, 0), feedback=int(i != 1), fb_window=3 + 5 * i) for i in range(3)]
+    else:
+        ps = [W.small_2d(n=(24 + 8 * i, 20 + 2 * i, 1), ylo=6, yhi=14, ppc=5 + i, instance=i,
+                         **(dict(kw, ce_nu=0.5 + i) if kw else {})) for i in range(3)]
     sim = lbmpcd.Sim(ps)
     sim.step(4)
     bins = [sim.binning(i) for i in range(len(ps))]
