@@ -380,6 +380,25 @@ int lbmpcd_closure_features(struct lbmpcd_ctx* c, float* X);
 int lbmpcd_closure_forward(struct lbmpcd_ctx* c, const float* X, int64_t n, float* Y, void* scratch,
                            size_t scratch_bytes);
 
+/*
+ * lbmpcd_closure_forward without allocation, for callers that cannot
+ * allocate device memory at the call (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc).  Same result as
+ * lbmpcd_closure_forward on the same X (same kernels and operands): device X
+ * [n][271] raw features in, device Y [n][9] physical outputs out, both owned
+ * by the caller.  The activations live in a file-scope device array of the
+ * library (about 24 MB, one copy on every device the library runs on, held
+ * until the process ends; its address is resolved once per device at
+ * lbmpcd_init); no scratch argument, and the call allocates and frees
+ * nothing.  n must be at most LBMPCD_NOALLOC_MAX_ROWS (E_INVALID otherwise,
+ * before any work is enqueued).  All calls on one device share the array:
+ * calls that overlap on one device (several streams or threads) race and
+ * must be serialised by the caller.  Asynchronous on the context's stream;
+ * E_STATE before the parameters are set.
+ */
+#define LBMPCD_NOALLOC_MAX_ROWS 8192
+int lbmpcd_closure_forward_noalloc(struct lbmpcd_ctx* c, const float* X, int64_t n, float* Y);
+
 /* Network output in physical units for every slab node of the current
  * populations (device Y, nslab x 9, slab nodes x fastest, then y - ylo, then
  * z), computed by the fused inference kernel that the surrogate step uses:

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,12 @@
 #include "launch.hpp"
 
 using namespace lbmpcd;
+
+// Activations of lbmpcd_closure_forward_noalloc: a file-scope device array, one
+// copy on every device the library runs on, held until the process ends.  In
+// host code this name is only a stand-in for the symbol; the device address of
+// each copy comes from hipGetSymbolAddress (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[closure_fwd_bytes(LBMPCD_NOALLOC_MAX_ROWS)];
 
 struct lbmpcd_ctx {
     int n_inst = 0, dim = 2, lb_fp = 64, part_fp = 64, S = 1, Q = 9, mpcd = 0;
@@ -105,6 +112,32 @@ thread_local std::string g_err;
 int fail(lbmpcd_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg; else g_err = msg;
     return code;
+}
+
+// Device address of the `scratch` array on each device, resolved once per
+// device (with that device current) at lbmpcd_init.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+int resolve_noalloc_scratch(int device, std::string& msg) {
+    if (device < 0 || device >= MAX_DEVICES) { msg = "device index beyond the library's table"; return LBMPCD_E_DEVICE; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return 0;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return LBMPCD_E_DEVICE;
+    }
+    g_scratch_ptr[device] = p;
+    return 0;
+}
+
+void* noalloc_scratch(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 #define HIPCHK(ctx, expr)                                                                          \
@@ -564,6 +597,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     c->Q = c->dim == 2 ? 9 : 19; c->mpcd = p[0].mpcd;
     c->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return fail(nullptr, LBMPCD_E_DEVICE, "no HIP device"); }
+    if (int se = resolve_noalloc_scratch(c->device, msg)) { delete c; return fail(nullptr, se, msg); }
     c->ws = (char*)dev_workspace;
     c->ws_bytes = bytes;
     c->total_nodes = tot[0]; c->total_band = tot[1]; c->total_ufine = tot[2]; c->total_tiles = tot[3];
@@ -1266,6 +1300,24 @@ int lbmpcd_closure_forward(lbmpcd_ctx* c, const float* X, int64_t n, float* Y, v
     ClosureBufs b;
     float* Yb = nullptr;
     if (int e = closure_batch(c, X, nullptr, n, n, false, 0u, scratch, b, Yb)) return e;
+    HIPCHK(c, mlp_forward(c->cl_P, c->cl_Pb, b, c->stream));
+    HIPCHK(c, mlp_destandardize(b.Y, c->cl_stats, X, n, Y, c->stream));
+    return 0;
+}
+
+int lbmpcd_closure_forward_noalloc(lbmpcd_ctx* c, const float* X, int64_t n, float* Y) {
+    if (int e = need_closure(c)) return e;
+    if (!c->cl_ready) return fail(c, LBMPCD_E_STATE, "closure parameters are not set");
+    if (!X || !Y || n < 1) return fail(c, LBMPCD_E_INVALID, "bad arguments");
+    if (n > LBMPCD_NOALLOC_MAX_ROWS)
+        return fail(c, LBMPCD_E_INVALID, "n exceeds LBMPCD_NOALLOC_MAX_ROWS (" +
+                                             std::to_string(LBMPCD_NOALLOC_MAX_ROWS) + ") rows; split the call");
+    void* ptr = noalloc_scratch(c->device);
+    if (!ptr) return fail(c, LBMPCD_E_STATE, "the device's scratch array was not resolved at lbmpcd_init");
+    ClosureBufs b;
+    closure_bufs_carve((unsigned char*)ptr, n, false, b);
+    const InstDesc& d = c->desc[0];
+    HIPCHK(c, mlp_gather(X, nullptr, n, c->cl_stats, n, false, d.key0, d.key1, 0u, b.X, nullptr, c->stream));
     HIPCHK(c, mlp_forward(c->cl_P, c->cl_Pb, b, c->stream));
     HIPCHK(c, mlp_destandardize(b.Y, c->cl_stats, X, n, Y, c->stream));
     return 0;

@@ -116,9 +116,8 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
 static inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 size_t closure_bufs_bytes(long long rows, bool backward) {
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    size_t b = al((size_t)rows * NFP * 2) + 3 * (al((size_t)rows * NH * 4) + al((size_t)rows * NH * 2)) +
-               al((size_t)rows * NOUT * 4);
+    auto al = closure_al256;
+    size_t b = closure_fwd_bytes(rows);
     if (backward) b += al((size_t)rows * NOUT * 4) + al((size_t)rows * NOUT * 2) +
                        3 * (al((size_t)rows * NH * 4) + al((size_t)rows * NH * 2));
     return b;

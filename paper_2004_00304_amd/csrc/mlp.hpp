@@ -73,7 +73,14 @@ struct ClosureBufs {
     float* dY; uint16_t* dYb; // [rows][NOUT] loss gradient
     float* dZ[3]; uint16_t* dZb[3];  // [rows][NH] hidden pre-activation gradients
 };
-// Bytes of ClosureBufs for `rows` rows, and the carve-up of such an area.
+// Bytes of ClosureBufs for `rows` rows, and the carve-up of such an area
+// (every buffer starts on a 256-byte boundary).
+constexpr size_t closure_al256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t closure_fwd_bytes(long long rows) {
+    return closure_al256((size_t)rows * NFP * 2) +
+           3 * (closure_al256((size_t)rows * NH * 4) + closure_al256((size_t)rows * NH * 2)) +
+           closure_al256((size_t)rows * NOUT * 4);
+}
 size_t closure_bufs_bytes(long long rows, bool backward);
 void closure_bufs_carve(unsigned char* base, long long rows, bool backward, ClosureBufs& b);
 

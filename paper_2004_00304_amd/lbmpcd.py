@@ -101,6 +101,7 @@ def _load():
     L.lbmpcd_closure_forward.argtypes = [P, P, C.c_int64, P, P, C.c_size_t]
     L.lbmpcd_closure_features.argtypes = [P, P]
     L.lbmpcd_closure_predict.argtypes = [P, P]
+    L.lbmpcd_closure_forward_noalloc.argtypes = [P, P, C.c_int64, P]
     L.lbmpcd_viscosity.argtypes = [C.POINTER(Params), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.lbmpcd_viscosity.restype = C.c_int
     L.lbmpcd_closure_weights.argtypes = [P, C.c_int32, P, C.c_size_t]
@@ -111,7 +112,8 @@ def _load():
     for name in ("lbmpcd_closure_scratch_size", "lbmpcd_closure_collect", "lbmpcd_closure_train",
                  "lbmpcd_closure_loss_grad", "lbmpcd_closure_forward", "lbmpcd_closure_weights",
                  "lbmpcd_closure_enable", "lbmpcd_closure_check", "lbmpcd_closure_status",
-                 "lbmpcd_closure_gemm_bf16", "lbmpcd_closure_features", "lbmpcd_closure_predict"):
+                 "lbmpcd_closure_gemm_bf16", "lbmpcd_closure_features", "lbmpcd_closure_predict",
+                 "lbmpcd_closure_forward_noalloc"):
         getattr(L, name).restype = C.c_int
     L.lbmpcd_last_error.argtypes = [P]
     L.lbmpcd_last_error.restype = C.c_char_p
@@ -130,7 +132,11 @@ EXPORTED = ("lbmpcd_workspace_size", "lbmpcd_init", "lbmpcd_step", "lbmpcd_momen
             "lbmpcd_closure_collect", "lbmpcd_closure_train", "lbmpcd_closure_loss_grad",
             "lbmpcd_closure_forward", "lbmpcd_closure_weights", "lbmpcd_closure_enable",
             "lbmpcd_closure_check", "lbmpcd_closure_status", "lbmpcd_closure_gemm_bf16",
-            "lbmpcd_closure_features", "lbmpcd_closure_predict", "lbmpcd_viscosity")
+            "lbmpcd_closure_features", "lbmpcd_closure_predict", "lbmpcd_viscosity",
+            "lbmpcd_closure_forward_noalloc")
+
+# rows of one lbmpcd_closure_forward_noalloc call
+NOALLOC_MAX_ROWS = 8192
 
 # candidate tile sizes of lbmpcd_autotune (expected particles per tile)
 TUNE_TILE_TARGETS = (160, 320, 640, 1280)
@@ -477,6 +483,17 @@ class Sim:
         Y = self.torch.empty(n, CLOSURE_NOUT, dtype=self.torch.float32, device=self.device)
         _check(_lib.lbmpcd_closure_forward(self._h, C.c_void_p(X.data_ptr()), n, C.c_void_p(Y.data_ptr()),
                                            C.c_void_p(scr.data_ptr()), scr.numel()), self._h)
+        return Y
+
+    def closure_forward_noalloc(self, X):
+        """lbmpcd_closure_forward_noalloc: the network on rows of raw features
+        (at most NOALLOC_MAX_ROWS) with the library's own device array for the
+        activations.  Only the output tensor is allocated here, by torch."""
+        X = X.contiguous()
+        n = X.shape[0]
+        Y = self.torch.empty(n, CLOSURE_NOUT, dtype=self.torch.float32, device=self.device)
+        _check(_lib.lbmpcd_closure_forward_noalloc(self._h, C.c_void_p(X.data_ptr()), n, C.c_void_p(Y.data_ptr())),
+               self._h)
         return Y
 
     def closure_predict(self):
