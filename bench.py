@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of the coupled LB-MPCD time step on one MI355X.
 
-Workload: the 3D channel -- D3Q19 128x64x64 (tau 0.8, g 1e-6 along x, walls
-at y = 0 and 64, periodic x and z) coupled to an MPCD slab y in [24, 40) with
-2-row buffers, cell side 1/4 (512x64x256 cells), 20 particles per cell
-(167,772,160 binary32 particles, FP64 cell sums), SRD 120 deg about a random
-axis, 4 MPCD steps per LB step, random grid shift, feedback on.  Synthetic,
-seeded: positions uniform in cells, Maxwell-Boltzmann velocities.
+Default workload: the thin film -- D3Q19 512x256x256 nodes with binary32
+populations (tau 0.7, g 1e-6 along x, walls at y = 0 and 256, periodic x and
+z) coupled to an MPCD film y in [126, 130) with 1-row buffers, cell side 1/4
+(2048x16x1024 cells), 10 particles per cell (335,544,320 binary32 particles,
+FP64 cell sums), SRD 120 deg about a random axis, 4 MPCD steps per LB step,
+random grid shift, feedback on (window 50 LB steps).  The largest of the
+single-GPU configurations.  Synthetic, seeded: positions uniform in cells,
+Maxwell-Boltzmann velocities.
 
 One "step" is one coupled LB step (LB collide-stream, feedback projection,
 interpolation to the buffer cells, 4 fused MPCD steps).  Prints one JSON line:
 the contract's fields; `roofline` for the fused particle kernel (algorithmic
 bytes per launch over its HIP-event time, against 8 TB/s; `traffic` from the
-committed rocprofv3 PMC summary while the kernel source is unchanged);
+committed rocprofv3 PMC summary of the workload while the sources of the
+step's kernels are unchanged); `lb_roofline` for the LB collide-stream kernel;
 `coupled_hbm_frac` (algorithmic) and `coupled_counter_frac` (counter-measured)
 for the whole step; the timed steps in five chunks; the sample-window misses;
-and `cpu_baseline`, the oracle timed on one host core on a cut of the workload.
-Other workloads: --workload channel_3d_at | channel_3d_ce | thin_film_3d |
+and `cpu_baseline`, the oracle timed on the host cores (one process per core,
+up to 16) on a cut of the workload, taken before the GPU is touched.
+Other workloads: --workload channel_3d | channel_3d_at | channel_3d_ce |
 channel_2d | ensemble | closure.
 """
 from __future__ import annotations
@@ -32,9 +36,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
-PMC_FILE = os.path.join(ROOT, "profiles", "k_particles_channel_3d_pmc.json")
+# every source the coupled step's kernels are compiled from, and the flags
 KERNEL_SOURCES = ["paper_2004_00304_amd/csrc/particles.hpp", "paper_2004_00304_amd/csrc/kernels_mpcd.hip",
-                  "paper_2004_00304_amd/csrc/common.hpp"]
+                  "paper_2004_00304_amd/csrc/kernels_mpcd_ce.hip", "paper_2004_00304_amd/csrc/common.hpp",
+                  "paper_2004_00304_amd/csrc/fmath.hpp", "paper_2004_00304_amd/csrc/launch.hpp",
+                  "paper_2004_00304_amd/csrc/kernels_lb.hip", "paper_2004_00304_amd/build.py"]
+MAX_CPU_WORKERS = 16  # host cores the CPU baseline may use (the GPU machine's share)
+
+
+def pmc_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"k_particles_{workload}_pmc.json")
 
 
 def kernel_hash() -> str:
@@ -45,7 +56,7 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def workload(name: str) -> list:
+def workload_params(name: str) -> list:
     """Parameter dicts of the named workload (one per channel)."""
     from paper_2004_00304_amd import workloads as W
     if name == "ensemble":
@@ -72,88 +83,131 @@ def totals(plist: list) -> dict:
     return out
 
 
-def _pmc():
-    """The committed rocprofv3 PMC summary (FETCH_SIZE, WRITE_SIZE scaled by a
-    plain copy of known size), or None when it is absent or the kernel
-    changed since it was taken."""
-    if not os.path.exists(PMC_FILE):
+def _pmc(workload: str):
+    """The committed rocprofv3 PMC summary of the workload (FETCH_SIZE,
+    WRITE_SIZE scaled by a plain copy of known size), or None when it is
+    absent or a source of the step's kernels changed since it was taken."""
+    path = pmc_file(workload)
+    if not os.path.exists(path):
         return None
-    with open(PMC_FILE) as f:
+    with open(path) as f:
         pmc = json.load(f)
     if pmc.get("kernel_hash") != kernel_hash():
         return None
     return pmc
 
 
-def measured_traffic(per_launch_particles: int):
+def measured_traffic(workload: str):
     """HBM bytes per launch of the particle kernel from the PMC summary."""
-    pmc = _pmc()
+    pmc = _pmc(workload)
     return pmc.get("bytes_per_launch") if pmc else None
 
 
-def measured_step_traffic():
+def measured_step_traffic(workload: str):
     """HBM bytes per coupled LB step (all its kernels) from the PMC summary."""
-    pmc = _pmc()
+    pmc = _pmc(workload)
     return pmc.get("step_bytes_per_lb_step") if pmc else None
 
 
-def cpu_baseline_ensemble(plist: list, seconds_cap: float = 15.0) -> dict:
-    """The oracle on the first channels of the ensemble, one LB step each in
-    turn, single thread, scaled to the whole ensemble by the particle ratio."""
-    from oracle import oracle as O
+def _cut(p: dict) -> dict:
+    """The bounded CPU sample of a workload: x and z cut (same per-node and
+    per-particle work) by 8, or by 16 for the 512-node-long thin film."""
     from paper_2004_00304_amd import workloads as W
-
-    if not os.path.exists(O.LIB_PATH):
-        O.build()
-    total = sum(W.sizes(p)["particles"] for p in plist)
-    done_particles, k, steps = 0, 0, 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds_cap and k < len(plist):
-        o = O.Oracle(plist[k])
-        o.step(1)
-        done_particles += W.sizes(plist[k])["particles"]
-        k += 1
-        steps += 1
-    dt = time.perf_counter() - t0
-    rate = done_particles / dt  # particle-LB-steps per second
-    return dict(value=rate / total, unit="coupled LB steps/s", cores=1, kind="oracle",
-                sample=(f"channels 0..{k - 1} of {len(plist)} ({done_particles} particles), one LB step "
-                        f"each in {dt:.1f} s (including set-up), scaled by the particle ratio "
-                        f"{done_particles / total:.5f}"),
-                particle_updates_per_s=rate * plist[0]["substeps"])
-
-
-def cpu_baseline(p: dict, seconds_cap: float = 15.0) -> dict:
-    """The oracle, as it stands, on a bounded sample of the same workload:
-    x and z cut by 8 (same per-node and per-particle work), single thread."""
-    from oracle import oracle as O
-    from paper_2004_00304_amd import workloads as W
-
-    if not os.path.exists(O.LIB_PATH):
-        O.build()
     if p["dim"] == 2:
-        q = W.make(**{**p, "n": (max(p["n"][0] // 8, 8), p["n"][1], 1)})
-    else:
-        q = W.make(**{**p, "n": (p["n"][0] // 8, p["n"][1], p["n"][2] // 8)})
-    o = O.Oracle(q)
-    full = W.sizes(p)
-    samp = W.sizes(q)
-    steps = 0
+        return W.make(**{**p, "n": (max(p["n"][0] // 8, 8), p["n"][1], 1)})
+    f = 16 if p["n"][0] >= 512 else 8
+    return W.make(**{**p, "n": (p["n"][0] // f, p["n"][1], p["n"][2] // f)})
+
+
+def cpu_worker(workload: str, seconds: float, index: int, stride: int) -> None:
+    """One CPU-baseline process: the oracle, single-threaded, on the cut of
+    the workload (the ensemble: channels index, index + stride, ... one LB
+    step each) until `seconds` have passed; prints its counts as JSON."""
+    from oracle import oracle as O
+    from paper_2004_00304_amd import workloads as W
+    plist = workload_params(workload)
+    particles = nodes = steps = 0
     t0 = time.perf_counter()
-    while True:
-        o.step(1)
-        steps += 1
-        if time.perf_counter() - t0 > seconds_cap or steps >= 200:
-            break
-    dt = time.perf_counter() - t0
-    sample_sps = steps / dt
-    scale = samp["particles"] / full["particles"]
-    return dict(value=sample_sps * scale, unit="coupled LB steps/s", cores=1, kind="oracle",
-                sample=(f"{q['n'][0]}x{q['n'][1]}x{q['n'][2]} nodes, {samp['particles']} particles "
-                        f"(x and z cut 8x), {steps} LB steps in {dt:.1f} s, scaled by the particle "
-                        f"ratio {scale:.5f}"),
-                particle_updates_per_s=samp["particles"] * p["substeps"] * sample_sps,
-                lb_mlups=samp["nodes"] * sample_sps / 1e6)
+    if len(plist) > 1:
+        k = index
+        while time.perf_counter() - t0 < seconds and k < len(plist):
+            O.Oracle(plist[k]).step(1)
+            sz = W.sizes(plist[k])
+            particles += sz["particles"]
+            nodes += sz["nodes"]
+            steps += 1
+            k += stride
+    else:
+        q = _cut(plist[0])
+        o = O.Oracle(q)
+        sz = W.sizes(q)
+        while True:
+            o.step(1)
+            steps += 1
+            particles += sz["particles"]
+            nodes += sz["nodes"]
+            if time.perf_counter() - t0 > seconds or steps >= 200:
+                break
+    print(json.dumps(dict(steps=steps, particles=particles, nodes=nodes, dt=time.perf_counter() - t0)), flush=True)
+
+
+def host_description() -> dict:
+    """The host's CPU from lscpu (model, counts) and the cores this process may use."""
+    import subprocess
+    out = {"usable_cpus": len(os.sched_getaffinity(0))}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket", "Socket(s)",
+                             "CPU max MHz"):
+                out[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        out["lscpu"] = "unavailable"
+    return out
+
+
+def cpu_baseline(workload: str, seconds: float = 12.0) -> dict:
+    """The oracle, as it stands, on a bounded sample of the workload: first
+    one process (one core), then one process per usable core (at most 16)
+    side by side; coupled LB steps/s of the whole workload scaled from the
+    sample by the particle ratio.  Run before the GPU is initialised (the
+    workers are child processes)."""
+    import subprocess
+    from oracle import oracle as O
+    from paper_2004_00304_amd import workloads as W
+    if not os.path.exists(O.LIB_PATH):
+        O.build()
+    plist = workload_params(workload)
+    total_particles = sum(W.sizes(p)["particles"] for p in plist)
+    substeps = plist[0]["substeps"]
+
+    def run(nproc):
+        procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", workload,
+                                   str(seconds), str(i), str(nproc)], stdout=subprocess.PIPE, text=True)
+                 for i in range(nproc)]
+        res = [json.loads(pr.communicate()[0].strip().splitlines()[-1]) for pr in procs]
+        rate = sum(r["particles"] / r["dt"] for r in res)  # particle-LB-steps per second
+        lb = sum(r["nodes"] / r["dt"] for r in res)
+        return rate, lb, res
+
+    r1, lb1, res1 = run(1)
+    nproc = max(1, min(len(os.sched_getaffinity(0)), MAX_CPU_WORKERS))
+    rn, lbn, resn = run(nproc) if nproc > 1 else (r1, lb1, res1)
+    if len(plist) > 1:
+        sample = (f"one LB step of each of the first channels of the ensemble in turn, {seconds:.0f} s per "
+                  f"process ({res1[0]['steps']} channels on one core; {sum(r['steps'] for r in resn)} on "
+                  f"{nproc} cores), scaled by the particle ratio")
+    else:
+        q = _cut(plist[0])
+        sample = (f"{q['n'][0]}x{q['n'][1]}x{q['n'][2]} nodes, {W.sizes(q)['particles']} particles (x and z "
+                  f"cut like the workload's), {res1[0]['steps']} LB steps in {res1[0]['dt']:.1f} s on one core; "
+                  f"{nproc} such processes side by side, {sum(r['steps'] for r in resn)} LB steps; scaled by "
+                  f"the particle ratio {W.sizes(q)['particles'] / total_particles:.5f}")
+    return dict(value=rn / total_particles, unit="coupled LB steps/s", cores=nproc, kind="oracle", sample=sample,
+                one_core_value=r1 / total_particles,
+                particle_updates_per_s=rn * substeps, particle_updates_per_s_one_core=r1 * substeps,
+                lb_mlups=lbn / 1e6, lb_mlups_one_core=lb1 / 1e6, host=host_description())
 
 
 def one_by_one(lbmpcd, plist: list, batched_ms: float, sample: int = 16, steps: int = 8) -> dict:
@@ -267,11 +321,11 @@ def calib_copy():
     print(json.dumps({"calib_copy_bytes": n}), flush=True)
 
 
-def pmc_summary(fetch_csv: str, write_csv: str, command: str) -> None:
-    """Writes the committed PMC summary of the particle kernel from two
-    rocprofv3 --pmc runs of `bench.py --calib-copy` (FETCH_SIZE, WRITE_SIZE;
-    KiB per dispatch).  Each counter is scaled by what it reads for the plain
-    1 GiB device copy in the same run."""
+def pmc_summary(workload: str, fetch_csv: str, write_csv: str, command: str) -> None:
+    """Writes the committed PMC summary of the workload's particle kernel
+    from two rocprofv3 --pmc runs of `bench.py --calib-copy` (FETCH_SIZE,
+    WRITE_SIZE; KiB per dispatch).  Each counter is scaled by what it reads
+    for the plain 1 GiB device copy in the same run."""
     import csv
     from paper_2004_00304_amd import workloads as W
 
@@ -305,10 +359,12 @@ def pmc_summary(fetch_csv: str, write_csv: str, command: str) -> None:
         wk = [v for k, vs in w.items() if tag in k for v in vs]
         return (sum(fk) / len(fk) * fscale + sum(wk) / len(wk) * wscale) * 1024 if fk and wk else 0.0
     other = {t: mean_bytes(t) for t in ("k_lb_step", "k_band", "k_interp")}
-    p = W.channel_3d()
-    alg = W.algorithmic_bytes_per_lb_step(p)["per_particle_update"] * W.sizes(p)["particles"]
+    plist = workload_params(workload)
+    p = plist[0]
+    alg = totals(plist)["launch_bytes"]
+    lb_alg = totals(plist)["lb_bytes"]
     out = {
-        "kernel": f"{', '.join(names)} (fused MPCD step), channel_3d",
+        "kernel": f"{', '.join(names)} (fused MPCD step), {workload}",
         "kernel_hash": kernel_hash(),
         "command": command,
         "dispatches": len(pf),
@@ -321,9 +377,10 @@ def pmc_summary(fetch_csv: str, write_csv: str, command: str) -> None:
         "algorithmic_bytes_per_launch": alg,
         "traffic_over_algorithmic": (fetch_b + write_b) / alg,
         "other_kernels_bytes_per_lb_step": other,
+        "lb_step_algorithmic_bytes": lb_alg,
         "step_bytes_per_lb_step": p["substeps"] * (fetch_b + write_b) + sum(other.values()),
     }
-    with open(PMC_FILE, "w") as fo:
+    with open(pmc_file(workload), "w") as fo:
         json.dump(out, fo, indent=1)
     print(json.dumps(out, indent=1))
 
@@ -333,7 +390,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="channel_3d",
+    ap.add_argument("--workload", default="thin_film_3d",
                     choices=["channel_3d", "channel_3d_at", "channel_3d_ce", "channel_2d", "thin_film_3d",
                              "ensemble", "closure"])
     ap.add_argument("--autotune", action="store_true",
@@ -343,10 +400,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
-                    help="write the particle kernel's PMC summary from two rocprofv3 runs and exit")
+                    help="write the workload's particle-kernel PMC summary from two rocprofv3 runs and exit")
+    ap.add_argument("--cpu-worker", nargs=4, metavar=("WORKLOAD", "SECONDS", "INDEX", "STRIDE"),
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        w, sec, i, st = args.cpu_worker
+        cpu_worker(w, float(sec), int(i), int(st))
+        return
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary)
+        pmc_summary(args.workload, *args.pmc_summary)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU "
@@ -360,9 +423,12 @@ def main():
     if args.workload == "closure":
         closure_bench(lbmpcd, W, args)
         return
+    # the CPU baseline first: its worker processes start before this one
+    # touches the GPU, and nothing else loads the host while the GPU is timed
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload)
     if args.calib_copy:
         calib_copy()
-    plist = workload(args.workload)
+    plist = workload_params(args.workload)
     p = plist[0]
     tot = totals(plist)
     torch.cuda.set_device(0)
@@ -404,8 +470,9 @@ def main():
     part_ms = kp["ms"] / max(kp["launches"], 1)
     per_launch = tot["launch_bytes"]
     achieved = per_launch / (part_ms * 1e-3) / 1e9
-    traffic = measured_traffic(tot["particles"]) if args.workload == "channel_3d" else None
-    step_traffic = measured_step_traffic() if args.workload == "channel_3d" else None
+    traffic = measured_traffic(args.workload)
+    step_traffic = measured_step_traffic(args.workload)
+    lb_ms = kt["lb_step"]["ms"] / max(kt["lb_step"]["launches"], 1)
     if args.workload == "ensemble":
         wl = (f"ensemble: 256 2D channels (D2Q9, widths 16-128, lengths 32-256, strip W/4 with 1-row "
               f"buffers, r 4, 5-20 ppc, FP64), {tot['nodes']} nodes, {tot['particles']} particles, "
@@ -429,7 +496,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 particles / f64 LB and cell sums" if p["part_fp"] == 32 else "f64",
+        "dtype": ("f64" if p["part_fp"] == 64 and p["lb_fp"] == 64 else
+                  f"f32 particles, f{p['lb_fp']} LB populations, f64 cell sums and arithmetic"),
         "data": "synthetic (seeded Poiseuille channel; uniform-in-cell positions, Maxwellian velocities)",
         "config": {
             "workload": wl, "channels": len(plist),
@@ -456,14 +524,18 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": per_launch,
         },
-        "cpu_baseline": None,
+        "lb_roofline": {
+            "bound": "hbm", "kernel": "k_lb_step (collide and stream)",
+            "achieved": tot["lb_bytes"] / (lb_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": tot["lb_bytes"] / (lb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": tot["lb_bytes"],
+        },
+        "cpu_baseline": cpu,
     }
     if len(plist) > 1:
         del sim
         torch.cuda.empty_cache()
         out["batched_vs_one_by_one"] = one_by_one(lbmpcd, plist, ms_per_step)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_ensemble(plist) if len(plist) > 1 else cpu_baseline(p)
     print(json.dumps(out), flush=True)
 
 
