@@ -935,17 +935,22 @@ static void stream_particle(orc_state* s, int64_t k) {
 }
 
 /* READING: the sample instant is right after streaming.  The per-LB-step
- * accumulators feed the feedback; while sampling is on every MPCD step also
- * adds to the time-averaged profile of its fine row (the paper averages the
- * profiles over samples to suppress the particle noise, Sec. 3.1). */
+ * accumulators feed the feedback, which projects the interior slab nodes
+ * only, so particles in buffer rows are not sampled for it; while sampling is
+ * on every sample also adds to the time-averaged profile of its fine row,
+ * buffers included (the paper averages the profiles over samples to
+ * suppress the particle noise, Sec. 3.1). */
 static void sample_particle(orc_state* s, int64_t k) {
     const orc_params* p = &s->p;
     int ix = clampi((int)floor(s->pos[0][k]), 0, p->nx - 1);
     int J = fine_row(s, s->pos[1][k]);
     int iz = (p->dim == 3) ? clampi((int)floor(s->pos[2][k]), 0, p->nz - 1) : 0;
-    double* a = s->acc + 4 * (((int64_t)iz * s->R + J) * p->nx + ix);
-    a[0] += 1.0;
-    for (int d = 0; d < p->dim; ++d) a[1 + d] += s->vel[d][k];
+    const int r = p->refine;
+    if (J >= p->buf_lo * r && J < s->R - p->buf_hi * r) {
+        double* a = s->acc + 4 * (((int64_t)iz * s->R + J) * p->nx + ix);
+        a[0] += 1.0;
+        for (int d = 0; d < p->dim; ++d) a[1 + d] += s->vel[d][k];
+    }
     if (s->sampling) {
         double* q = s->prof + 4 * J;
         q[0] += 1.0;

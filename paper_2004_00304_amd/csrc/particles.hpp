@@ -487,7 +487,10 @@ k_particles(PArgs<PT> A) {
         uint32_t dest[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) dest[k] = BAD_SLOT;
-        // exchange step: redraw buffer particles about the LB velocity
+        // exchange step: redraw buffer particles about the LB velocity.  (A
+        // version that first listed each wave's buffer particles densely in
+        // LDS, so that mixed waves ran the normals once per 64 of them, was
+        // measured: 1 % faster on the thin film, 2 % slower on the 3D channel.)
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             if (!valid[k]) continue;
@@ -584,7 +587,9 @@ k_particles(PArgs<PT> A) {
                 if (!valid[k]) continue;
                 const int J = clampi((int)floor(((double)px[k][1] - ylo_d) * (double)d.r), 0, d.R - 1);
                 double vals[4] = {1.0, (double)pv[k][0], (double)pv[k][1], DIM == 3 ? (double)pv[k][2] : 0.0};
-                if (A.do_fb) {
+                // the feedback projects the interior slab nodes only: buffer
+                // rows are not sampled for it (the profile takes every row)
+                if (A.do_fb && J >= rb_lo && J < rb_hi) {
                     const int ixn = clampi((int)floor((double)px[k][0]), 0, d.nx - 1);
                     const int iyn = d.lr >= 0 ? (J >> d.lr) : J / d.r;
                     const int izn = (DIM == 3) ? clampi((int)floor((double)px[k][2]), 0, d.nz - 1) : 0;

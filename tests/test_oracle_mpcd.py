@@ -412,3 +412,25 @@ def test_profile_is_row_average_of_samples(oracle_lib):
     acc, _ = o.profile()
     assert (acc[:, 0] == ref[:, 0]).all()
     assert np.abs(acc[:, 1:3] - ref[:, 1:3]).max() < 1e-11
+
+
+def test_feedback_samples_only_interior_rows(oracle_lib):
+    """The feedback projects the interior slab nodes only, so its per-LB-step
+    samples are taken in the interior fine rows (every particle there, once)
+    and none in the buffer rows, while the time-averaged profile takes every
+    row."""
+    p = W.small_2d(alpha_deg=0.0, substeps=1)
+    o = oracle_lib.Oracle(p)
+    o.sample(1)
+    o.step(1)
+    pos, _ = o.particles()
+    r = p["refine"]
+    R = (p["yhi"] - p["ylo"]) * r
+    J = np.clip(np.floor((pos[1] - p["ylo"]) * r).astype(int), 0, R - 1)
+    acc = o.step_acc()[0]  # [R][nx][4]
+    rows = acc[:, :, 0].sum(axis=1)
+    interior = (np.arange(R) >= p["buf_lo"] * r) & (np.arange(R) < R - p["buf_hi"] * r)
+    assert (rows[~interior] == 0).all()
+    assert (rows[interior] == np.bincount(J, minlength=R)[interior]).all()
+    prof, _ = o.profile()
+    assert (prof[:, 0] == np.bincount(J, minlength=R)).all()
