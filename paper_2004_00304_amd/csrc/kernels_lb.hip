@@ -36,9 +36,10 @@ __device__ __forceinline__ void equilibrium_guo(const double* f, double omega, d
         j1 += f[i] * (double)L::cy[i];
         j2 += f[i] * (double)L::cz[i];
     }
-    double u0 = j0 / rho + 0.5 * g[0];
-    double u1 = j1 / rho + 0.5 * g[1];
-    double u2 = j2 / rho + 0.5 * g[2];
+    const double inv = 1.0 / rho;
+    double u0 = j0 * inv + 0.5 * g[0];
+    double u1 = j1 * inv + 0.5 * g[1];
+    double u2 = j2 * inv + 0.5 * g[2];
     double F0 = rho * g[0], F1 = rho * g[1], F2 = rho * g[2];
     double uu = u0 * u0 + u1 * u1 + u2 * u2;
 #pragma unroll
@@ -92,18 +93,52 @@ __global__ void __launch_bounds__(WG) k_lb_step(const InstDesc* __restrict__ D, 
     const InstDesc& d = D[ii];
     long long n = gid - d.node_off;
     const int nx = d.nx, ny = d.ny, nz = d.nz;
-    int x = (int)(n % nx);
-    int y = (int)((n / nx) % ny);
-    int z = (int)(n / ((long long)nx * ny));
     const long long N = d.N;
+    int x, y, z;
+    if (N < (1LL << 31)) {  // node coordinates in 32-bit arithmetic
+        const uint32_t n32 = (uint32_t)n, row = n32 / (uint32_t)nx;
+        x = (int)(n32 - row * (uint32_t)nx);
+        y = (int)(row % (uint32_t)ny);
+        z = (int)(row / (uint32_t)ny);
+    } else {
+        x = (int)(n % nx);
+        y = (int)((n / nx) % ny);
+        z = (int)(n / ((long long)nx * ny));
+    }
     const LT* f_in = fin + d.node_off * Q;
     LT* f_out = fout + d.node_off * Q;
+    const long long sxy = (long long)nx * ny;
+    // Rows that touch neither a y nor a z face stream with offsets that are
+    // the same for every node of the row (only x wraps): each population
+    // array is addressed as a uniform base plus a 32-bit byte offset.  For a
+    // channel whose x extent is a multiple of 64 a wave lies in one row, so
+    // the test is uniform across the wave.
+    const bool fast = N * (long long)sizeof(LT) < (1LL << 32) && y > 0 && y < ny - 1 &&
+                      (DIM == 2 || (z > 0 && z < nz - 1));
+    const uint32_t nb = (uint32_t)n * (uint32_t)sizeof(LT);
+    const size_t qbytes = (size_t)N * sizeof(LT);
     double f[Q], fs[Q];
+    if (fast) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = (double)f_in[i * N + n];
+        for (int i = 0; i < Q; ++i) f[i] = (double)*(const LT*)((const unsigned char*)f_in + i * qbytes + nb);
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = (double)f_in[i * N + n];
+    }
     double g[3] = {d.g[0], d.g[1], d.g[2]};
     equilibrium_guo<DIM>(f, d.omega, d.src, g, fs);
-    const long long sxy = (long long)nx * ny;
+    if (fast) {
+        const int rowb = (int)(n - x);  // node index of x = 0 in this row
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int xd = x + L::cx[i];
+            if (L::cx[i] < 0 && xd < 0) xd += nx;
+            if (L::cx[i] > 0 && xd >= nx) xd -= nx;
+            const int nd = rowb + xd + L::cy[i] * nx + L::cz[i] * (int)sxy;
+            *(LT*)((unsigned char*)f_out + i * qbytes + (uint32_t)nd * (uint32_t)sizeof(LT)) = (LT)fs[i];
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int yd = y + L::cy[i];
