@@ -101,6 +101,104 @@ void orc_box_muller(double u0, double u1, double* z0, double* z1) {
     *z1 = r * sin(th);
 }
 
+/* READING (binary32 normals): particles stored in binary32 draw the normal
+ * deviates of the Maxwell-Boltzmann exchange step and of MPCD-AT in binary32
+ * arithmetic.  One Philox block w[0..3] of the element's stream gives four
+ * uniforms a_k = (w_k >> 8) 2^-24 (exact in binary32); the pairs (a0, a1) and
+ * (a2, a3) give Box-Muller pairs with radius sqrt(-2 ln(1 - a_even)) and angle
+ * 2 pi a_odd (z0 = rho cos, z1 = rho sin; in 3D z2 is the cosine of the second
+ * pair).  ln and sin/cos are the series below, every step one IEEE binary32
+ * operation (fmaf, correctly rounded division and square root), so that any
+ * implementation of the definition yields the same bits. */
+
+/* ln x for x in (0, 1], binary32: x = m 2^e with m in [sqrt(1/2), sqrt(2));
+ * ln m = 2 atanh s with s = (m - 1)/(m + 1) = f/(2 + f), f = m - 1 exact;
+ * 2 atanh s = 2s (1 + z/3 + z^2/5 + z^3/7 + z^4/9 + ...), z = s^2 < 0.0295,
+ * summed to z^4/9: the first omitted term, z^5/11, is below 2e-9 of the sum,
+ * a thirtieth of a binary32 unit.  Constants: sqrt(1/2) and ln 2 rounded to
+ * binary32, 1/(2k+1) as binary32 quotients. */
+float orc_ln32(float x) {
+    int e;
+    float m = frexpf(x, &e); /* m in [1/2, 1) */
+    if (m < 0x1.6a09e6p-1f) {
+        m = m + m;
+        e = e - 1;
+    }
+    const float f = m - 1.0f;
+    const float s = f / (2.0f + f);
+    const float z = s * s;
+    float c = 1.0f / 9.0f;
+    c = fmaf(c, z, 1.0f / 7.0f);
+    c = fmaf(c, z, 1.0f / 5.0f);
+    c = fmaf(c, z, 1.0f / 3.0f);
+    const float s2 = s + s;
+    const float lnm = fmaf(s2 * z, c, s2);
+    return fmaf((float)e, 0x1.62e430p-1f, lnm);
+}
+
+/* sin and cos of 2 pi u for u in [0, 1), binary32: 4u = q + y' exactly with
+ * q = rint(4u) (ties to even) and |y'| <= 1/2; y = y' (pi/2), |y| <= pi/4;
+ * sin y = y - y^3/3! + ... to y^9/9!, cos y = 1 - y^2/2! + ... to y^8/8!
+ * (first omitted terms below 2e-9 and 2.5e-8 on that interval, under half a
+ * binary32 unit of the result); the
+ * quadrant q mod 4 then swaps and negates them.  pi/2 rounded to binary32. */
+void orc_sincos32(float u, float* sn, float* cs) {
+    const float t = 4.0f * u;
+    const float q = rintf(t);
+    const float y = (t - q) * 0x1.921fb6p+0f;
+    const float z = y * y;
+    float ps = 1.0f / 362880.0f;
+    ps = fmaf(ps, z, -1.0f / 5040.0f);
+    ps = fmaf(ps, z, 1.0f / 120.0f);
+    ps = fmaf(ps, z, -1.0f / 6.0f);
+    const float sy = fmaf(ps * z, y, y);
+    float pc = 1.0f / 40320.0f;
+    pc = fmaf(pc, z, -1.0f / 720.0f);
+    pc = fmaf(pc, z, 1.0f / 24.0f);
+    pc = fmaf(pc, z, -0.5f);
+    const float cy = fmaf(pc, z, 1.0f);
+    const int quad = (int)q & 3;
+    /* angle = quad pi/2 + y */
+    switch (quad) {
+        case 0: *sn = sy; *cs = cy; break;
+        case 1: *sn = cy; *cs = -sy; break;
+        case 2: *sn = -sy; *cs = -cy; break;
+        default: *sn = -cy; *cs = sy; break;
+    }
+}
+
+/* The binary32 normals of one Philox block (READING above); z[2] = 0 in 2D. */
+void orc_normals32(const uint32_t w[4], int32_t dim, float z[3]) {
+    float a[4];
+    for (int k = 0; k < 4; ++k) a[k] = (float)(w[k] >> 8) * 0x1p-24f;
+    float sn, cs;
+    const float r0 = sqrtf(-2.0f * orc_ln32(1.0f - a[0]));
+    orc_sincos32(a[1], &sn, &cs);
+    z[0] = r0 * cs;
+    z[1] = r0 * sn;
+    z[2] = 0.0f;
+    if (dim == 3) {
+        const float r1 = sqrtf(-2.0f * orc_ln32(1.0f - a[2]));
+        orc_sincos32(a[3], &sn, &cs);
+        z[2] = r1 * cs;
+    }
+}
+
+/* n blocks at once (tests): w[4n] -> z[3n] */
+void orc_normals32_n(const uint32_t* w, int64_t n, int32_t dim, float* z) {
+    for (int64_t i = 0; i < n; ++i) orc_normals32(w + 4 * i, dim, z + 3 * i);
+}
+
+/* d binary32 normals of one stream element (block 0), widened */
+static void rng_normals32(const orc_params* p, uint32_t elem, uint32_t t, uint32_t sub, uint32_t purpose,
+                          double z[3]) {
+    uint32_t w[4];
+    float zf[3];
+    rng_block(p, elem, t, sub, purpose, 0, w);
+    orc_normals32(w, p->dim, zf);
+    for (int k = 0; k < 3; ++k) z[k] = (double)zf[k];
+}
+
 /* d standard normals of one stream element from the Philox blocks blk and
  * blk + 1 */
 static void rng_normals_at(const orc_params* p, uint32_t elem, uint32_t t, uint32_t sub,
@@ -817,6 +915,8 @@ static void reinject_one(const orc_state* s, uint32_t id, uint32_t t, uint32_t s
     double z[3];
     if (p->reinject && T)
         orc_ce_normals(p, id, t, sub, T, z);
+    else if (p->part_fp32)
+        rng_normals32(p, id, t, sub, P_REINJ, z);
     else
         rng_normals(p, id, t, sub, P_REINJ, z);
     for (int d = 0; d < p->dim; ++d) v[d] = st(s, u[d] + sd * z[d]);
@@ -1037,13 +1137,17 @@ static void collide_one(const orc_state* s, int32_t c, uint32_t t, uint32_t sub,
     if (p->collision == 1) {
         /* MPCD-AT: one Gaussian velocity per particle (READING: variance
          * kT/m per component, as for the exchange step), keyed by the
-         * particle's id and the collision's MPCD step; stored in the
-         * particle precision before use */
+         * particle's id and the collision's MPCD step, drawn in binary32 for
+         * binary32 particles (READING above); stored in the particle
+         * precision before use */
         double* vr = (double*)malloc(sizeof(double) * 3 * (size_t)n);
         const double sd = sqrt(p->kT / p->mass);
         for (int i = 0; i < n; ++i) {
             double z[3];
-            rng_normals(p, (uint32_t)ids[i], t, sub, P_AT, z);
+            if (p->part_fp32)
+                rng_normals32(p, (uint32_t)ids[i], t, sub, P_AT, z);
+            else
+                rng_normals(p, (uint32_t)ids[i], t, sub, P_AT, z);
             for (int k = 0; k < d; ++k) vr[k * n + i] = st(s, sd * z[k]);
         }
         double vc[3] = {0.0, 0.0, 0.0};

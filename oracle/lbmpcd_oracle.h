@@ -141,6 +141,12 @@ void orc_feq(int32_t dim, double rho, const double u[3], double* feq);
 void orc_collide_node(int32_t dim, double tau, const double g[3], double* f);
 /* Box-Muller pair from two uniforms */
 void orc_box_muller(double u0, double u1, double* z0, double* z1);
+/* binary32 normals of binary32 particles: ln on (0, 1], sin/cos of 2 pi u,
+ * the normals of one Philox block (z[2] = 0 in 2D), and n blocks at once */
+float orc_ln32(float x);
+void orc_sincos32(float u, float* sn, float* cs);
+void orc_normals32(const uint32_t w[4], int32_t dim, float z[3]);
+void orc_normals32_n(const uint32_t* w, int64_t n, int32_t dim, float* z);
 /* SRD rotation of n velocities (vel[d][n]) about their centre of mass */
 void orc_srd_rotate(int32_t dim, int32_t n, double* vel, double cos_a, double sin_a,
                     double sign2d, const double axis[3], const double p_virt[3], double m_virt,

@@ -85,6 +85,11 @@ def lib():
         L.orc_feq.argtypes = [C.c_int32, C.c_double, P, P]
         L.orc_collide_node.argtypes = [C.c_int32, C.c_double, P, P]
         L.orc_box_muller.argtypes = [C.c_double, C.c_double, P, P]
+        L.orc_ln32.argtypes = [C.c_float]
+        L.orc_ln32.restype = C.c_float
+        L.orc_sincos32.argtypes = [C.c_float, P, P]
+        L.orc_normals32.argtypes = [P, C.c_int32, P]
+        L.orc_normals32_n.argtypes = [P, C.c_int64, C.c_int32, P]
         L.orc_srd_rotate.argtypes = [C.c_int32, C.c_int32, P, C.c_double, C.c_double,
                                      C.c_double, P, P, C.c_double, P]
         L.orc_counting_sort.argtypes = [C.c_int32, P, C.c_int32, P, P, P]
@@ -322,6 +327,31 @@ def box_muller(u0: float, u1: float):
     z1 = np.zeros(1)
     lib().orc_box_muller(float(u0), float(u1), _ptr(z0), _ptr(z1))
     return float(z0[0]), float(z1[0])
+
+
+def ln32(x) -> np.ndarray:
+    """The binary32 ln on (0, 1] of the binary32 normals, elementwise."""
+    x = np.atleast_1d(np.asarray(x, np.float32))
+    return np.array([lib().orc_ln32(float(v)) for v in x], np.float32)
+
+
+def sincos32(u):
+    """The binary32 sin and cos of 2 pi u, elementwise: (sin, cos)."""
+    u = np.atleast_1d(np.asarray(u, np.float32))
+    sn, cs = np.zeros(1, np.float32), np.zeros(1, np.float32)
+    out = np.empty((2, u.size), np.float32)
+    for i, v in enumerate(u):
+        lib().orc_sincos32(float(v), _ptr(sn), _ptr(cs))
+        out[0, i], out[1, i] = sn[0], cs[0]
+    return out[0], out[1]
+
+
+def normals32(w, dim: int = 3) -> np.ndarray:
+    """The binary32 normals of Philox blocks w [n][4]: [n][3] (z2 = 0 in 2D)."""
+    w = np.ascontiguousarray(np.asarray(w, np.uint32).reshape(-1, 4))
+    z = np.empty((w.shape[0], 3), np.float32)
+    lib().orc_normals32_n(_ptr(w), int(w.shape[0]), int(dim), _ptr(z))
+    return z
 
 
 def srd_rotate(dim, vel, alpha_deg, sign2d=1.0, axis=(0.0, 0.0, 1.0), p_virt=(0, 0, 0), m_virt=0.0):
