@@ -154,6 +154,28 @@ __device__ __forceinline__ void rng_normals(Key k, uint32_t elem, uint32_t t, ui
     }
 }
 
+// DIM binary32 standard normals of one element, for particles stored in
+// binary32: block 0 of the element's stream gives four 24-bit uniforms
+// a_k = (w_k >> 8) 2^-24; Box-Muller pairs (a0, a1), (a2, a3) with radius
+// sqrt(-2 ln(1 - a_even)) and angle 2 pi a_odd; the third 3D component is the
+// cosine of the second pair.  Binary32 throughout (fmath.hpp).
+template <int DIM>
+__device__ __forceinline__ void rng_normals32(Key k, uint32_t elem, uint32_t t, uint32_t sub,
+                                              uint32_t purpose, float z[3]) {
+    const U4 w = rng_block(k, elem, t, sub, purpose, 0);
+    float s, c;
+    const float r0 = sqrtf(-2.0f * ln_unit32(1.0f - (float)(w.x >> 8) * 0x1p-24f));
+    sincos_2pi32((float)(w.y >> 8) * 0x1p-24f, &s, &c);
+    z[0] = r0 * c;
+    z[1] = r0 * s;
+    z[2] = 0.0f;
+    if constexpr (DIM == 3) {
+        const float r1 = sqrtf(-2.0f * ln_unit32(1.0f - (float)(w.z >> 8) * 0x1p-24f));
+        sincos_2pi32((float)(w.w >> 8) * 0x1p-24f, &s, &c);
+        z[2] = r1 * c;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Lattices: D2Q9 and D3Q19 with the textbook weights (c_s^2 = 1/3).
 // ---------------------------------------------------------------------------

@@ -14,6 +14,16 @@
 //     the quadrant q mod 4 swaps and negates them.
 // Both are accurate to a few units in the last place, which is what the FP64
 // path needs (the C library's versions differ from each other by as much).
+//
+// The binary32 pair (for particles stored in binary32) follows a fixed
+// definition, every step one IEEE binary32 operation, so that it is bit-exact
+// wherever it is evaluated:
+//   ln x, x in (0, 1]:  m in [sqrt(1/2), sqrt(2)) as above; 2 atanh s summed as
+//     2 s (1 + z/3 + z^2/5 + z^3/7 + z^4/9), z = s^2 (first omitted term below
+//     2e-9 of the sum); ln 2 and sqrt(1/2) rounded to binary32.
+//   sin and cos of 2 pi u:  the same quadrant reduction with pi/2 rounded to
+//     binary32; sin y to y^9/9!, cos y to y^8/8! (first omitted terms below
+//     2e-9 and 2.5e-8 for |y| <= pi/4).
 #pragma once
 
 #include <math.h>
@@ -78,6 +88,47 @@ LBMPCD_HD void sincos_2pi(double u, double* sn, double* cs) {
     const int qm = (int)q & 3;
     const double a = (qm & 1) ? C : S;  // sin of the angle up to sign
     const double b = (qm & 1) ? S : C;  // cos of the angle up to sign
+    *sn = (qm & 2) ? -a : a;
+    *cs = (qm == 1 || qm == 2) ? -b : b;
+}
+
+LBMPCD_HD float ln_unit32(float x) {
+    int e;
+    float m = frexpf(x, &e);  // x = m 2^e, m in [1/2, 1)
+    if (m < 0x1.6a09e6p-1f) {  // sqrt(1/2) in binary32
+        m = m + m;
+        e -= 1;
+    }
+    const float f = m - 1.0f;  // exact
+    const float s = f / (2.0f + f);
+    const float z = s * s;
+    float p = 1.0f / 9.0f;
+    p = fmaf(p, z, 1.0f / 7.0f);
+    p = fmaf(p, z, 1.0f / 5.0f);
+    p = fmaf(p, z, 1.0f / 3.0f);
+    const float two_s = s + s;
+    const float lm = fmaf(two_s * z, p, two_s);
+    return fmaf((float)e, 0x1.62e430p-1f, lm);  // ln 2 in binary32
+}
+
+LBMPCD_HD void sincos_2pi32(float u, float* sn, float* cs) {
+    const float t = 4.0f * u;
+    const float q = rintf(t);
+    const float y = (t - q) * 0x1.921fb6p+0f;  // pi/2 in binary32; t - q is exact
+    const float z = y * y;
+    float ps = 1.0f / 362880.0f;       // 1/9!
+    ps = fmaf(ps, z, -1.0f / 5040.0f);  // -1/7!
+    ps = fmaf(ps, z, 1.0f / 120.0f);    // 1/5!
+    ps = fmaf(ps, z, -1.0f / 6.0f);     // -1/3!
+    const float S = fmaf(ps * z, y, y);
+    float pc = 1.0f / 40320.0f;         // 1/8!
+    pc = fmaf(pc, z, -1.0f / 720.0f);   // -1/6!
+    pc = fmaf(pc, z, 1.0f / 24.0f);     // 1/4!
+    pc = fmaf(pc, z, -0.5f);            // -1/2!
+    const float C = fmaf(pc, z, 1.0f);
+    const int qm = (int)q & 3;
+    const float a = (qm & 1) ? C : S;
+    const float b = (qm & 1) ? S : C;
     *sn = (qm & 2) ? -a : a;
     *cs = (qm == 1 || qm == 2) ? -b : b;
 }

@@ -318,8 +318,9 @@ k_particles(PArgs<PT> A) {
         const PT sh[3] = {(PT)shc[0], (PT)shc[1], (PT)shc[2]};
         int lc[PPT];
         // MPCD-AT: each particle's random velocity (variance kT/m per
-        // component, keyed by its id and the collision's MPCD step), kept in
-        // the particle precision between the two passes over the cell
+        // component, keyed by its id and the collision's MPCD step; binary32
+        // normals for binary32 particles), kept in the particle precision
+        // between the two passes over the cell
         [[maybe_unused]] PT vr[AT ? PPT : 1][3];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -346,7 +347,14 @@ k_particles(PArgs<PT> A) {
             for (int q = 0; q < DIM; ++q) lds_add(&csv[3 * c + q], (double)pv[k][q]);
             if constexpr (AT) {
                 double z[3];
-                rng_normals<DIM>(key, pid[k], tc, sc, P_AT, z);
+                if constexpr (sizeof(PT) == 4) {
+                    float zf[3];
+                    rng_normals32<DIM>(key, pid[k], tc, sc, P_AT, zf);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) z[q] = (double)zf[q];
+                } else {
+                    rng_normals<DIM>(key, pid[k], tc, sc, P_AT, z);
+                }
 #pragma unroll
                 for (int q = 0; q < DIM; ++q) {
                     vr[k][q] = (PT)(d.sd * z[q]);
@@ -501,9 +509,18 @@ k_particles(PArgs<PT> A) {
                 const int Jb = (J0 < rb_lo) ? J0 : J0 - (d.R - d.NB);
                 const long long fc = ((long long)K * d.NB + Jb) * d.Cx + I;
                 double z[3];
-                reinject_normals<DIM>(key, pid[k], ts, ss, z);
-                if constexpr (CE) {
-                    if (ce_on) ce_redraw<DIM>(key, pid[k], ts, ss, tfl, NF, fc, z);
+                if (sizeof(PT) == 4 && !(CE && ce_on)) {
+                    // binary32 particles draw binary32 normals (one Philox
+                    // block); the Chapman-Enskog draws stay binary64
+                    float zf[3];
+                    rng_normals32<DIM>(key, pid[k], ts, ss, P_REINJ, zf);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) z[q] = (double)zf[q];
+                } else {
+                    reinject_normals<DIM>(key, pid[k], ts, ss, z);
+                    if constexpr (CE) {
+                        if (ce_on) ce_redraw<DIM>(key, pid[k], ts, ss, tfl, NF, fc, z);
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < DIM; ++q) pv[k][q] = (PT)(uf[q * NF + fc] + d.sd * z[q]);
