@@ -28,29 +28,59 @@ __device__ __forceinline__ void equilibrium_guo(const double* f, double omega, d
                                                 double* fs) {
     using L = Lat<DIM>;
     constexpr int Q = L::Q;
-    double rho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+    // Moments.  Lattice components are 0 or +-1: only the nonzero ones enter
+    // a sum, as additions or subtractions (the dropped products are zeros,
+    // which would leave every sum unchanged).
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         rho += f[i];
-        j0 += f[i] * (double)L::cx[i];
-        j1 += f[i] * (double)L::cy[i];
-        j2 += f[i] * (double)L::cz[i];
+        const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (c[k] > 0) j[k] += f[i];
+            if (c[k] < 0) j[k] -= f[i];
+        }
     }
     const double inv = 1.0 / rho;
-    double u0 = j0 * inv + 0.5 * g[0];
-    double u1 = j1 * inv + 0.5 * g[1];
-    double u2 = j2 * inv + 0.5 * g[2];
-    double F0 = rho * g[0], F1 = rho * g[1], F2 = rho * g[2];
-    double uu = u0 * u0 + u1 * u1 + u2 * u2;
+    const double u[3] = {j[0] * inv + 0.5 * g[0], j[1] * inv + 0.5 * g[1], j[2] * inv + 0.5 * g[2]};
+    const double F[3] = {rho * g[0], rho * g[1], rho * g[2]};
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double uu15 = 1.5 * uu;
+    // Guo forcing (3 (c_k - u_k) + 9 (c.u) c_k) F_k per component: the
+    // c_k = 0 terms are the same for every direction, and 3 (c_k - u_k) takes
+    // two values for c_k = +-1
+    double T0[3], Ap[3], Am[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T0[k] = (3.0 * (0.0 - u[k])) * F[k];
+        Ap[k] = 3.0 * (1.0 - u[k]);
+        Am[k] = 3.0 * (-1.0 - u[k]);
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double c0 = L::cx[i], c1 = L::cy[i], c2 = L::cz[i];
-        double cu = c0 * u0 + c1 * u1 + c2 * u2;
-        double feq = L::w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
+        // c.u over the nonzero components, in component order
+        double cu = 0.0;
+        bool first = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (c[k] == 0) continue;
+            const double t = c[k] > 0 ? u[k] : -u[k];
+            cu = first ? t : cu + t;
+            first = false;
+        }
+        const double feq = (L::w[i] * rho) * (((1.0 + 3.0 * cu) + (4.5 * cu) * cu) - uu15);
+        const double cu9 = 9.0 * cu;
         double Fi = 0.0;
-        Fi += (3.0 * (c0 - u0) + 9.0 * cu * c0) * F0;
-        Fi += (3.0 * (c1 - u1) + 9.0 * cu * c1) * F1;
-        Fi += (3.0 * (c2 - u2) + 9.0 * cu * c2) * F2;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double t;
+            if (c[k] == 0) t = T0[k];
+            else if (c[k] > 0) t = (Ap[k] + cu9) * F[k];
+            else t = (Am[k] - cu9) * F[k];
+            Fi += t;
+        }
         Fi *= L::w[i];
         fs[i] = f[i] - omega * (f[i] - feq) + src * Fi;
     }
