@@ -210,6 +210,48 @@ def cpu_baseline(workload: str, seconds: float = 12.0) -> dict:
                 lb_mlups=lbn / 1e6, lb_mlups_one_core=lb1 / 1e6, host=host_description())
 
 
+def instance_profiles(sim, plist: list, steps: int, path: str | None) -> dict:
+    """Time-averaged profiles of every channel of a batched context, after
+    the timed region: `steps` sampled LB steps, then per channel the MPCD
+    streamwise velocity of each interior slab row (the fine rows of an LB row
+    pooled), the LB velocity of the same rows (mean over x) and the one-way
+    Poiseuille parabola g y (H - y) / (2 nu) at the rows' centres.  The line
+    carries the relative L2 difference of the MPCD profile from each, per
+    channel (median, 90th percentile, largest); `path`, when given, receives
+    every profile.  Narrow channels are dominated by thermal noise (a 16-row
+    channel at g = 1e-6 peaks at 2e-4); the widest carries the flow."""
+    import numpy as np
+    sim.sample(1)
+    sim.step(steps)
+    sim.sync()
+    devs, devp, rows = [], [], []
+    for i, p in enumerate(plist):
+        r, nsy = p["refine"], p["yhi"] - p["ylo"]
+        prof = np.asarray(sim.profile(i)).reshape(nsy, r, 4).sum(axis=1)
+        ys = range(p["buf_lo"], nsy - p["buf_hi"])
+        u_m = np.array([prof[y, 1] / prof[y, 0] for y in ys])
+        _, u, _ = sim.fields(i)
+        u_lb = np.array([u[0, 0, p["ylo"] + y, :].mean() for y in ys])
+        nu = (p["tau"] - 0.5) / 3.0
+        yc = np.array([p["ylo"] + y + 0.5 for y in ys])
+        u_par = p["g"][0] * yc * (p["n"][1] - yc) / (2.0 * nu)
+        devs.append(float(np.linalg.norm(u_m - u_lb) / np.linalg.norm(u_lb)))
+        devp.append(float(np.linalg.norm(u_m - u_par) / np.linalg.norm(u_par)))
+        rows.append({"channel": i, "n": list(p["n"][:2]), "slab": [p["ylo"], p["yhi"]],
+                     "mpcd_u": [round(float(x), 8) for x in u_m], "lb_u": [round(float(x), 8) for x in u_lb],
+                     "parabola_u": [round(float(x), 8) for x in u_par]})
+    sim.sample(0)
+    if path:
+        with open(path, "w") as fo:
+            json.dump({"sampled_lb_steps": steps, "channels": rows}, fo)
+    def summary(v):
+        d = sorted(v)
+        return {"median": d[len(d) // 2], "p90": d[int(0.9 * (len(d) - 1))], "max": d[-1]}
+    return {"sampled_lb_steps": steps, "channels": len(plist),
+            "rel_l2_mpcd_vs_lb": summary(devs), "rel_l2_mpcd_vs_parabola": summary(devp),
+            "widest_channel": rows[int(np.argmax([q["n"][1] for q in plist]))], "file": path}
+
+
 def one_by_one(lbmpcd, plist: list, batched_ms: float, sample: int = 16, steps: int = 8) -> dict:
     """The same channels advanced one context at a time (each alone on the
     GPU), for every len(plist)/sample-th channel; the summed time per coupled
@@ -458,6 +500,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape for the ensemble too")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=1000,
+                    help="batched workloads: LB steps sampled after the timed region for per-channel profiles")
+    ap.add_argument("--profiles-out", default=None, help="batched workloads: file for every channel's profile")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="write the workload's particle-kernel PMC summary from two rocprofv3 runs and exit")
@@ -593,6 +638,7 @@ def main():
         "cpu_baseline": cpu,
     }
     if len(plist) > 1:
+        out["per_instance_profiles"] = instance_profiles(sim, plist, args.profile_steps, args.profiles_out)
         del sim
         torch.cuda.empty_cache()
         out["batched_vs_one_by_one"] = one_by_one(lbmpcd, plist, ms_per_step)
