@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define LBMPCD_ABI_VERSION 5u
+#define LBMPCD_ABI_VERSION 6u
 
 enum lbmpcd_status {
     LBMPCD_OK = 0,
@@ -182,6 +182,15 @@ typedef struct lbmpcd_params {
                               holds a few hundred particles, whose mean carries thermal
                               noise of the size of the flow (the paper averages its
                               MPCD profiles over many samples, Sec. 3.1). */
+    int32_t deterministic; /* 1: two runs of the same parameters give identical bits.  The
+                              particle kernel's sums (cell velocity sums, the MPCD-AT sums,
+                              the sample windows and node and profile sums) become 64-bit
+                              integer sums of the values in units of 2^-40, which do not
+                              depend on the order the atomics land in; the ordinary FP64
+                              sums do, at the level of their last bits.  Results differ
+                              from the FP64 sums by at most 2^-41 per summed value.  All
+                              instances of a context share it; not with the closure or
+                              the Chapman-Enskog exchange.  0: FP64 sums. */
 } lbmpcd_params;
 
 /*

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbmpcd.so")
-SOURCES = ["api.hip", "kernels_lb.hip", "kernels_mpcd.hip", "kernels_mpcd_ce.hip", "kernels_util.hip", "kernels_mlp.hip"]
+SOURCES = ["api.hip", "kernels_lb.hip", "kernels_mpcd.hip", "kernels_mpcd_ce.hip", "kernels_mpcd_det.hip",
+           "kernels_util.hip", "kernels_mlp.hip"]
 ARCH = os.environ.get("LBMPCD_ARCH", "gfx950")
 
 FLAGS = [

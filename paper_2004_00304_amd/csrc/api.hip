@@ -61,6 +61,7 @@ struct lbmpcd_ctx {
     int wg_threads = 0;           // particle kernel workgroup size
     int coll_bit = 0;             // 4 for the MPCD-AT collision (particle kernel mode bit)
     int ce_bit = 0;               // 8 for the Chapman-Enskog exchange (particle kernel mode bit)
+    int det_bit = 0;              // 16 for the deterministic mode (particle kernel mode bit)
     int xcd_blocked = 1;          // XCD-blocked tile order of the particle kernel
     long long cstride = 0;        // bytes between the component arrays of a particle buffer
     long long t = 0;
@@ -267,6 +268,11 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     if (p.reinject != 0 && p.reinject != 1) { msg = "reinject must be 0 or 1"; return LBMPCD_E_INVALID; }
     if (!std::isfinite(p.ce_nu)) { msg = "ce_nu must be finite"; return LBMPCD_E_INVALID; }
     if (p.fb_window < 0) { msg = "fb_window must be >= 0"; return LBMPCD_E_INVALID; }
+    if (p.deterministic != 0 && p.deterministic != 1) { msg = "deterministic must be 0 or 1"; return LBMPCD_E_INVALID; }
+    if (p.deterministic && p.mpcd && (p.closure || p.reinject)) {
+        msg = "the deterministic mode covers neither the closure nor the Chapman-Enskog exchange";
+        return LBMPCD_E_UNSUPPORTED;
+    }
     if (p.reinject && !(p.kT > 0.0)) { msg = "the Chapman-Enskog exchange needs kT > 0"; return LBMPCD_E_INVALID; }
     const bool ywrap = !p.walls_y && p.ylo == 0 && p.yhi == p.n[1] && p.buf_lo == 0 && p.buf_hi == 0;
     if (!p.walls_y && !ywrap && (p.ylo < 1 || p.yhi > p.n[1] - 1)) {
@@ -356,6 +362,7 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
         d.key1 = (uint32_t)(q.seed >> 32) ^ q.instance;
         d.S = q.mpcd ? q.substeps : 0;
         d.ce = (q.mpcd && q.reinject) ? 1 : 0;
+        d.det = q.deterministic ? 1 : 0;
         d.ce_scale = d.ce ? ce_nu(q) * q.mass / q.kT / (2.0 * q.tau / 3.0) : 0.0;
         d.fb_lam = 1.0 / (double)(q.fb_window > 0 ? q.fb_window : FB_WINDOW_DEFAULT);
         node += d.N;
@@ -430,8 +437,9 @@ int validate_all(const lbmpcd_params* p, int n, std::string& msg) {
             return LBMPCD_E_INVALID;
         }
         if (p[i].wg_threads != p[0].wg_threads || p[i].collision != p[0].collision ||
-            (p[0].mpcd && p[i].reinject != p[0].reinject)) {
-            msg = "all instances must share wg_threads, the collision rule and the exchange rule";
+            (p[0].mpcd && p[i].reinject != p[0].reinject) || p[i].deterministic != p[0].deterministic) {
+            msg = "all instances must share wg_threads, the collision rule, the exchange rule and the "
+                  "deterministic mode";
             return LBMPCD_E_INVALID;
         }
         if (p[i].closure && n != 1) {
@@ -486,7 +494,7 @@ hipError_t timed(lbmpcd_ctx* c, int cls, F f) {
 int finalize(lbmpcd_ctx* c) {
     if (!c->pending || !c->mpcd) return 0;
     ParticleLaunch L{};
-    L.dim = c->dim; L.part_fp = c->part_fp; L.mode = 1 | c->coll_bit;
+    L.dim = c->dim; L.part_fp = c->part_fp; L.mode = 1 | c->coll_bit | c->det_bit;
     L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
     L.in = c->part[c->pcur]; L.out = c->part[c->pcur];
     L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
@@ -662,6 +670,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     c->wg_threads = p[0].wg_threads ? p[0].wg_threads : (c->part_fp == 64 && cap_max > 4 * 256 ? 512 : 256);
     c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max);
     c->coll_bit = p[0].collision == 1 ? 4 : 0;
+    c->det_bit = (p[0].mpcd && p[0].deterministic) ? 16 : 0;
 
     // tile -> instance table
     std::vector<int> tinst((size_t)std::max<long long>(c->total_tiles, 1));
@@ -759,7 +768,7 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
             for (int sub = 0; sub < c->S; ++sub) {
                 ParticleLaunch L{};
                 L.dim = c->dim; L.part_fp = c->part_fp;
-                L.mode = ((sub == 0 && !c->pending) ? 2 : (3 | c->coll_bit)) | c->ce_bit;
+                L.mode = ((sub == 0 && !c->pending) ? 2 : (3 | c->coll_bit)) | c->ce_bit | c->det_bit;
                 L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
                 L.in = c->part[c->pcur]; L.out = c->part[c->pcur ^ 1];
                 L.fill_in = c->fill[c->pcur]; L.fill_out = c->fill[c->pcur ^ 1];
@@ -928,7 +937,7 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             return 0;
         case LBMPCD_NODE_MPCD_U:
             if (!d.feedback) return fail(c, LBMPCD_E_STATE, "node sample averages are kept only with feedback 1");
-            HIPCHK(c, launch_node_mean(c->acc + d.acc_off * 4, d.nslab, c->dim, (double*)dst, s));
+            HIPCHK(c, launch_node_mean(c->acc + d.acc_off * 4, d.nslab, c->dim, d.det, (double*)dst, s));
             return 0;
         case LBMPCD_NODE_FB_U:
             if (!d.feedback) return fail(c, LBMPCD_E_STATE, "the feedback's running mean exists only with feedback 1");
@@ -940,7 +949,7 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             if (!c->pending) return fail(c, LBMPCD_E_STATE, "cell velocities exist only right after lbmpcd_step");
             HIPCHK(c, launch_zero(dst, nbytes, s));
             ParticleLaunch L{};
-            L.dim = c->dim; L.part_fp = c->part_fp; L.mode = 1 | c->coll_bit;
+            L.dim = c->dim; L.part_fp = c->part_fp; L.mode = 1 | c->coll_bit | c->det_bit;
             L.D = c->d_desc; L.n_inst = c->n_inst; L.tiles = c->total_tiles;
             // the pending collision is evaluated into the idle particle buffer, so
             // the state (and the other instances' pending collisions) is untouched

@@ -64,10 +64,25 @@ struct InstDesc {
     uint32_t key0, key1;
     int S, pad2;          // MPCD steps per LB step
     // Chapman-Enskog exchange: T = ce_scale dev(-Pi_neq) / rho at the band nodes
-    int ce, pad3;         // 1: Chapman-Enskog draws in this instance's buffers
+    int ce;               // 1: Chapman-Enskog draws in this instance's buffers
+    int det;              // 1: the sample sums (acc, prof) hold fixed-point integers (to_fix below)
     double ce_scale;      // nu_x m / kT / (2 cs2 tau), nu_x the exchange's stress coefficient
     double fb_lam;        // feedback: weight of an LB step's node sample in the running mean (1/fb_window)
 };
+
+// Deterministic sums: a value v enters a sum as the 64-bit integer
+// round(v 2^40) (ties to even), and the integer sums, which do not depend on
+// the order of the atomic additions, are read back as q 2^-40.  Exact for the
+// count (1 -> 2^40); 2^-41 at most per value otherwise; sums must stay below
+// 2^23 in magnitude (velocities of a valid state are far below).
+constexpr double FIX_ONE = 1099511627776.0;  // 2^40
+__device__ __forceinline__ unsigned long long to_fix(double v) {
+    return (unsigned long long)__double2ll_rn(v * FIX_ONE);
+}
+__device__ __forceinline__ double from_fix(unsigned long long q) { return (double)(long long)q * (1.0 / FIX_ONE); }
+__device__ __forceinline__ double fix_bits(const double* p) {  // a fixed-point sum stored in a double slot
+    return from_fix(*(const unsigned long long*)p);
+}
 
 // Components of the Chapman-Enskog tensor per band node / buffer cell
 // (xx, yy, zz, xy, xz, yz; the z ones are zero in 2D).

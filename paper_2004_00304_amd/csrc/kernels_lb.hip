@@ -218,7 +218,9 @@ __global__ void __launch_bounds__(WG) k_band(const InstDesc* __restrict__ D, int
     if (do_feedback && y >= d.ylo && y < d.yhi) {
         long long s = ((long long)z * (d.yhi - d.ylo) + (y - d.ylo)) * nx + x;
         double* a = acc + (d.acc_off + s) * 4;
-        double cnt = a[0], s0 = a[1], s1 = a[2], s2 = a[3];
+        // fixed-point sums in the deterministic mode
+        const double cnt = d.det ? fix_bits(a) : a[0], s0 = d.det ? fix_bits(a + 1) : a[1];
+        const double s1 = d.det ? fix_bits(a + 2) : a[2], s2 = d.det ? fix_bits(a + 3) : a[3];
         a[0] = 0.0; a[1] = 0.0; a[2] = 0.0; a[3] = 0.0;
         if (d.feedback && y >= d.ylo + d.buf_lo && y < d.yhi - d.buf_hi && cnt > 0.0) {
             double rho = 0.0;

@@ -24,6 +24,7 @@ struct PlainModes {
 }  // namespace
 
 hipError_t launch_particles(const ParticleLaunch& L, hipStream_t s) {
+    if (L.mode & 16) return launch_particles_det(L, s);
     if (L.mode & 8) return launch_particles_ce(L, s);
     return launch_modes<PlainModes>(L, s);
 }

@@ -170,7 +170,10 @@ __global__ void __launch_bounds__(WG) k_profile_reduce(const InstDesc* __restric
     if (i >= d.R * 4) return;
     const int J = i / 4, q = i % 4;
     double s = 0.0;
-    for (int c = 0; c < NCOPY; ++c) s += prof[(d.prof_off + (long long)c * d.R + J) * 4 + q];
+    for (int c = 0; c < NCOPY; ++c) {
+        const double* v = &prof[(d.prof_off + (long long)c * d.R + J) * 4 + q];
+        s += d.det ? fix_bits(v) : *v;  // fixed-point sums in the deterministic mode
+    }
     out[i] = s;
 }
 
@@ -274,16 +277,19 @@ hipError_t launch_exclusive_scan(int* a, long long n, hipStream_t s) {
 
 // Mean particle velocity per slab node from the per-node sample sums
 // [count, sum v_x, sum v_y, sum v_z]: out[q][node], zero where no particle.
-__global__ void __launch_bounds__(WG) k_node_mean(const double* acc, long long nslab, int dim, double* out) {
+__global__ void __launch_bounds__(WG) k_node_mean(const double* acc, long long nslab, int dim, int det,
+                                                  double* out) {
     const long long i = (long long)blockIdx.x * WG + threadIdx.x;
     if (i >= nslab) return;
     const double* a = acc + 4 * i;
-    for (int q = 0; q < dim; ++q) out[(long long)q * nslab + i] = a[0] > 0.0 ? a[1 + q] / a[0] : 0.0;
+    double v[4];
+    for (int q = 0; q < 4; ++q) v[q] = det ? fix_bits(a + q) : a[q];  // fixed point in the deterministic mode
+    for (int q = 0; q < dim; ++q) out[(long long)q * nslab + i] = v[0] > 0.0 ? v[1 + q] / v[0] : 0.0;
 }
 
-hipError_t launch_node_mean(const double* acc, long long nslab, int dim, double* out, hipStream_t s) {
+hipError_t launch_node_mean(const double* acc, long long nslab, int dim, int det, double* out, hipStream_t s) {
     if (nslab <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_node_mean, dim3(nblk(nslab)), dim3(WG), 0, s, acc, nslab, dim, out);
+    hipLaunchKernelGGL(k_node_mean, dim3(nblk(nslab)), dim3(WG), 0, s, acc, nslab, dim, det, out);
     return hipGetLastError();
 }
 

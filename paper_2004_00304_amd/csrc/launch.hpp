@@ -42,7 +42,8 @@ inline PartPtrs<PT> typed(const PartBuf& b) {
 
 struct ParticleLaunch {
     int dim, part_fp, mode;       // mode bit 0: collide, bit 1: stream, bit 2: MPCD-AT instead of SRD,
-                                  // bit 3: Chapman-Enskog exchange (with streaming)
+                                  // bit 3: Chapman-Enskog exchange (with streaming), bit 4:
+                                  // deterministic (fixed-point integer sums)
     const InstDesc* D;
     int n_inst;
     long long tiles;              // workgroups (tiles of all instances)
@@ -85,7 +86,7 @@ hipError_t launch_set_field(int dim, int part_fp, const InstDesc* D, int inst, P
                             int which, const double* src, long long slots, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_exclusive_scan(int* a, long long n, hipStream_t s);
-hipError_t launch_node_mean(const double* acc, long long nslab, int dim, double* out, hipStream_t s);
+hipError_t launch_node_mean(const double* acc, long long nslab, int dim, int det, double* out, hipStream_t s);
 hipError_t launch_profile_reduce(const InstDesc* D, int inst, int R, const double* prof, double* out,
                                  hipStream_t s);
 

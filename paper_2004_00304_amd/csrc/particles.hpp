@@ -177,6 +177,24 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
 }
 __device__ __forceinline__ void gl_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
+// A sum in LDS or global memory: FP64 atomics, or with DET (deterministic
+// mode) fixed-point integer atomics in the same 8-byte slot (to_fix).
+template <bool DET>
+__device__ __forceinline__ void sum_lds(double* p, double v) {
+    if constexpr (DET) atomicAdd((unsigned long long*)p, to_fix(v));
+    else lds_add(p, v);
+}
+template <bool DET>
+__device__ __forceinline__ void sum_gl(double* p, double v) {
+    if constexpr (DET) atomicAdd((unsigned long long*)p, to_fix(v));
+    else gl_add(p, v);
+}
+template <bool DET>
+__device__ __forceinline__ double sum_read(const double* p) {
+    if constexpr (DET) return fix_bits(p);
+    else return *p;
+}
+
 // LDS carve-up (bytes): header (counters and the table of destination tiles),
 // sample windows, collision arrays.
 constexpr int NHASH_BITS = 6;
@@ -210,6 +228,7 @@ k_particles(PArgs<PT> A) {
     constexpr bool STREAM = (MODE & 2) != 0;
     constexpr bool AT = (MODE & 4) != 0;  // MPCD-AT collision (Eq. 6) instead of SRD (Eq. 4)
     constexpr bool CE = (MODE & 8) != 0;  // Chapman-Enskog exchange instead of Maxwell-Boltzmann
+    constexpr bool DET = (MODE & 16) != 0;  // deterministic: fixed-point integer sums
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* wstat = (uint32_t*)smem;          // [4] far moves, misplaced, samples outside the LDS windows,
                                                 // invalid particles
@@ -344,7 +363,7 @@ k_particles(PArgs<PT> A) {
             lc[k] = c;
             atomicAdd(&ccnt[c], 1u);
 #pragma unroll
-            for (int q = 0; q < DIM; ++q) lds_add(&csv[3 * c + q], (double)pv[k][q]);
+            for (int q = 0; q < DIM; ++q) sum_lds<DET>(&csv[3 * c + q], (double)pv[k][q]);
             if constexpr (AT) {
                 double z[3];
                 if constexpr (sizeof(PT) == 4) {
@@ -358,7 +377,7 @@ k_particles(PArgs<PT> A) {
 #pragma unroll
                 for (int q = 0; q < DIM; ++q) {
                     vr[k][q] = (PT)(d.sd * z[q]);
-                    lds_add(&crot[3 * c + q], (double)vr[k][q]);
+                    sum_lds<DET>(&crot[3 * c + q], (double)vr[k][q]);
                 }
             }
         }
@@ -386,11 +405,11 @@ k_particles(PArgs<PT> A) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) cvcm[3 * j + q] = 0.0;
 #pragma unroll
-            for (int q = 0; q < DIM; ++q) cvcm[3 * j + q] = (csv[3 * j + q] + pvv[q]) / ((double)nc + mv);
+            for (int q = 0; q < DIM; ++q) cvcm[3 * j + q] = (sum_read<DET>(&csv[3 * j + q]) + pvv[q]) / ((double)nc + mv);
             if constexpr (AT) {
                 // mean random velocity over the cell's real particles
 #pragma unroll
-                for (int q = 0; q < DIM; ++q) crot[3 * j + q] = crot[3 * j + q] / (double)nc;
+                for (int q = 0; q < DIM; ++q) crot[3 * j + q] = sum_read<DET>(&crot[3 * j + q]) / (double)nc;
             }
             if (A.cell_vcm && ii == A.diag_inst) {
 #pragma unroll
@@ -617,12 +636,12 @@ k_particles(PArgs<PT> A) {
                     if (win_ok && ax < wnx && ay >= 0 && ay < wny && az < wnz) {
                         double* wb = wacc + 4 * NREP * (ax + wnx * (ay + wny * az)) + wrep;
 #pragma unroll
-                        for (int q = 0; q < DIM + 1; ++q) lds_add(&wb[q], vals[q]);
+                        for (int q = 0; q < DIM + 1; ++q) sum_lds<DET>(&wb[q], vals[q]);
                     } else {
                         const long long sidx = ((long long)izn * nslab_y + iyn) * d.nx + ixn;
                         double* gb = A.acc + (d.acc_off + sidx) * 4;
 #pragma unroll
-                        for (int q = 0; q < DIM + 1; ++q) gl_add(&gb[q], vals[q]);
+                        for (int q = 0; q < DIM + 1; ++q) sum_gl<DET>(&gb[q], vals[q]);
                         atomicAdd(&wstat[2], 1u);
                     }
                 }
@@ -630,11 +649,11 @@ k_particles(PArgs<PT> A) {
                     const int aj = J - wj0;
                     if (wj_ok && aj >= 0 && aj < wnj) {
 #pragma unroll
-                        for (int q = 0; q < DIM + 1; ++q) lds_add(&wprof[4 * NREP * aj + wrep + q], vals[q]);
+                        for (int q = 0; q < DIM + 1; ++q) sum_lds<DET>(&wprof[4 * NREP * aj + wrep + q], vals[q]);
                     } else {
                         double* gb = A.prof + (d.prof_off + (long long)copy * d.R + J) * 4;
 #pragma unroll
-                        for (int q = 0; q < DIM + 1; ++q) gl_add(&gb[q], vals[q]);
+                        for (int q = 0; q < DIM + 1; ++q) sum_gl<DET>(&gb[q], vals[q]);
                         atomicAdd(&wstat[2], 1u);
                     }
                 }
@@ -764,11 +783,15 @@ k_particles(PArgs<PT> A) {
         if (A.do_fb && win_ok) {
             for (int i = tid; i < wnx * wny * wnz; i += NT) {
                 double sum[4] = {0.0, 0.0, 0.0, 0.0};
+                [[maybe_unused]] unsigned long long isum[4] = {0ull, 0ull, 0ull, 0ull};
 #pragma unroll
                 for (int r = 0; r < NREP; ++r)
 #pragma unroll
-                    for (int q = 0; q < DIM + 1; ++q) sum[q] += wacc[4 * (NREP * i + r) + q];
-                if (sum[0] == 0.0) continue;
+                    for (int q = 0; q < DIM + 1; ++q) {
+                        if constexpr (DET) isum[q] += ((const unsigned long long*)wacc)[4 * (NREP * i + r) + q];
+                        else sum[q] += wacc[4 * (NREP * i + r) + q];
+                    }
+                if (DET ? isum[0] == 0ull : sum[0] == 0.0) continue;
                 const int ax = i % wnx, ay = (i / wnx) % wny, az = i / (wnx * wny);
                 int ixn = wx0 + ax; if (ixn < 0) ixn += d.nx; else if (ixn >= d.nx) ixn -= d.nx;
                 const int iyn = wy0 + ay;
@@ -778,21 +801,31 @@ k_particles(PArgs<PT> A) {
                 const long long sidx = ((long long)izn * nslab_y + iyn) * d.nx + ixn;
                 double* gb = A.acc + (d.acc_off + sidx) * 4;
 #pragma unroll
-                for (int q = 0; q < DIM + 1; ++q) gl_add(&gb[q], sum[q]);
+                for (int q = 0; q < DIM + 1; ++q) {
+                    if constexpr (DET) atomicAdd((unsigned long long*)&gb[q], isum[q]);
+                    else gl_add(&gb[q], sum[q]);
+                }
             }
         }
         if (A.do_prof && wj_ok) {
             for (int i = tid; i < wnj; i += NT) {
                 double sum[4] = {0.0, 0.0, 0.0, 0.0};
+                [[maybe_unused]] unsigned long long isum[4] = {0ull, 0ull, 0ull, 0ull};
 #pragma unroll
                 for (int r = 0; r < NREP; ++r)
 #pragma unroll
-                    for (int q = 0; q < DIM + 1; ++q) sum[q] += wprof[4 * (NREP * i + r) + q];
-                if (sum[0] == 0.0) continue;
+                    for (int q = 0; q < DIM + 1; ++q) {
+                        if constexpr (DET) isum[q] += ((const unsigned long long*)wprof)[4 * (NREP * i + r) + q];
+                        else sum[q] += wprof[4 * (NREP * i + r) + q];
+                    }
+                if (DET ? isum[0] == 0ull : sum[0] == 0.0) continue;
                 const int J = wj0 + i;
                 double* gb = A.prof + (d.prof_off + (long long)copy * d.R + J) * 4;
 #pragma unroll
-                for (int q = 0; q < DIM + 1; ++q) gl_add(&gb[q], sum[q]);
+                for (int q = 0; q < DIM + 1; ++q) {
+                    if constexpr (DET) atomicAdd((unsigned long long*)&gb[q], isum[q]);
+                    else gl_add(&gb[q], sum[q]);
+                }
             }
         }
         if (tid == 0) {
@@ -858,5 +891,7 @@ static hipError_t launch_modes(const ParticleLaunch& L, hipStream_t s) {
 
 // The Chapman-Enskog modes (bit 8), instantiated in kernels_mpcd_ce.hip.
 hipError_t launch_particles_ce(const ParticleLaunch& L, hipStream_t s);
+// The deterministic modes (bit 16), instantiated in kernels_mpcd_det.hip.
+hipError_t launch_particles_det(const ParticleLaunch& L, hipStream_t s);
 
 }  // namespace lbmpcd

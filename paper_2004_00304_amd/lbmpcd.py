@@ -19,7 +19,7 @@ import torch  # noqa: F401
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmpcd.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 RHO, U, PI, POP, PART_POS, PART_VEL, CELL_ID, CELL_COUNT, CELL_VCM, PROFILE, UFINE, STATS, \
     PART_VEL_PENDING, CELL_START, NODE_MPCD_U, TFINE, NODE_FB_U = range(17)
@@ -49,7 +49,7 @@ class Params(C.Structure):
         ("init_flow", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint32),
         ("tile", C.c_int32 * 3), ("capacity_factor", C.c_double),
         ("tile_target", C.c_int32), ("wg_threads", C.c_int32), ("closure", C.c_int32),
-        ("reinject", C.c_int32), ("ce_nu", C.c_double), ("fb_window", C.c_int32),
+        ("reinject", C.c_int32), ("ce_nu", C.c_double), ("fb_window", C.c_int32), ("deterministic", C.c_int32),
     ]
 
 
@@ -171,6 +171,7 @@ def params_struct(p: dict) -> Params:
     s.reinject = p.get("reinject", 0)
     s.ce_nu = p.get("ce_nu", 0.0)
     s.fb_window = p.get("fb_window", 0)
+    s.deterministic = p.get("deterministic", 0)
     return s
 
 

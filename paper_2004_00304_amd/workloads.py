@@ -27,6 +27,8 @@ _BASE = dict(
     # feedback: LB steps of the running mean of the node samples that is
     # projected onto the LB equilibria (0 = the library default, 50)
     fb_window=0,
+    # 1: order-independent integer sums in the particle kernel (bit-identical runs)
+    deterministic=0,
     # launch configuration of the HIP path (tile shape in cells, tile slot
     # capacity over expected occupancy); 0 = library default
     tile=(0, 0, 0), capacity_factor=0.0, tile_target=0, wg_threads=0, closure=0,

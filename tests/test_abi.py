@@ -61,6 +61,8 @@ def test_workspace_sizes(binding):
     (dict(walls_y=0, ylo=0, yhi=8), 6), (dict(substeps=300), 1),
     (dict(reinject=2), 1), (dict(reinject=1, kT=0.0), 1), (dict(ce_nu=float("nan")), 1),
     (dict(ce_nu=float("inf")), 1), (dict(reinject=1, alpha_deg=0.0), 1),
+    (dict(deterministic=2), 1), (dict(deterministic=1, reinject=1), 6),
+    (dict(dim=3, n=(16, 16, 8), ylo=4, yhi=12, buf_lo=1, buf_hi=1, closure=1, deterministic=1), 6),
 ])
 def test_invalid_params(binding, kw, code):
     with pytest.raises(binding.LbmpcdError) as e:
@@ -73,6 +75,8 @@ def test_mixed_batch_rejected(binding):
         binding.workspace_size([W.channel_2d(), W.small_3d()])
     with pytest.raises(binding.LbmpcdError):
         binding.workspace_size([W.channel_2d(), W.make(reinject=1)])
+    with pytest.raises(binding.LbmpcdError):
+        binding.workspace_size([W.channel_2d(), {**W.channel_2d(), "deterministic": 1, "instance": 1}])
 
 
 def test_chapman_enskog_workspace(binding):
