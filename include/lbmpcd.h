@@ -191,6 +191,12 @@ typedef struct lbmpcd_params {
                               from the FP64 sums by at most 2^-41 per summed value.  All
                               instances of a context share it; not with the closure or
                               the Chapman-Enskog exchange.  0: FP64 sums. */
+    int32_t schedule;      /* order in which the particle kernel's workgroups take tiles:
+                              0 XCD-blocked (the workgroups the hardware deals to one of
+                              the eight XCDs take one contiguous range of tiles, so that
+                              neighbouring tiles, which trade particles, share an L2);
+                              1 linear (workgroup b takes tile b).  All instances of a
+                              context share it; the results do not depend on it. */
 } lbmpcd_params;
 
 /*
@@ -300,7 +306,8 @@ void lbmpcd_destroy(struct lbmpcd_ctx* c);
  * step is cut into work, never what it computes).  Candidates are the tile
  * sizes tile_target in {160, 320, 640, 1280} expected particles per tile
  * (each instance's tile then follows from its own particles per cell) times
- * the particle kernel's workgroup size wg_threads in {256, 512}.  Each
+ * the particle kernel's workgroup size wg_threads in {256, 512} times the
+ * tile order schedule in {0, 1} (lbmpcd_params.schedule).  Each
  * candidate is initialised in dev_workspace (candidates that need more than
  * `bytes`, or are invalid for the parameters, are skipped), run for
  * 2 * lb_steps coupled steps and timed over the last lb_steps with HIP events
@@ -315,7 +322,9 @@ typedef struct lbmpcd_tuning {
     int32_t tried;         /* candidates measured */
     double ms_per_step;    /* ms per coupled LB step of the chosen candidate */
     double ms_default;     /* ms per coupled LB step of the library's default shape (tile
-                              target 1280, its default workgroup), -1 if not measured */
+                              target 1280, its default workgroup, schedule 0), -1 if not
+                              measured */
+    int32_t schedule;      /* chosen tile order */
 } lbmpcd_tuning;
 
 int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, size_t bytes,

@@ -269,6 +269,7 @@ int validate_one(const lbmpcd_params& p, std::string& msg) {
     if (!std::isfinite(p.ce_nu)) { msg = "ce_nu must be finite"; return LBMPCD_E_INVALID; }
     if (p.fb_window < 0) { msg = "fb_window must be >= 0"; return LBMPCD_E_INVALID; }
     if (p.deterministic != 0 && p.deterministic != 1) { msg = "deterministic must be 0 or 1"; return LBMPCD_E_INVALID; }
+    if (p.schedule != 0 && p.schedule != 1) { msg = "schedule must be 0 or 1"; return LBMPCD_E_INVALID; }
     if (p.deterministic && p.mpcd && (p.closure || p.reinject)) {
         msg = "the deterministic mode covers neither the closure nor the Chapman-Enskog exchange";
         return LBMPCD_E_UNSUPPORTED;
@@ -437,9 +438,10 @@ int validate_all(const lbmpcd_params* p, int n, std::string& msg) {
             return LBMPCD_E_INVALID;
         }
         if (p[i].wg_threads != p[0].wg_threads || p[i].collision != p[0].collision ||
-            (p[0].mpcd && p[i].reinject != p[0].reinject) || p[i].deterministic != p[0].deterministic) {
-            msg = "all instances must share wg_threads, the collision rule, the exchange rule and the "
-                  "deterministic mode";
+            (p[0].mpcd && p[i].reinject != p[0].reinject) || p[i].deterministic != p[0].deterministic ||
+            p[i].schedule != p[0].schedule) {
+            msg = "all instances must share wg_threads, the collision rule, the exchange rule, the "
+                  "deterministic mode and the schedule";
             return LBMPCD_E_INVALID;
         }
         if (p[i].closure && n != 1) {
@@ -671,6 +673,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max);
     c->coll_bit = p[0].collision == 1 ? 4 : 0;
     c->det_bit = (p[0].mpcd && p[0].deterministic) ? 16 : 0;
+    c->xcd_blocked = p[0].schedule == 0 ? 1 : 0;
 
     // tile -> instance table
     std::vector<int> tinst((size_t)std::max<long long>(c->total_tiles, 1));
@@ -1126,8 +1129,9 @@ int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace,
     out->tried = 0;
     out->ms_default = -1.0;
     for (int tt : targets) {
-        for (int wg : wgs) {
-            for (auto& x : q) { x.tile_target = tt; x.wg_threads = wg; }
+        for (int cand = 0; cand < 4; ++cand) {
+            const int wg = wgs[cand & 1], sched = cand >> 1;
+            for (auto& x : q) { x.tile_target = tt; x.wg_threads = wg; x.schedule = sched; }
             size_t need = 0;
             if (lbmpcd_workspace_size(q.data(), n_inst, &need) != LBMPCD_OK || need > bytes) continue;
             lbmpcd_ctx* c = nullptr;
@@ -1143,8 +1147,8 @@ int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace,
             if (!e) e = lbmpcd_sync(c);
             if (!e && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) e = LBMPCD_E_DEVICE;
             if (e) {
-                g_err = "autotune candidate (" + std::to_string(tt) + ", " + std::to_string(wg) + "): " +
-                        c->err;
+                g_err = "autotune candidate (" + std::to_string(tt) + ", " + std::to_string(wg) + ", " +
+                        std::to_string(sched) + "): " + c->err;
                 lbmpcd_destroy(c);
                 rc = e;
                 break;
@@ -1154,11 +1158,12 @@ int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace,
             lbmpcd_destroy(c);
             const double per = (double)ms / lb_steps;
             ++out->tried;
-            if (tt == 1280 && wg == default_wg) out->ms_default = per;
+            if (tt == 1280 && wg == default_wg && sched == 0) out->ms_default = per;
             if (best < 0 || per < best) {
                 best = per;
                 out->tile_target = tt;
                 out->wg_threads = wg;
+                out->schedule = sched;
                 out->ms_per_step = per;
             }
         }

@@ -50,6 +50,7 @@ class Params(C.Structure):
         ("tile", C.c_int32 * 3), ("capacity_factor", C.c_double),
         ("tile_target", C.c_int32), ("wg_threads", C.c_int32), ("closure", C.c_int32),
         ("reinject", C.c_int32), ("ce_nu", C.c_double), ("fb_window", C.c_int32), ("deterministic", C.c_int32),
+        ("schedule", C.c_int32),
     ]
 
 
@@ -64,7 +65,8 @@ CLOSURE_NF, CLOSURE_NOUT, CLOSURE_NPARAM, CLOSURE_NSTATS = 271, 9, 71177, 560
 
 class Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("tile_target", C.c_int32), ("wg_threads", C.c_int32),
-                ("tried", C.c_int32), ("ms_per_step", C.c_double), ("ms_default", C.c_double)]
+                ("tried", C.c_int32), ("ms_per_step", C.c_double), ("ms_default", C.c_double),
+                ("schedule", C.c_int32)]
 
 
 def _load():
@@ -172,6 +174,7 @@ def params_struct(p: dict) -> Params:
     s.ce_nu = p.get("ce_nu", 0.0)
     s.fb_window = p.get("fb_window", 0)
     s.deterministic = p.get("deterministic", 0)
+    s.schedule = p.get("schedule", 0)
     return s
 
 
@@ -198,8 +201,8 @@ def viscosity(params) -> tuple:
 
 def autotune(params, lb_steps: int = 5, device="cuda", stream=None) -> dict:
     """Runs lbmpcd_autotune on a scratch workspace large enough for every
-    candidate and returns the chosen launch shape (tile_target, wg_threads)
-    with the timings."""
+    candidate and returns the chosen launch shape (tile_target, wg_threads,
+    schedule) with the timings."""
     import torch
 
     plist = list(params) if isinstance(params, (list, tuple)) else [params]
@@ -222,7 +225,7 @@ def autotune(params, lb_steps: int = 5, device="cuda", stream=None) -> dict:
                                   C.c_void_p(st.cuda_stream), int(lb_steps), C.byref(out))
         _check(rc, None)
         del ws
-    return dict(tile_target=out.tile_target, wg_threads=out.wg_threads, tried=out.tried,
+    return dict(tile_target=out.tile_target, wg_threads=out.wg_threads, schedule=out.schedule, tried=out.tried,
                 ms_per_step=out.ms_per_step, ms_default=out.ms_default)
 
 
@@ -249,7 +252,8 @@ def scratch_size(n: int, batch: int = 0) -> int:
 
 def with_tuning(params, tuning: dict):
     """The parameter dict(s) with the launch shape chosen by autotune."""
-    upd = {"tile_target": tuning["tile_target"], "wg_threads": tuning["wg_threads"]}
+    upd = {"tile_target": tuning["tile_target"], "wg_threads": tuning["wg_threads"],
+           "schedule": tuning.get("schedule", 0)}
     if isinstance(params, (list, tuple)):
         return [{**p, **upd} for p in params]
     return {**params, **upd}

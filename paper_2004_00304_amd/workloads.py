@@ -29,6 +29,8 @@ _BASE = dict(
     fb_window=0,
     # 1: order-independent integer sums in the particle kernel (bit-identical runs)
     deterministic=0,
+    # particle kernel's tile order: 0 XCD-blocked, 1 linear (launch shape, like tile_target)
+    schedule=0,
     # launch configuration of the HIP path (tile shape in cells, tile slot
     # capacity over expected occupancy); 0 = library default
     tile=(0, 0, 0), capacity_factor=0.0, tile_target=0, wg_threads=0, closure=0,

@@ -61,7 +61,7 @@ def test_workspace_sizes(binding):
     (dict(walls_y=0, ylo=0, yhi=8), 6), (dict(substeps=300), 1),
     (dict(reinject=2), 1), (dict(reinject=1, kT=0.0), 1), (dict(ce_nu=float("nan")), 1),
     (dict(ce_nu=float("inf")), 1), (dict(reinject=1, alpha_deg=0.0), 1),
-    (dict(deterministic=2), 1), (dict(deterministic=1, reinject=1), 6),
+    (dict(deterministic=2), 1), (dict(deterministic=1, reinject=1), 6), (dict(schedule=2), 1),
     (dict(dim=3, n=(16, 16, 8), ylo=4, yhi=12, buf_lo=1, buf_hi=1, closure=1, deterministic=1), 6),
 ])
 def test_invalid_params(binding, kw, code):

@@ -47,6 +47,7 @@ CASES = {
     "shape_small_tiles_wg512": (W.small_3d(tile_target=160, wg_threads=512), 4, RTOL64),
     "shape_large_tiles": (W.small_2d(tile_target=1280), 4, RTOL64),
     "shape_wg512_fp32": (W.small_3d(part_fp=32, wg_threads=512), 4, RTOL32),
+    "shape_linear_order_fp32": (W.small_3d(part_fp=32, schedule=1), 4, RTOL32),
     # MPCD with Andersen thermostat (Eq. 6), the paper's own collision rule
     "at_small_2d": (W.small_2d(collision=1), 6, RTOL64),
     "at_small_3d": (W.small_3d(collision=1), 5, RTOL64),
