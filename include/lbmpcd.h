@@ -86,7 +86,9 @@ enum lbmpcd_field {
     LBMPCD_PROFILE = 9,    /* double[R][4]: per fine row sum n, sum v_x, v_y, v_z  */
     LBMPCD_UFINE = 10,     /* double[dim][nz*r][R][nx*r]: buffer-cell LB velocity  */
     LBMPCD_STATS = 11,     /* int64[10]: lb steps, sampled steps, dropped particles,
-                              misplaced particles, far moves, max tile fill,
+                              misplaced particles, far moves (particles that moved
+                              beyond the neighbour tiles, counted in the MPCD steps
+                              that take samples), max tile fill,
                               particles, cells, samples that missed their tile's LDS
                               window and went to global atomics (a slow path: 0
                               for the default tiles at refinement >= 2), invalid

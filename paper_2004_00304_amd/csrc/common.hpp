@@ -233,7 +233,7 @@ __device__ __forceinline__ int find_inst(const InstDesc* __restrict__ D, int n_i
 struct DevStats {
     unsigned long long dropped;     // particles lost to tile overflow
     unsigned long long misplaced;   // particles found outside their tile
-    unsigned long long far_moves;   // particles moving beyond the neighbour tiles
+    unsigned long long far_moves;   // particles moving beyond the neighbour tiles (sampling MPCD steps)
     unsigned int max_fill;          // largest tile occupancy seen
     unsigned int pad;
     unsigned long long window_misses;  // samples outside their tile's LDS window (global atomics)

@@ -680,10 +680,15 @@ k_particles(PArgs<PT> A) {
                 dest[k] = lt;
                 atomicAdd(&wstat[3], 1u);
             }
-            int dx = ntx - tx, dy = nty - ty, dz = ntz - tz;
-            if (d.ntx > 2) { if (dx == d.ntx - 1) dx = -1; else if (dx == 1 - d.ntx) dx = 1; }
-            if (DIM == 3 && d.ntz > 2) { if (dz == d.ntz - 1) dz = -1; else if (dz == 1 - d.ntz) dz = 1; }
-            if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) atomicAdd(&wstat[0], 1u);
+            // moves beyond the neighbour tiles (they are grouped like any other
+            // destination; the count bounds the sample-window misses, so it is
+            // kept in the MPCD steps that sample, and skipped in the others)
+            if (A.do_fb | A.do_prof) {
+                int dx = ntx - tx, dy = nty - ty, dz = ntz - tz;
+                if (d.ntx > 2) { if (dx == d.ntx - 1) dx = -1; else if (dx == 1 - d.ntx) dx = 1; }
+                if (DIM == 3 && d.ntz > 2) { if (dz == d.ntz - 1) dz = -1; else if (dz == 1 - d.ntz) dz = 1; }
+                if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) atomicAdd(&wstat[0], 1u);
+            }
         }
 
         // ---- phase 3a: group each wave's particles by destination tile.
