@@ -126,37 +126,48 @@ def test_longrun_profile_matches_analytic(env, collision):
 
 def test_longrun_two_way_profile_matches_closed_form(env):
     """Feedback on (the running time average of the MPCD velocity projected
-    onto the LB equilibria of the slab interior, window 50 LB steps): the
-    run stays bounded (rho within 5 %, no invalid particle or band node) and
-    the time-averaged slab profile over 100,000 LB steps follows the two-way
-    closed form (two parabolas, nu_L = 0.1 and nu_M = 0.068) within 2 %,
-    against 7-10 % from the one-way form.  Projecting the instantaneous
-    sample instead (a window of one LB step) drives this channel unstable
-    within a few thousand steps in the oracle, and with positions left
-    unchecked such a run once addressed memory out of range; both are fixed
-    (the oracle's two-way pins and the range guards)."""
+    onto the LB equilibria of the slab interior, window 50 LB steps), eight
+    independent realizations of the channel (distinct Philox keys) in one
+    batched context: every one stays bounded (rho within 5 %, no invalid
+    particle or band node), and their mean time-averaged slab profile over
+    100,000 LB steps follows the two-way closed form (two parabolas,
+    nu_L = 0.1 and nu_M = 0.068) within 1 %, against 7-10 % from the one-way
+    form.  The mean is needed: with feedback the MPCD's thermal noise drives
+    the LB, whose mean flow then wanders on the viscous time (H^2/nu ~ 10^4
+    LB steps), so one realization averaged over 100,000 steps lands 0.1-3 %
+    from the closed form (measured 0.47 % for the mean of eight).  Projecting
+    the instantaneous sample instead (a window of one LB step) drives this
+    channel unstable within a few thousand steps in the oracle, and with
+    positions left unchecked such a run once addressed memory out of range;
+    both are fixed (the oracle's two-way pins and the range guards)."""
     O, lbmpcd = env
-    p = W.make(n=(128, 32, 1), tau=0.8, g=(4e-5, 0.0, 0.0), ylo=12, yhi=20, buf_lo=2, buf_hi=2, ppc=10,
-               feedback=1, init_flow=1)
+    ps = [W.make(n=(128, 32, 1), tau=0.8, g=(4e-5, 0.0, 0.0), ylo=12, yhi=20, buf_lo=2, buf_hi=2, ppc=10,
+                 feedback=1, init_flow=1, instance=i) for i in range(8)]
+    p = ps[0]
     J, y = interior_rows(p)
     u2, u1 = two_way(p, y), analytic(p, y)
     # the closed form itself: matched viscosities give the LB parabola
     q = dict(p, tau=0.5 + 3 * nu_srd_2d(p))
     assert np.allclose(two_way(q, y), lb_poiseuille(q, y), rtol=1e-12)
-    sim = lbmpcd.Sim(p)
+    sim = lbmpcd.Sim(ps)
     sim.step(3000)
     sim.sample(1)
     for _ in range(5):
         sim.step(20000)
-        rho, _, _ = sim.fields()
         st = sim.stats()
-        banner(f"two-way: rho [{rho.min():.4f}, {rho.max():.4f}], invalid {st['bad_state']}")
-        assert 0.95 < rho.min() and rho.max() < 1.05 and st["bad_state"] == 0
-    u = profile_u(sim.profile(), J)
+        for i in range(len(ps)):
+            rho, _, _ = sim.fields(i)
+            assert 0.95 < rho.min() and rho.max() < 1.05, (i, rho.min(), rho.max())
+        banner(f"two-way: invalid {st['bad_state']}")
+        assert st["bad_state"] == 0
+    us = np.array([profile_u(sim.profile(i), J) for i in range(len(ps))])
+    each = [np.linalg.norm(u - u2) / np.linalg.norm(u2) for u in us]
+    u = us.mean(axis=0)
     e2 = np.linalg.norm(u - u2) / np.linalg.norm(u2)
     e1 = np.linalg.norm(u - u1) / np.linalg.norm(u1)
-    banner(f"two-way long run: vs two-way form {e2:.4f}, vs one-way form {e1:.4f}; u {np.round(u, 5)}")
-    assert e2 <= 0.02
+    banner(f"two-way long run, mean of {len(ps)}: vs two-way form {e2:.4f}, vs one-way form {e1:.4f}; "
+           f"each {np.round(each, 4).tolist()}; u {np.round(u, 5)}")
+    assert e2 <= 0.01
     assert e1 >= 0.04
 
 
