@@ -406,7 +406,10 @@ def closure_bench(lbmpcd, W, args):
         "training": {"samples": int(n_samples), "data_s": t_data, "train_s": t_train,
                      "initial_loss": float(first[0]), "epoch_loss": [float(x) for x in losses],
                      "loss_floor": float(floor_k.mean()),
-                     "loss_floor_per_output": [round(float(x), 4) for x in floor_k]},
+                     "loss_floor_per_output": [round(float(x), 4) for x in floor_k],
+                     # share of the reducible loss (initial loss less the noise floor)
+                     # that training removed
+                     "learned_fraction": float((first[0] - losses[-1]) / max(first[0] - floor_k.mean(), 1e-12))},
     }
     print(json.dumps(out), flush=True)
 
