@@ -196,16 +196,25 @@ __device__ __forceinline__ double sum_read(const double* p) {
 }
 
 // LDS carve-up (bytes): header (counters and the table of destination tiles),
-// sample windows, collision arrays.
+// sample windows, collision arrays and the tile's window of buffer-cell LB
+// velocities.
 constexpr int NHASH_BITS = 6;
 constexpr int NHASH = 1 << NHASH_BITS;
 constexpr size_t LDS_HDR = 1088;  // >= 4 * (4 + 3 * NHASH + 2), a multiple of 16
 // Sample windows hold NREP interleaved replicas of every bin (lane l adds
 // into replica l mod NREP), so that the lanes of a wave, which mostly sample
 // the same one or two nodes, spread their FP64 atomics over more banks.
-constexpr int NREP = 8;
+constexpr int NREP = 4;
 constexpr size_t LDS_WIN = (size_t)(MAX_WIN + MAX_WJ) * NREP * 4 * sizeof(double);
-constexpr size_t LDS_COLL = (size_t)MAX_NCT * 4 + (size_t)MAX_NCT * 9 * sizeof(double);
+// The exchange reads the LB velocity of a buffer particle's fine cell.  A
+// particle binned into shifted cell i (shift in [0, a)) sits in unshifted
+// fine cell i - 1 or i, so the particles of a tile of Tx x Ty x Tz cells read
+// at most (Tx + 1)(Ty + 1)(Tz + 1) fine cells, which the workgroup copies into
+// LDS at the start of the launch, where the loads overlap the particle loads
+// and the collision instead of stalling the exchange.
+constexpr int MAX_UFC = 256;
+constexpr size_t LDS_COLL = (size_t)MAX_NCT * 4 + (size_t)MAX_NCT * 9 * sizeof(double) +
+                            (size_t)MAX_UFC * 3 * sizeof(double);
 constexpr uint32_t DROP_SLOT = 0x7FFFFFFFu;  // never a slot: the slot total stays below it
 static_assert(4 * (4 + 3 * NHASH + 2) <= (int)LDS_HDR, "LDS header too small");
 
@@ -241,6 +250,7 @@ k_particles(PArgs<PT> A) {
     uint32_t* ccnt = (uint32_t*)uni;                 // [MAX_NCT]
     double* csv = (double*)(uni + MAX_NCT * 4);      // [MAX_NCT][3]
     double* cvcm = csv + MAX_NCT * 3;                // [MAX_NCT][3]
+    double* ucache = cvcm + MAX_NCT * 6;          // [3][MAX_UFC] LB velocities of the tile's buffer cells
     double* crot = cvcm + MAX_NCT * 3;               // [MAX_NCT][3] SRD sign/axis; MPCD-AT: sum, then mean, of the random velocities
 
     const int tid = threadIdx.x;
@@ -302,6 +312,29 @@ k_particles(PArgs<PT> A) {
     }
     if (tid == 0 && n > (uint32_t)(3 * cap / 4)) atomicMax(&A.stats->max_fill, n);
     if (tid < 4) wstat[tid] = 0u;
+    // window of fine cells (origin one cell below the tile on each axis);
+    // only buffer rows are copied, and only for tiles that reach them
+    if constexpr (STREAM) {
+        const int uwx = d.Tx + 1, uwy = d.Ty + 1, uwz = (DIM == 3) ? d.Tz + 1 : 1;
+        const int uJ0 = (ty << d.lTy) - 1;
+        const int rbl = d.buf_lo * d.r, rbh = d.R - d.buf_hi * d.r;
+        if (((uJ0 < rbl) || (uJ0 + uwy - 1 >= rbh)) && uwx * uwy * uwz <= MAX_UFC) {
+            const int uI0 = (tx << d.lTx) - 1, uK0 = (DIM == 3) ? (tz << d.lTz) - 1 : 0;
+            const long long NFc = (long long)d.Cx * d.NB * d.Cz;
+            const double* ufc = A.ufine + d.ufine_off * DIM;
+            for (int i = tid; i < uwx * uwy * uwz; i += NT) {
+                const int ax = i % uwx, ay = (i / uwx) % uwy, az = i / (uwx * uwy);
+                const int J = uJ0 + ay;
+                if (J < 0 || J >= d.R || (J >= rbl && J < rbh)) continue;
+                const int I = ((uI0 + ax) % d.Cx + d.Cx) % d.Cx;
+                const int K = (DIM == 3) ? ((uK0 + az) % d.Cz + d.Cz) % d.Cz : 0;
+                const int Jb = (J < rbl) ? J : J - (d.R - d.NB);
+                const long long fc = ((long long)K * d.NB + Jb) * d.Cx + I;
+#pragma unroll
+                for (int q = 0; q < DIM; ++q) ucache[q * MAX_UFC + i] = ufc[q * NFc + fc];
+            }
+        }
+    }
 
     // rotation of every cell of the tile (2D sign / 3D axis): independent of
     // the particles
@@ -527,7 +560,7 @@ k_particles(PArgs<PT> A) {
                 const int K = (DIM == 3) ? clampi((int)floor((double)px[k][2] * (double)d.r), 0, d.Cz - 1) : 0;
                 const int Jb = (J0 < rb_lo) ? J0 : J0 - (d.R - d.NB);
                 const long long fc = ((long long)K * d.NB + Jb) * d.Cx + I;
-                double z[3];
+                double z[3], ulv[3];
                 if (sizeof(PT) == 4 && !(CE && ce_on)) {
                     // binary32 particles draw binary32 normals (one Philox
                     // block); the Chapman-Enskog draws stay binary64
@@ -542,7 +575,30 @@ k_particles(PArgs<PT> A) {
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < DIM; ++q) pv[k][q] = (PT)(uf[q * NF + fc] + d.sd * z[q]);
+                for (int q = 0; q < DIM; ++q) ulv[q] = 0.0;
+                {
+                    // the LB velocity from the tile's LDS window, or from
+                    // global memory for a particle outside it (misplaced, or
+                    // a window too large for the LDS)
+                    const int uwx = d.Tx + 1, uwy = d.Ty + 1, uwz = (DIM == 3) ? d.Tz + 1 : 1;
+                    const int uJ0 = (ty << d.lTy) - 1;
+                    const bool uc_ok = ((uJ0 < rb_lo) || (uJ0 + uwy - 1 >= rb_hi)) && uwx * uwy * uwz <= MAX_UFC;
+                    int ax = I - ((tx << d.lTx) - 1);
+                    if (ax < 0) ax += d.Cx;
+                    const int ay = J0 - uJ0;
+                    int az = 0;
+                    if (DIM == 3) { az = K - ((tz << d.lTz) - 1); if (az < 0) az += d.Cz; }
+                    if (uc_ok && ax < uwx && ay >= 0 && ay < uwy && az < uwz) {
+                        const int ci = ax + uwx * (ay + uwy * az);
+#pragma unroll
+                        for (int q = 0; q < DIM; ++q) ulv[q] = ucache[q * MAX_UFC + ci];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < DIM; ++q) ulv[q] = uf[q * NF + fc];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < DIM; ++q) pv[k][q] = (PT)(ulv[q] + d.sd * z[q]);
             }
         }
 
