@@ -48,6 +48,13 @@ CASES = {
     "shape_large_tiles": (W.small_2d(tile_target=1280), 4, RTOL64),
     "shape_wg512_fp32": (W.small_3d(part_fp=32, wg_threads=512), 4, RTOL32),
     "shape_linear_order_fp32": (W.small_3d(part_fp=32, schedule=1), 4, RTOL32),
+    # the tile's LDS window of buffer-cell LB velocities read by the exchange:
+    # a window larger than its table (17 x 9 x 2 cells: every buffer particle
+    # reads global memory) and a tile wider than the channel (the window wraps
+    # onto itself); the feedback makes the LB velocity vary along x and z
+    "lbwin_too_large_3d": (W.small_3d(tile=(16, 8, 1), init_flow=1, g=(1e-4, 0, 0)), 5, RTOL64),
+    "lbwin_tile_wider_than_channel_2d": (W.small_2d(n=(3, 24, 1), tile=(16, 4, 0), init_flow=1, g=(1e-4, 0, 0)),
+                                         6, RTOL64),
     # MPCD with Andersen thermostat (Eq. 6), the paper's own collision rule
     "at_small_2d": (W.small_2d(collision=1), 6, RTOL64),
     "at_small_3d": (W.small_3d(collision=1), 5, RTOL64),
