@@ -49,10 +49,22 @@ def pmc_file(workload: str) -> str:
 
 
 def kernel_hash() -> str:
+    """Hash of the sources the particle and LB kernels are built from.  In the
+    C++ sources comments and white space are dropped first (none of them holds
+    a comment marker inside a string), so that an edit of comments alone keeps
+    the committed counter summaries valid; build.py, which holds the compiler
+    flags, enters as it is."""
+    import re
     h = hashlib.sha256()
     for s in KERNEL_SOURCES:
         with open(os.path.join(ROOT, s), "rb") as f:
-            h.update(f.read())
+            text = f.read()
+        if not s.endswith(".py"):
+            t = text.decode()
+            t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)
+            t = re.sub(r"//[^\n]*", " ", t)
+            text = " ".join(t.split()).encode()
+        h.update(text)
     return h.hexdigest()[:16]
 
 

@@ -1,5 +1,5 @@
 // particles.hpp -- the fused MPCD step for gfx950 (the particle kernel template;
-// kernels_mpcd.hip and kernels_mpcd_ce.hip instantiate it).
+// kernels_mpcd.hip, kernels_mpcd_ce.hip and kernels_mpcd_det.hip instantiate it).
 //
 // Particle layout.  The cells of the shifted grid are grouped into tiles of
 // Tx x Ty x Tz cells; every tile owns `cap` slots in each SoA component
@@ -15,7 +15,9 @@
 //     particle is rotated about its cell's centre of mass in registers;
 //   phase 2 (next MPCD step): Maxwell-Boltzmann redraw of buffer particles
 //     (exchange step of Alg. 1; with mode bit 8 the first-order
-//     Chapman-Enskog redraw instead), streaming with the body force (Eq. 3) and
+//     Chapman-Enskog redraw instead) about the LB velocity of their fine cell,
+//     which the workgroup copied into LDS for every buffer cell of the tile
+//     while the particles were loading, streaming with the body force (Eq. 3) and
 //     boundary conditions, samples of the last MPCD step of an LB step,
 //     binning into the new shifted grid;
 //   phase 3 (counting sort into tiles): each wave groups its particles by
