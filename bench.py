@@ -442,7 +442,8 @@ def pmc_summary(workload: str, fetch_csv: str, write_csv: str, command: str) -> 
     """Writes the committed PMC summary of the workload's particle kernel
     from two rocprofv3 --pmc runs of `bench.py --calib-copy` (FETCH_SIZE,
     WRITE_SIZE; KiB per dispatch).  Each counter is scaled by what it reads
-    for the plain 1 GiB device copy in the same run."""
+    for the plain 1 GiB device copy in the same run; the same scales applied
+    to k_lb_step, whose bytes are known exactly, check the calibration."""
     import csv
     from paper_2004_00304_amd import workloads as W
 
@@ -480,6 +481,13 @@ def pmc_summary(workload: str, fetch_csv: str, write_csv: str, command: str) -> 
     p = plist[0]
     alg = totals(plist)["launch_bytes"]
     lb_alg = totals(plist)["lb_bytes"]
+    # a check of the copy calibration on another kernel: k_lb_step reads and
+    # writes each population once, half of its algorithmic bytes each way
+    lbf = [v for k, vs in f.items() if "k_lb_step" in k for v in vs]
+    lbw = [v for k, vs in w.items() if "k_lb_step" in k for v in vs]
+    lb_check = ({"fetch_over_algorithmic": sum(lbf) / len(lbf) * 1024 * fscale / (lb_alg / 2),
+                 "write_over_algorithmic": sum(lbw) / len(lbw) * 1024 * wscale / (lb_alg / 2)}
+                if lbf and lbw else None)
     out = {
         "kernel": f"{', '.join(names)} (fused MPCD step), {workload}",
         "kernel_hash": kernel_hash(),
@@ -495,6 +503,7 @@ def pmc_summary(workload: str, fetch_csv: str, write_csv: str, command: str) -> 
         "traffic_over_algorithmic": (fetch_b + write_b) / alg,
         "other_kernels_bytes_per_lb_step": other,
         "lb_step_algorithmic_bytes": lb_alg,
+        "calibration_check_k_lb_step": lb_check,
         "step_bytes_per_lb_step": p["substeps"] * (fetch_b + write_b) + sum(other.values()),
     }
     with open(pmc_file(workload), "w") as fo:
