@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "gelu.hpp"
 #include "mlp.hpp"
 
 namespace lbmpcd {
@@ -30,13 +31,6 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// GELU with the exact normal CDF, and its derivative Phi(x) + x phi(x).
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad(float x) {
-    const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
-    const float pdf = 0.39894228040143268f * expf(-0.5f * x * x);
-    return cdf + x * pdf;
-}
 
 constexpr int GT = 64;   // output tile side
 constexpr int GK = 32;   // K step
