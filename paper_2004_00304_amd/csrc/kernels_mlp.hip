@@ -363,7 +363,11 @@ hipError_t mlp_stats(const float* X, const float* Y, long long n, double* sums, 
 }
 
 // Row r of the batch: source row idx (drawn uniformly from n with Philox when
-// `draw`, else r), standardised; features to BF16 with zero padding.
+// `draw`, else r), standardised; features to BF16 with zero padding.  Every
+// kernel standardises a feature as (x - mean) times the binary32 reciprocal of
+// its standard deviation, so that training and the fused inference see the
+// same values (the fused kernel reads the reciprocals from LDS, a multiply per
+// feature where a division took 6 % of its time).
 __global__ void __launch_bounds__(256) k_gather(const float* X, const float* Y, long long n, const float* st,
                                                 long long rows, int draw, uint32_t k0, uint32_t k1,
                                                 uint32_t step, uint16_t* Xb, float* Yb) {
@@ -377,7 +381,7 @@ __global__ void __launch_bounds__(256) k_gather(const float* X, const float* Y, 
     }
     for (int c = threadIdx.x; c < NFP; c += 256) {
         float x = 0.0f;
-        if (c < NF) x = (X[src * NF + c] - st[c]) / st[NF + c];
+        if (c < NF) x = (X[src * NF + c] - st[c]) * (1.0f / st[NF + c]);
         Xb[r * NFP + c] = to_bf16(x);
     }
     if (Y && threadIdx.x < NOUT) {
@@ -463,7 +467,7 @@ __global__ void __launch_bounds__(256) k_features(const InstDesc* __restrict__ D
     // each feature goes straight to its output as it is formed
     auto emit = [&](int q, double v) {
         if (facc) facc[sn * NF + q] += v;
-        if (Xb) Xb[sn * NFP + q] = to_bf16(((float)v - st[q]) / st[NF + q]);
+        if (Xb) Xb[sn * NFP + q] = to_bf16(((float)v - st[q]) * (1.0f / st[NF + q]));
     };
     int k = 0;
     double mc[10];
@@ -648,12 +652,23 @@ __global__ void __launch_bounds__(FNT) k_mlp_fused(const InstDesc* __restrict__ 
                                                    const uint16_t* __restrict__ Pf, const float* __restrict__ P32,
                                                    float* Y, float* uc) {
     __shared__ uint16_t xs[FR * XPITCH];
+    __shared__ float sinv[NF];     // reciprocals of the features' standard deviations
+    __shared__ int rxyz[3 * FR];   // node coordinates of the block's rows
     const InstDesc& d = D[inst];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long r0 = (long long)blockIdx.x * FR;
     const int nsy = d.yhi - d.ylo;
-    auto band_index = [&](long long sn, int dx, int dy, int dz) {
-        const int x = (int)(sn % d.nx), y = d.ylo + (int)((sn / d.nx) % nsy), z = (int)(sn / ((long long)d.nx * nsy));
+    for (int k = tid; k < NF; k += FNT) sinv[k] = 1.0f / st[NF + k];
+    // the divisions by the channel's sizes once per row, not per stencil entry
+    for (int r = tid; r < FR; r += FNT) {
+        const long long sn = r0 + r < nslab ? r0 + r : 0;
+        rxyz[3 * r] = (int)(sn % d.nx);
+        rxyz[3 * r + 1] = d.ylo + (int)((sn / d.nx) % nsy);
+        rxyz[3 * r + 2] = (int)(sn / ((long long)d.nx * nsy));
+    }
+    __syncthreads();
+    auto band_index = [&](int r, int dx, int dy, int dz) {
+        const int x = rxyz[3 * r], y = rxyz[3 * r + 1], z = rxyz[3 * r + 2];
         int xx = x + dx; if (xx < 0) xx += d.nx; else if (xx >= d.nx) xx -= d.nx;
         int zz = z + dz; if (zz < 0) zz += d.nz; else if (zz >= d.nz) zz -= d.nz;
         int yy = y + dy; yy = yy < 0 ? 0 : (yy >= d.ny ? d.ny - 1 : yy);
@@ -670,10 +685,10 @@ __global__ void __launch_bounds__(FNT) k_mlp_fused(const InstDesc* __restrict__ 
             for (int q = 0; q < 10; ++q) xr[q] = 0;
             continue;
         }
-        const float* m = M + band_index(sn, s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1) * BMS;
+        const float* m = M + band_index(r, s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1) * BMS;
         for (int q = 0; q < 10; ++q) {
             const int k = s * 10 + q;
-            xr[q] = to_bf16((m[q] - st[k]) / st[NF + k]);
+            xr[q] = to_bf16((m[q] - st[k]) * sinv[k]);
         }
     }
     for (int r = tid; r < FR; r += FNT) {
@@ -681,8 +696,8 @@ __global__ void __launch_bounds__(FNT) k_mlp_fused(const InstDesc* __restrict__ 
         uint16_t* xr = xs + r * XPITCH;
         for (int q = NF - 1; q < NFP; ++q) xr[q] = 0;
         if (sn >= nslab) continue;
-        const float* m = M + band_index(sn, 0, 0, 0) * BMS;
-        xr[NF - 1] = to_bf16((m[10] - st[NF - 1]) / st[2 * NF - 1]);
+        const float* m = M + band_index(r, 0, 0, 0) * BMS;
+        xr[NF - 1] = to_bf16((m[10] - st[NF - 1]) * sinv[NF - 1]);
         for (int a = 0; a < 3; ++a) uc[sn * 3 + a] = m[1 + a];
     }
     __syncthreads();
