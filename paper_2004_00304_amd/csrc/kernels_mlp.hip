@@ -21,14 +21,9 @@ typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// BF16 with round-to-nearest-even (NaN kept quiet); branch-free, so that
-// loops of conversions stay one basic block the scheduler can overlap.
-__device__ __forceinline__ uint16_t to_bf16(float x) {
-    const uint32_t u = __float_as_uint(x);
-    const uint32_t rounded = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-    const uint32_t quiet = (u >> 16) | 0x40u;
-    return (uint16_t)((u & 0x7FFFFFFFu) > 0x7F800000u ? quiet : rounded);
-}
+// BF16 with round-to-nearest-even: gfx950's conversion instruction
+// (v_cvt_pk_bf16_f32); NaN stays NaN.
+__device__ __forceinline__ uint16_t to_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 
