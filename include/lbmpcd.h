@@ -40,7 +40,8 @@
  * below; no exception or abort crosses the ABI.  lbmpcd_last_error gives a
  * message.  Device-side overflow or state corruption is latched and reported
  * by the next synchronising call (lbmpcd_sync, moments, get_state):
- * E_OVERFLOW when a tile overflowed; E_STATE when a particle moved more than
+ * E_OVERFLOW when a tile overflowed (E_STATE takes precedence: invalid
+ * particles are parked in one tile, which may overflow); E_STATE when a particle moved more than
  * one period in one MPCD step or its position or velocity became non-finite
  * (it is parked at the slab's lower corner at rest, so every index the
  * kernels derive stays in range), when a node of the rows next to the slab

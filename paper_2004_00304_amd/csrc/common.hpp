@@ -14,10 +14,12 @@ constexpr int NCOPY = 64;         // replicas of the profile accumulators
 constexpr int MAX_NCT = 128;      // cells per particle tile
 constexpr int MAX_WIN = 96;       // LDS bins of the feedback sample window: the nodes a tile's
                                   // particles can sample, (Tx/r + 2)(Ty/r + 2)(Tz/r + 2) rounded
-                                  // up, for every default tile shape at r >= 2 (36 for the thin
-                                  // film's 4x4x8 cells at r = 4, 96 for 4x4x8 at r = 2); larger
+                                  // up (48 for the thin film's 8x2x8 cells at r = 4); larger
                                   // windows fall back to global atomics per sample
 constexpr int MAX_WJ = 16;        // LDS rows of the profile sample window
+constexpr int NM_WIN = 64;        // nodes of the closure's LDS window of node sums (same formula)
+constexpr int MAX_UFC = 256;      // fine cells of the exchange's LDS window of LB velocities,
+                                  // (Tx + 1)(Ty + 1)(Tz + 1)
 constexpr uint32_t BAD_SLOT = 0xFFFFFFFFu;
 
 // Purposes of the random streams: the counter of every draw is

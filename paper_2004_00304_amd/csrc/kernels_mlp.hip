@@ -761,7 +761,6 @@ hipError_t mlp_destandardize_uc(const float* Y, const float* stats, const float*
 // of those nodes (NMREP interleaved replicas of each, lane l adding into
 // replica l mod NMREP) and reach memory with one global atomic per node and
 // moment; a particle outside the window adds to memory directly.
-constexpr int NM_WIN = 64;  // nodes of the LDS window: a 4x4x8-cell tile at r = 4 needs 3x3x4 = 36
 constexpr int NMREP = 8;    // 40 KB of LDS with 10 FP64 sums per node and replica
 
 template <typename PT>

@@ -214,7 +214,6 @@ constexpr size_t LDS_WIN = (size_t)(MAX_WIN + MAX_WJ) * NREP * 4 * sizeof(double
 // at most (Tx + 1)(Ty + 1)(Tz + 1) fine cells, which the workgroup copies into
 // LDS at the start of the launch, where the loads overlap the particle loads
 // and the collision instead of stalling the exchange.
-constexpr int MAX_UFC = 256;
 constexpr size_t LDS_COLL = (size_t)MAX_NCT * 4 + (size_t)MAX_NCT * 9 * sizeof(double) +
                             (size_t)MAX_UFC * 3 * sizeof(double);
 constexpr uint32_t DROP_SLOT = 0x7FFFFFFFu;  // never a slot: the slot total stays below it

@@ -21,7 +21,7 @@ import numpy as np
 import pytest
 
 _HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                    "paper_2004_00304_amd", "csrc", "particles.hpp")
+                    "paper_2004_00304_amd", "csrc", "common.hpp")
 MAX_UFC = int(re.search(r"constexpr int MAX_UFC = (\d+);", open(_HDR).read()).group(1))
 
 
