@@ -41,7 +41,8 @@ def _geometry(rng, dim):
     R = nsy * r                                 # fine rows of the slab
     Cx, Cz = nx * r, (nz * r if dim == 3 else 1)
     opts = [(1, 1, 1), (2, 1, 1), (2, 2, 1), (4, 2, 1), (4, 4, 1), (8, 4, 1), (8, 8, 1), (16, 8, 1)] if dim == 2 else \
-        [(1, 1, 1), (2, 2, 1), (2, 2, 2), (4, 2, 2), (4, 4, 2), (4, 4, 4), (4, 4, 8), (8, 4, 4), (16, 8, 1)]
+        [(1, 1, 1), (2, 2, 1), (2, 2, 2), (4, 2, 2), (4, 4, 2), (4, 4, 4), (4, 4, 8), (8, 4, 4), (16, 8, 1),
+         (8, 2, 8), (4, 2, 8), (8, 2, 4), (8, 1, 8)]
     T = opts[int(rng.integers(len(opts)))]
     return dict(dim=dim, r=r, R=R, Cx=Cx, Cz=Cz, CyB=R + 1, NB=(buf_lo + buf_hi) * r,
                 rbl=buf_lo * r, rbh=R - buf_hi * r, T=T, nx=nx, nz=nz, nsy=nsy)
@@ -120,11 +121,11 @@ def test_window_lookup_reads_the_particles_own_cell(dim, dtype):
 
 
 def test_film_tiles_fit_the_table():
-    """The thin film's 4 x 4 x 8 tiles need (5)(5)(9) = 225 entries, the
-    largest default 3D shape; every default 2D shape fits as well, and a
-    16 x 8 x 1 tile (306 entries) does not, which the parity case for an
-    oversized window uses."""
-    assert 5 * 5 * 9 <= MAX_UFC
+    """The thin film's 8 x 2 x 8 tiles need (9)(3)(9) = 243 entries and the 3D
+    channel's 4 x 2 x 8 tiles 135 (the library only picks shapes whose window
+    fits); every default 2D shape fits as well, and a 16 x 8 x 1 tile (306
+    entries) does not, which the parity case for an oversized window uses."""
+    assert 9 * 3 * 9 <= MAX_UFC and 5 * 3 * 9 <= MAX_UFC
     for T in [(1, 1), (2, 1), (2, 2), (4, 2), (4, 4), (8, 4), (8, 8), (16, 8)]:
         assert (T[0] + 1) * (T[1] + 1) <= MAX_UFC
     assert 17 * 9 * 2 > MAX_UFC
