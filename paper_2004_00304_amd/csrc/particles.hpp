@@ -752,29 +752,29 @@ k_particles(PArgs<PT> A) {
         // Lanes with equal destinations get consecutive ranks; the group's
         // first lane claims a row of the LDS destination table and the
         // group's offset in it, and hands both back with one permute.
-        const unsigned long long below_me = (1ull << lane) - 1ull;
         uint32_t pk[PPT];  // bit 31: direct slot; else (table row + 1) << 24 | rank
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const uint32_t key = dest[k];
-            unsigned long long todo = __ballot(key != BAD_SLOT);
+            // Waterfall over the lanes still waiting: the lowest of them
+            // names the next group, whose lanes (the active lanes with its
+            // key) take their ranks from the active mask and leave the loop.
             int my_leader = 0;
             uint32_t my_rank = 0, lead_cnt = 0;
-            bool is_lead = false;
-            while (todo) {
-                const int leader = __ffsll((unsigned long long)todo) - 1;
-                const uint32_t kv = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
-                const unsigned long long m = __ballot(key == kv);
-                if (key == kv) {
-                    my_leader = leader;
-                    my_rank = (uint32_t)__popcll(m & below_me);
+            if (key != BAD_SLOT) {
+                for (;;) {
+                    const uint32_t kv = (uint32_t)__builtin_amdgcn_readfirstlane((int)key);
+                    if (key == kv) {
+                        const unsigned long long m = __ballot(1);
+                        my_leader = __ffsll(m) - 1;
+                        my_rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        lead_cnt = (uint32_t)__popcll(m);
+                        break;
+                    }
                 }
-                if (lane == leader) {
-                    is_lead = true;
-                    lead_cnt = (uint32_t)__popcll(m);
-                }
-                todo &= ~m;
             }
+            const bool is_lead = key != BAD_SLOT && my_rank == 0u;
             uint32_t packed = 0u;
             if (is_lead) {
                 int h = -1;
