@@ -50,6 +50,7 @@ struct lbmpcd_ctx {
     double* prof = nullptr;
     double* shifts = nullptr;   // [n_inst][2][S][3] grid shifts drawn by the LB kernel
     DevStats* stats = nullptr;
+    uint32_t* ovf = nullptr;      // [2 + total_tiles] overflow list of the two-pass particle launch
     long long* clock = nullptr;
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
@@ -58,6 +59,7 @@ struct lbmpcd_ctx {
               total_particles = 0, total_slab = 0;
     size_t lds = 0;
     int cap_max = 0;              // largest tile capacity
+    int exp_max = 0;              // largest expected tile occupancy
     int wg_threads = 0;           // particle kernel workgroup size
     int coll_bit = 0;             // 4 for the MPCD-AT collision (particle kernel mode bit)
     int ce_bit = 0;               // 8 for the Chapman-Enskog exchange (particle kernel mode bit)
@@ -357,7 +359,7 @@ double ce_nu(const lbmpcd_params& p) {
 constexpr int FB_WINDOW_DEFAULT = 50;
 
 struct Layout {
-    size_t desc, tile_inst, f0, f1, ub, uf, tb, tf, acc, fbu, prof, fill0, fill1, stats, clock, shifts, scratch, end;
+    size_t desc, tile_inst, f0, f1, ub, uf, tb, tf, acc, fbu, prof, fill0, fill1, stats, ovf, clock, shifts, scratch, end;
     size_t cl_P, cl_Pb, cl_Pf, cl_G, cl_m, cl_v, cl_stats, cl_sums, cl_loss, cl_facc, cl_nm, cl_uc, cl_inf;
     size_t part[2];       // particle buffer: 2 dim component arrays of cstride bytes, then ids
     size_t cstride;
@@ -447,6 +449,7 @@ int build(const lbmpcd_params* p, int n, std::vector<InstDesc>& D, Layout& L, lo
     L.cstride = align_up((size_t)slots * pw, 256);
     for (int b = 0; b < 2; ++b) L.part[b] = take(2 * (size_t)dim * L.cstride + (size_t)slots * 4);
     L.stats = take(sizeof(DevStats));
+    L.ovf = take(4 * ((size_t)tiles + 2));
     L.clock = take(sizeof(long long));
     L.shifts = take(sizeof(double) * 6 * (size_t)n * (p[0].mpcd ? p[0].substeps : 1));
     L.scratch_bytes = std::min<size_t>(align_up(max_field, 256), (size_t)64 << 20);
@@ -546,7 +549,7 @@ int finalize(lbmpcd_ctx* c) {
     L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.tfine = c->tf; L.acc = c->acc; L.prof = c->prof;
     L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts;
     L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
-    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
+    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.ovf = c->ovf; L.exp_max = c->exp_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
     HIPCHK(c, launch_particles(L, c->stream));
     c->pending = false;
     return 0;
@@ -686,6 +689,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
         c->part[b].id = (uint32_t*)(pb + (size_t)2 * c->dim * L.cstride);
     }
     c->stats = (DevStats*)(c->ws + L.stats);
+    c->ovf = (uint32_t*)(c->ws + L.ovf);
     c->clock = (long long*)(c->ws + L.clock);
     c->shifts = (double*)(c->ws + L.shifts);
     if (p[0].closure) {
@@ -710,6 +714,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     int cap_max = 64;
     for (const InstDesc& d : c->desc) {
         cap_max = std::max(cap_max, d.cap);
+        c->exp_max = std::max(c->exp_max, d.ppc * d.nct);
         if (d.feedback) c->any_feedback = true;
     }
     c->cap_max = cap_max;
@@ -739,6 +744,7 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
     rc = rc ? rc : chk(hipMemcpyAsync(c->d_tile_inst, tinst.data(), 4 * (size_t)c->total_tiles, hipMemcpyHostToDevice, s), "tile table");
     rc = rc ? rc : chk(hipMemcpyAsync(c->clock, &clock0, sizeof(clock0), hipMemcpyHostToDevice, s), "clock");
     rc = rc ? rc : chk(launch_zero(c->stats, sizeof(DevStats), s), "stats");
+    rc = rc ? rc : chk(launch_zero(c->ovf, 4 * ((size_t)c->total_tiles + 2), s), "overflow list");
     rc = rc ? rc : chk(launch_zero(c->acc, c->acc_bytes, s), "acc");
     rc = rc ? rc : chk(launch_zero(c->prof, c->prof_bytes, s), "prof");
     rc = rc ? rc : chk(launch_zero(c->ub, 3 * 8 * (size_t)c->total_band, s), "ub");
@@ -829,7 +835,7 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
                 // samples are taken in the last MPCD step of the LB step
                 L.do_fb = (c->any_feedback && sub == c->S - 1) ? 1 : 0;
                 L.do_prof = (c->sampling && sub == c->S - 1) ? 1 : 0;
-                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
+                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.ovf = c->ovf; L.exp_max = c->exp_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
                 HIPCHK(c, timed(c, 3, [&] { return launch_particles(L, s); }));
                 c->pcur ^= 1;
                 c->pending = true;
@@ -1007,7 +1013,7 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.tfine = c->tf; L.acc = c->acc; L.prof = c->prof;
             L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts; L.shifts = c->shifts;
             L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
-            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
+            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.ovf = c->ovf; L.exp_max = c->exp_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
             HIPCHK(c, launch_particles(L, s));
             return 0;
         }

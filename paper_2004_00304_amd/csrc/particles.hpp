@@ -61,6 +61,12 @@ struct PArgs {
     int coll_dt, coll_s, str_s, do_fb, do_prof, diag_inst;
     long long ntiles;  // tiles of all instances
     long long xcd_per; // > 0: tiles per XCD of the XCD-blocked order, 0: workgroup b takes tile b
+    // Overflow list: [0] tiles listed, [1] workgroups of the overflow pass
+    // done, [2..] tiles.  ovf_mode 0: every tile fits the launch's slots;
+    // 1: a tile with more particles than NT * PPT is listed and skipped;
+    // 2: the overflow pass over the listed tiles.
+    uint32_t* ovf;
+    int ovf_mode;
 };
 
 template <typename PT>
@@ -217,6 +223,7 @@ constexpr size_t LDS_WIN = (size_t)(MAX_WIN + MAX_WJ) * NREP * 4 * sizeof(double
 constexpr size_t LDS_COLL = (size_t)MAX_NCT * 4 + (size_t)MAX_NCT * 9 * sizeof(double) +
                             (size_t)MAX_UFC * 3 * sizeof(double);
 constexpr uint32_t DROP_SLOT = 0x7FFFFFFFu;  // never a slot: the slot total stays below it
+constexpr long long OVF_GRID = 1024;          // workgroups of the overflow pass
 static_assert(4 * (4 + 3 * NHASH + 2) <= (int)LDS_HDR, "LDS header too small");
 
 // Minimum resident waves per SIMD the register allocation must allow.  With
@@ -225,21 +232,20 @@ static_assert(4 * (4 + 3 * NHASH + 2) <= (int)LDS_HDR, "LDS header too small");
 // 3.45 against 3.49 ms per MPCD step of the 3D channel with SRD, 4.93 against
 // 5.78 with MPCD-AT, 4.70 against 7.3 with the Chapman-Enskog exchange); with
 // binary64 particles (the batched 2D ensemble) four is as fast.
-template <typename PT, int MODE>
+template <typename PT, int MODE, int PPT>
 constexpr int particle_waves() {
+    if (PPT == 6 && sizeof(PT) == 4 && (MODE & 12) == 0) return 5;
     return (sizeof(PT) == 4 || (MODE & 8) != 0) ? 3 : 4;
 }
 
 // One workgroup per tile.
 template <int DIM, typename PT, int NT, int PPT, int MODE>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(particle_waves<PT, MODE>())))
-k_particles(PArgs<PT> A) {
+__device__ __forceinline__ void particle_tile(const PArgs<PT>& A, long long T, unsigned char* smem) {
     constexpr bool COLL = (MODE & 1) != 0;
     constexpr bool STREAM = (MODE & 2) != 0;
     constexpr bool AT = (MODE & 4) != 0;  // MPCD-AT collision (Eq. 6) instead of SRD (Eq. 4)
     constexpr bool CE = (MODE & 8) != 0;  // Chapman-Enskog exchange instead of Maxwell-Boltzmann
     constexpr bool DET = (MODE & 16) != 0;  // deterministic: fixed-point integer sums
-    extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* wstat = (uint32_t*)smem;          // [4] far moves, misplaced, samples outside the LDS windows,
                                                 // invalid particles
     uint32_t* hkey = wstat + 4;                 // [NHASH] destination tiles (local index)
@@ -256,15 +262,6 @@ k_particles(PArgs<PT> A) {
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    // Workgroups are dealt to the eight XCDs in turn.  In the XCD-blocked
-    // order the workgroups of one XCD take one contiguous range of tiles, so
-    // the tiles that trade particles are mostly served by one L2, where the
-    // partial lines of their destination runs merge.
-    long long T = blockIdx.x;
-    if (A.xcd_per > 0) {
-        T = (long long)(blockIdx.x % 8) * A.xcd_per + blockIdx.x / 8;
-        if (T >= A.ntiles) return;
-    }
     const long long cs = A.cs;
     const int ii = cptr(A.tile_inst)[T];
     cst<InstDesc>& d = cptr(A.D)[ii];
@@ -282,6 +279,12 @@ k_particles(PArgs<PT> A) {
     const unsigned char* tin = A.in.b + base * (long long)sizeof(PT);
     const unsigned char* tin_id = A.in.b + 2 * DIM * cs + base * 4;
     uint32_t n = cptr(A.fill_in)[T];
+    if (A.ovf_mode == 1 && n > (uint32_t)(NT * PPT)) {
+        // more particles than this launch's slots: left untouched for the
+        // overflow pass, which takes the tiles of this list
+        if (tid == 0) A.ovf[2 + atomicAdd(&A.ovf[0], 1u)] = (uint32_t)T;
+        return;
+    }
     if (n > (uint32_t)cap) n = (uint32_t)cap;
     const long long t_now = *cptr(A.clock);
     const PT rr = (PT)d.r;
@@ -900,11 +903,50 @@ k_particles(PArgs<PT> A) {
     }
 }
 
+// One workgroup per tile.
+template <int DIM, typename PT, int NT, int PPT, int MODE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(particle_waves<PT, MODE, PPT>())))
+k_particles(PArgs<PT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    // Workgroups are dealt to the eight XCDs in turn.  In the XCD-blocked
+    // order the workgroups of one XCD take one contiguous range of tiles, so
+    // the tiles that trade particles are mostly served by one L2, where the
+    // partial lines of their destination runs merge.
+    long long T = blockIdx.x;
+    if (A.xcd_per > 0) {
+        T = (long long)(blockIdx.x % 8) * A.xcd_per + blockIdx.x / 8;
+        if (T >= A.ntiles) return;
+    }
+    particle_tile<DIM, PT, NT, PPT, MODE>(A, T, smem);
+}
+
+// The overflow pass (ovf_mode 2): the workgroups of a small grid take the
+// listed tiles in turn; the last workgroup to finish clears the list.  A
+// kernel of its own, so that the loop does not weigh on the register
+// allocation of the one-tile kernel.
+template <int DIM, typename PT, int NT, int PPT, int MODE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(particle_waves<PT, MODE, PPT>())))
+k_particles_ovf(PArgs<PT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t cnt = A.ovf[0];
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        particle_tile<DIM, PT, NT, PPT, MODE>(A, (long long)A.ovf[2 + i], smem);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&A.ovf[1], 1u) == gridDim.x - 1) {
+            A.ovf[0] = 0u;
+            A.ovf[1] = 0u;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launch templates; `Modes::run<DIM, PT, NT, PPT>` picks the instantiation
 // of the mode (each translation unit instantiates its own set)
 // ---------------------------------------------------------------------------
-template <int DIM, typename PT, int NT, int PPT, int MODE>
+template <int DIM, typename PT, int NT, int PPT, int MODE, int OVF = 0>
 static hipError_t launch_p4(const ParticleLaunch& L, hipStream_t s) {
     PArgs<PT> a;
     a.D = L.D;
@@ -916,10 +958,19 @@ static hipError_t launch_p4(const ParticleLaunch& L, hipStream_t s) {
     a.do_fb = L.do_fb; a.do_prof = L.do_prof; a.diag_inst = L.diag_inst; a.cell_vcm = L.cell_vcm;
     a.ntiles = L.tiles;
     a.xcd_per = L.xcd_blocked ? (L.tiles + 7) / 8 : 0;
-    const long long grid = L.xcd_blocked ? 8 * a.xcd_per : L.tiles;
-    auto kern = k_particles<DIM, PT, NT, PPT, MODE>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), L.lds_bytes, s, a);
-    return hipGetLastError();
+    a.ovf = L.ovf;
+    a.ovf_mode = OVF;
+    if constexpr (OVF == 2) {
+        const long long grid = L.tiles < OVF_GRID ? L.tiles : OVF_GRID;
+        hipLaunchKernelGGL((k_particles_ovf<DIM, PT, NT, PPT, MODE>), dim3((unsigned)grid), dim3(NT), L.lds_bytes, s,
+                           a);
+        return hipGetLastError();
+    } else {
+        const long long grid = L.xcd_blocked ? 8 * a.xcd_per : L.tiles;
+        auto kern = k_particles<DIM, PT, NT, PPT, MODE>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), L.lds_bytes, s, a);
+        return hipGetLastError();
+    }
 }
 
 // Workgroup shape: threads x particles per thread must cover the largest
