@@ -288,6 +288,15 @@ __device__ __forceinline__ void particle_tile(const PArgs<PT>& A, long long T, u
     const int ii = cptr(A.tile_inst)[T];
     cst<InstDesc>& d = cptr(A.D)[ii];
     const Key key = key_of(d);
+    // The Philox key at a draw site, pinned to scalar registers there, so
+    // that the compiler derives the round keys next to each draw (scalar
+    // additions) instead of keeping twenty of them live across the kernel,
+    // which spills other scalars into vector lanes.
+    auto kfresh = [&]() {
+        Key k = key;
+        asm volatile("" : "+s"(k.k0), "+s"(k.k1));
+        return k;
+    };
     // tile coordinates in 32-bit arithmetic (a channel has fewer than 2^31 tiles)
     const uint32_t lt = (uint32_t)(T - d.tile_off);
     const uint32_t nxy = (uint32_t)d.ntx * (uint32_t)d.nty;
@@ -378,7 +387,7 @@ __device__ __forceinline__ void particle_tile(const PArgs<PT>& A, long long T, u
             const int lx = j & (d.Tx - 1), ly = (j >> d.lTx) & (d.Ty - 1), lz = j >> (d.lTx + d.lTy);
             const int ix = (tx << d.lTx) + lx, iy = (ty << d.lTy) + ly, iz = (tz << d.lTz) + lz;
             const uint32_t cg = (uint32_t)(ix + d.Cx * (iy + d.CyB * iz));
-            const U4 w = AT ? U4{0u, 0u, 0u, 0u} : rng_block(key, cg, tc, sc, P_ROT, 0);
+            const U4 w = AT ? U4{0u, 0u, 0u, 0u} : rng_block(kfresh(), cg, tc, sc, P_ROT, 0);
             if constexpr (AT) {
                 crot[3 * j] = 0.0; crot[3 * j + 1] = 0.0; crot[3 * j + 2] = 0.0;
             } else if constexpr (DIM == 2) {
@@ -436,11 +445,11 @@ __device__ __forceinline__ void particle_tile(const PArgs<PT>& A, long long T, u
                 double z[3];
                 if constexpr (sizeof(PT) == 4) {
                     float zf[3];
-                    rng_normals32<DIM>(key, pid[k], tc, sc, P_AT, zf);
+                    rng_normals32<DIM>(kfresh(), pid[k], tc, sc, P_AT, zf);
 #pragma unroll
                     for (int q = 0; q < 3; ++q) z[q] = (double)zf[q];
                 } else {
-                    rng_normals<DIM>(key, pid[k], tc, sc, P_AT, z);
+                    rng_normals<DIM>(kfresh(), pid[k], tc, sc, P_AT, z);
                 }
 #pragma unroll
                 for (int q = 0; q < DIM; ++q) {
@@ -463,7 +472,7 @@ __device__ __forceinline__ void particle_tile(const PArgs<PT>& A, long long T, u
             const bool cut = ((double)sh[1] > 0.0) && ((d.bot_wall && iy == 0) || (d.top_wall && iy == d.R));
             if (cut && (int)nc < d.ppc) {
                 double z[3];
-                rng_normals<DIM>(key, cg, tc, sc, P_WALL, z);
+                rng_normals<DIM>(kfresh(), cg, tc, sc, P_WALL, z);
                 const int nv = d.ppc - (int)nc;
                 const double sdv = sqrt((double)nv * d.kT / d.mass);
 #pragma unroll
@@ -600,13 +609,13 @@ __device__ __forceinline__ void particle_tile(const PArgs<PT>& A, long long T, u
                     // binary32 particles draw binary32 normals (one Philox
                     // block); the Chapman-Enskog draws stay binary64
                     float zf[3];
-                    rng_normals32<DIM>(key, pid[k], ts, ss, P_REINJ, zf);
+                    rng_normals32<DIM>(kfresh(), pid[k], ts, ss, P_REINJ, zf);
 #pragma unroll
                     for (int q = 0; q < 3; ++q) z[q] = (double)zf[q];
                 } else {
-                    reinject_normals<DIM>(key, pid[k], ts, ss, z);
+                    reinject_normals<DIM>(kfresh(), pid[k], ts, ss, z);
                     if constexpr (CE) {
-                        if (ce_on) ce_redraw<DIM>(key, pid[k], ts, ss, tfl, NF, fc, z);
+                        if (ce_on) ce_redraw<DIM>(kfresh(), pid[k], ts, ss, tfl, NF, fc, z);
                     }
                 }
 #pragma unroll
