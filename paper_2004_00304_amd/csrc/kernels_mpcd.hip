@@ -45,12 +45,14 @@ static hipError_t launch_split_mode(const ParticleLaunch& L, hipStream_t s) {
         case 1: return launch_split<DIM, 1>(L, s);
         case 2: return launch_split<DIM, 2>(L, s);
         case 3: return launch_split<DIM, 3>(L, s);
+        case 5: return launch_split<DIM, 5>(L, s);
+        case 7: return launch_split<DIM, 7>(L, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 static bool split_applies(const ParticleLaunch& L) {
-    if (L.part_fp != 32 || L.ovf == nullptr || (L.mode != 1 && L.mode != 2 && L.mode != 3)) return false;
+    if (L.part_fp != 32 || L.ovf == nullptr || (L.mode != 1 && L.mode != 2 && L.mode != 3 && L.mode != 5 && L.mode != 7)) return false;
     if ((L.wg_threads != 0 && L.wg_threads != 256) || L.cap_max <= 4 * 256 || L.cap_max > 8 * 256) return false;
     const double e = (double)L.exp_max;
     return e + 2.0 * std::sqrt(e) <= 6.0 * 256;

@@ -256,7 +256,7 @@ static_assert(4 * (4 + 3 * NHASH + 2) <= (int)LDS_HDR, "LDS header too small");
 // binary64 particles (the batched 2D ensemble) four is as fast.
 template <typename PT, int MODE, int PPT>
 constexpr int particle_waves() {
-    if (PPT == 6 && sizeof(PT) == 4 && (MODE & 12) == 0) return 5;
+    if (PPT == 6 && sizeof(PT) == 4 && (MODE & 8) == 0) return (MODE & 4) ? 4 : 5;
     return (sizeof(PT) == 4 || (MODE & 8) != 0) ? 3 : 4;
 }
 

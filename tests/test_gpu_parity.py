@@ -347,8 +347,9 @@ def test_chapman_enskog_xz_shear_parity(env):
     assert np.abs(orc.tfine()[4]).max() > 1e-3
 
 
-def test_parity_overflow_pass(env):
-    """Binary32 SRD particles in tiles of 4x4x2 cells at 45 per cell (1440
+@pytest.mark.parametrize("collision", [0, 1])
+def test_parity_overflow_pass(env, collision):
+    """Binary32 SRD (and MPCD-AT) particles in tiles of 4x4x2 cells at 45 per cell (1440
     expected, 1984 slots) run as two launches per MPCD step: six slots per
     thread (1536 per tile), then an eight-slot pass over the tiles that held
     more.  A tile's Poisson count passes 1536 now and then (the oracle's own
@@ -357,8 +358,8 @@ def test_parity_overflow_pass(env):
     matches the oracle, and the largest tile fill seen is above 1536, so the
     second launch took part."""
     O, lbmpcd = env
-    p = W.small_3d(part_fp=32, ppc=45, tile=(4, 4, 2), g=(1e-4, 0.0, 0.0))
-    banner("parity overflow pass: 45 ppc, 4x4x2 tiles, 12 LB steps")
+    p = W.small_3d(part_fp=32, ppc=45, tile=(4, 4, 2), g=(1e-4, 0.0, 0.0), collision=collision)
+    banner(f"parity overflow pass: 45 ppc, 4x4x2 tiles, 12 LB steps, collision {collision}")
     sim = lbmpcd.Sim(p)
     orc = O.Oracle(_params(p))
     sim.step(12)
