@@ -12,12 +12,12 @@ namespace lbmpcd {
 
 namespace {
 struct CEModes {
-    template <int DIM, typename PT, int NT, int PPT>
+    template <int DIM, typename PT, int NT, int PPT, int OVF = 0>
     static hipError_t run(const ParticleLaunch& L, hipStream_t s) {
         switch (L.mode) {
-            case 10: return launch_p4<DIM, PT, NT, PPT, 10>(L, s);
-            case 11: return launch_p4<DIM, PT, NT, PPT, 11>(L, s);
-            case 15: return launch_p4<DIM, PT, NT, PPT, 15>(L, s);
+            case 10: return launch_p4<DIM, PT, NT, PPT, 10, OVF>(L, s);
+            case 11: return launch_p4<DIM, PT, NT, PPT, 11, OVF>(L, s);
+            case 15: return launch_p4<DIM, PT, NT, PPT, 15, OVF>(L, s);
             default: return hipErrorInvalidValue;
         }
     }

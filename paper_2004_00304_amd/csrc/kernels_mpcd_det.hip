@@ -11,14 +11,14 @@ namespace lbmpcd {
 
 namespace {
 struct DetModes {
-    template <int DIM, typename PT, int NT, int PPT>
+    template <int DIM, typename PT, int NT, int PPT, int OVF = 0>
     static hipError_t run(const ParticleLaunch& L, hipStream_t s) {
         switch (L.mode) {
-            case 17: return launch_p4<DIM, PT, NT, PPT, 17>(L, s);
-            case 18: return launch_p4<DIM, PT, NT, PPT, 18>(L, s);
-            case 19: return launch_p4<DIM, PT, NT, PPT, 19>(L, s);
-            case 21: return launch_p4<DIM, PT, NT, PPT, 21>(L, s);
-            case 23: return launch_p4<DIM, PT, NT, PPT, 23>(L, s);
+            case 17: return launch_p4<DIM, PT, NT, PPT, 17, OVF>(L, s);
+            case 18: return launch_p4<DIM, PT, NT, PPT, 18, OVF>(L, s);
+            case 19: return launch_p4<DIM, PT, NT, PPT, 19, OVF>(L, s);
+            case 21: return launch_p4<DIM, PT, NT, PPT, 21, OVF>(L, s);
+            case 23: return launch_p4<DIM, PT, NT, PPT, 23, OVF>(L, s);
             default: return hipErrorInvalidValue;
         }
     }
