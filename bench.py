@@ -462,7 +462,8 @@ def pmc_summary(workload: str, fetch_csv: str, write_csv: str, command: str) -> 
     gib_kib = float(1 << 20)
     fscale = gib_kib / max(copy_f)  # the copy reads 1 GiB
     wscale = gib_kib / max(copy_w)  # and writes 1 GiB
-    is_fused = lambda k: "k_particles" in k and ", 3>" in k
+    # the particle kernel of the fused step (mode 3), not its overflow pass
+    is_fused = lambda k: "k_particles<" in k and ", 3>" in k
     fused = lambda d: [v for k, vs in d.items() if is_fused(k) for v in vs]
     pf, pw = fused(f), fused(w)
     names = sorted({k.split("(")[0].replace("void ", "").replace("lbmpcd::", "") for k in f if is_fused(k)})
@@ -479,6 +480,9 @@ def pmc_summary(workload: str, fetch_csv: str, write_csv: str, command: str) -> 
     other = {t: mean_bytes(t) for t in ("k_lb_step", "k_band", "k_interp")}
     plist = workload_params(workload)
     p = plist[0]
+    # the overflow pass after every particle launch of a two-pass step
+    # (almost always an empty list)
+    other["k_particles_ovf"] = p["substeps"] * mean_bytes("k_particles_ovf")
     alg = totals(plist)["launch_bytes"]
     lb_alg = totals(plist)["lb_bytes"]
     # a check of the copy calibration on another kernel: k_lb_step reads and
