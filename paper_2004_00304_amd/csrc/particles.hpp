@@ -247,7 +247,7 @@ constexpr size_t LDS_WIN = (size_t)(MAX_WIN + MAX_WJ) * NREP * 4 * sizeof(double
 constexpr size_t LDS_COLL = (size_t)MAX_NCT * 4 + (size_t)MAX_NCT * 9 * sizeof(double) +
                             (size_t)MAX_UFC * 3 * sizeof(double);
 constexpr uint32_t DROP_SLOT = 0x7FFFFFFFu;  // never a slot: the slot total stays below it
-constexpr long long OVF_GRID = 1024;          // workgroups of the overflow pass
+constexpr long long OVF_GRID = 128;           // workgroups of the overflow pass
 static_assert(4 * (4 + 3 * NHASH + 2) <= (int)LDS_HDR, "LDS header too small");
 
 // Minimum resident waves per SIMD the register allocation must allow.  With
