@@ -1046,32 +1046,38 @@ static hipError_t launch_p2(const ParticleLaunch& L, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-// Binary32 particles in tiles of 1025-2048 slots at 256 threads: six slots
-// per thread instead of eight leave the kernel fewer vector registers and
-// one more wave per SIMD (SRD: 96 VGPRs and five waves instead of 113 and
-// four; MPCD-AT: 123 and four instead of 152 and three).  A tile holding
+// Tiles of 1025-2048 slots at 256 threads: six slots per thread instead of
+// eight leave the kernel fewer vector registers and, for binary32
+// particles, one more wave per SIMD (SRD: 96 VGPRs and five waves instead
+// of 113 and four; MPCD-AT: 123 and four instead of 152 and three); binary64
+// particles stay at four waves and spill 24 bytes per lane instead of 108.
+// A tile holding
 // more than 1536 particles is skipped and listed by that launch and
 // processed by a second, eight-slot launch over the list.  It is rare: the
 // tile's expected occupancy plus two standard deviations of its Poisson
 // count must stay within 1536 for this form to be taken.
 inline bool split_applies(const ParticleLaunch& L) {
-    if (L.part_fp != 32 || L.ovf == nullptr) return false;
+    if (L.ovf == nullptr) return false;
     if ((L.wg_threads != 0 && L.wg_threads != 256) || L.cap_max <= 4 * 256 || L.cap_max > 8 * 256) return false;
     const double e = (double)L.exp_max;
     return e + 2.0 * std::sqrt(e) <= 6.0 * 256;
 }
 
-template <class Modes, int DIM>
+template <class Modes, int DIM, typename PT>
 static hipError_t launch_split_dim(const ParticleLaunch& L, hipStream_t s) {
-    hipError_t e = Modes::template run<DIM, float, 256, 6, 1>(L, s);
-    if (e == hipSuccess) e = Modes::template run<DIM, float, 256, 8, 2>(L, s);
+    hipError_t e = Modes::template run<DIM, PT, 256, 6, 1>(L, s);
+    if (e == hipSuccess) e = Modes::template run<DIM, PT, 256, 8, 2>(L, s);
     return e;
 }
 
 template <class Modes>
 static hipError_t launch_modes(const ParticleLaunch& L, hipStream_t s) {
     if (L.tiles <= 0) return hipSuccess;
-    if (split_applies(L)) return L.dim == 2 ? launch_split_dim<Modes, 2>(L, s) : launch_split_dim<Modes, 3>(L, s);
+    if (split_applies(L)) {
+        if (L.part_fp == 64)
+            return L.dim == 2 ? launch_split_dim<Modes, 2, double>(L, s) : launch_split_dim<Modes, 3, double>(L, s);
+        return L.dim == 2 ? launch_split_dim<Modes, 2, float>(L, s) : launch_split_dim<Modes, 3, float>(L, s);
+    }
     if (L.dim == 2 && L.part_fp == 64) return launch_p2<Modes, 2, double>(L, s);
     if (L.dim == 2) return launch_p2<Modes, 2, float>(L, s);
     if (L.part_fp == 64) return launch_p2<Modes, 3, double>(L, s);

@@ -347,9 +347,10 @@ def test_chapman_enskog_xz_shear_parity(env):
     assert np.abs(orc.tfine()[4]).max() > 1e-3
 
 
-@pytest.mark.parametrize("collision", [0, 1])
-def test_parity_overflow_pass(env, collision):
-    """Binary32 SRD (and MPCD-AT) particles in tiles of 4x4x2 cells at 45 per cell (1440
+@pytest.mark.parametrize("collision,part_fp", [(0, 32), (1, 32), (0, 64)])
+def test_parity_overflow_pass(env, collision, part_fp):
+    """Binary32 SRD and MPCD-AT, and binary64 SRD (256-thread workgroups),
+    particles in tiles of 4x4x2 cells at 45 per cell (1440
     expected, 1984 slots) run as two launches per MPCD step: six slots per
     thread (1536 per tile), then an eight-slot pass over the tiles that held
     more.  A tile's Poisson count passes 1536 now and then (the oracle's own
@@ -358,14 +359,16 @@ def test_parity_overflow_pass(env, collision):
     matches the oracle, and the largest tile fill seen is above 1536, so the
     second launch took part."""
     O, lbmpcd = env
-    p = W.small_3d(part_fp=32, ppc=45, tile=(4, 4, 2), g=(1e-4, 0.0, 0.0), collision=collision)
-    banner(f"parity overflow pass: 45 ppc, 4x4x2 tiles, 12 LB steps, collision {collision}")
+    p = W.small_3d(part_fp=part_fp, ppc=45, tile=(4, 4, 2), g=(1e-4, 0.0, 0.0), collision=collision,
+                   wg_threads=256)
+    banner(f"parity overflow pass: 45 ppc, 4x4x2 tiles, 12 LB steps, collision {collision}, fp{part_fp}")
     sim = lbmpcd.Sim(p)
     orc = O.Oracle(_params(p))
     sim.step(12)
     orc.step(12)
-    rep = compare_state(sim, orc, p, RTOL32)
+    rtol = RTOL32 if part_fp == 32 else RTOL64
+    rep = compare_state(sim, orc, p, rtol)
     st = sim.stats()
     banner(f"overflow pass: {rep}; max fill {st['max_fill']}")
-    assert_parity(rep, RTOL32)
+    assert_parity(rep, rtol)
     assert st["max_fill"] > 1536 and st["dropped"] == 0, st
