@@ -151,7 +151,13 @@ typedef struct lbmpcd_params {
     double capacity_factor;/* tile capacity / expected occupancy; 0 = default 1.3 */
     int32_t tile_target;   /* expected particles per tile when tile[] is 0; 0 = default 1280 */
     int32_t wg_threads;    /* particle kernel workgroup: 128, 256 or 512 threads; 0 = 256,
-                              or 512 for binary64 particles in tiles of over 1024 slots.
+                              or 512 for binary64 particles in tiles of over 1024 slots
+                              unless the six-slot form applies.  Six-slot form: at 256
+                              threads, tiles of 1025-2048 slots whose expected
+                              occupancy plus two Poisson standard deviations is within
+                              1536 run six particles per thread, then an overflow pass
+                              over the tiles holding more; taken with an explicit 256,
+                              and by default on grids of at least 4096 tiles.
                               All instances of a context must agree. */
     int32_t closure;       /* 1: reserve the learned closure (lbmpcd_closure_*); needs
                               dim 3, mpcd and a single channel */

@@ -60,6 +60,7 @@ struct lbmpcd_ctx {
     size_t lds = 0;
     int cap_max = 0;              // largest tile capacity
     int exp_max = 0;              // largest expected tile occupancy
+    bool split_ok = false;        // the particle launch may take the six-slot form
     int wg_threads = 0;           // particle kernel workgroup size
     int coll_bit = 0;             // 4 for the MPCD-AT collision (particle kernel mode bit)
     int ce_bit = 0;               // 8 for the Chapman-Enskog exchange (particle kernel mode bit)
@@ -358,6 +359,27 @@ double ce_nu(const lbmpcd_params& p) {
 // LB steps of the feedback's running mean when fb_window is 0
 constexpr int FB_WINDOW_DEFAULT = 50;
 
+// The six-slot form of the particle launch (six particles per thread at 256
+// threads, then an overflow pass over the tiles holding more than 1536) is
+// offered for tiles of 1025-2048 slots whose expected occupancy plus two
+// Poisson standard deviations is within 1536.  With the default shape it is
+// taken only for grids of at least SPLIT_MIN_TILES tiles: below that the
+// launch is one round of workgroups, which the extra launch only delays.
+constexpr long long SPLIT_MIN_TILES = 4096;
+static bool six_slot_fits(int cap_max, int exp_max) {
+    const double e = (double)exp_max;
+    return cap_max > 4 * 256 && cap_max <= 8 * 256 && e + 2.0 * std::sqrt(e) <= 6.0 * 256;
+}
+
+// Default particle workgroup: 256 threads.  Binary64 particles in tiles of
+// more than 1024 slots take 512 threads (four particles per thread) unless
+// the six-slot form applies at 256, which is faster: eight binary64
+// particles per thread spill.
+static int default_wg_threads(int part_fp, int cap_max, int exp_max, long long tiles) {
+    if (part_fp != 64 || cap_max <= 4 * 256) return 256;
+    return (six_slot_fits(cap_max, exp_max) && tiles >= SPLIT_MIN_TILES) ? 256 : 512;
+}
+
 struct Layout {
     size_t desc, tile_inst, f0, f1, ub, uf, tb, tf, acc, fbu, prof, fill0, fill1, stats, ovf, clock, shifts, scratch, end;
     size_t cl_P, cl_Pb, cl_Pf, cl_G, cl_m, cl_v, cl_stats, cl_sums, cl_loss, cl_facc, cl_nm, cl_uc, cl_inf;
@@ -549,7 +571,7 @@ int finalize(lbmpcd_ctx* c) {
     L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.tfine = c->tf; L.acc = c->acc; L.prof = c->prof;
     L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts;
     L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
-    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.ovf = c->ovf; L.exp_max = c->exp_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
+    L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.ovf = c->split_ok ? c->ovf : nullptr; L.exp_max = c->exp_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
     HIPCHK(c, launch_particles(L, c->stream));
     c->pending = false;
     return 0;
@@ -718,9 +740,12 @@ int lbmpcd_init(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace, siz
         if (d.feedback) c->any_feedback = true;
     }
     c->cap_max = cap_max;
-    // default workgroup: 256 threads; 512 for binary64 particles in tiles of
-    // more than 1024 slots (four particles per thread instead of eight)
-    c->wg_threads = p[0].wg_threads ? p[0].wg_threads : (c->part_fp == 64 && cap_max > 4 * 256 ? 512 : 256);
+    c->wg_threads = p[0].wg_threads ? p[0].wg_threads
+                                    : default_wg_threads(c->part_fp, cap_max, c->exp_max, c->total_tiles);
+    // an explicit 256 takes the six-slot form wherever it fits; the default
+    // only on grids large enough to gain from it
+    c->split_ok = c->wg_threads == 256 && six_slot_fits(cap_max, c->exp_max) &&
+                  (p[0].wg_threads == 256 || c->total_tiles >= SPLIT_MIN_TILES);
     c->lds = particle_lds_bytes(c->dim, c->part_fp, cap_max);
     c->coll_bit = p[0].collision == 1 ? 4 : 0;
     c->det_bit = (p[0].mpcd && p[0].deterministic) ? 16 : 0;
@@ -835,7 +860,7 @@ int enqueue_one_step(lbmpcd_ctx* c, hipStream_t s) {
                 // samples are taken in the last MPCD step of the LB step
                 L.do_fb = (c->any_feedback && sub == c->S - 1) ? 1 : 0;
                 L.do_prof = (c->sampling && sub == c->S - 1) ? 1 : 0;
-                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.ovf = c->ovf; L.exp_max = c->exp_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
+                L.diag_inst = -1; L.cell_vcm = nullptr; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.ovf = c->split_ok ? c->ovf : nullptr; L.exp_max = c->exp_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
                 HIPCHK(c, timed(c, 3, [&] { return launch_particles(L, s); }));
                 c->pcur ^= 1;
                 c->pending = true;
@@ -1013,7 +1038,7 @@ int produce(lbmpcd_ctx* c, int32_t field, int32_t inst, void* dst, size_t nbytes
             L.tile_inst = c->d_tile_inst; L.ufine = c->uf; L.tfine = c->tf; L.acc = c->acc; L.prof = c->prof;
             L.stats = c->stats; L.clock = c->clock; L.shifts = c->shifts; L.shifts = c->shifts;
             L.coll_dt = 0; L.coll_s = c->S - 1; L.str_s = 0;
-            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.ovf = c->ovf; L.exp_max = c->exp_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
+            L.diag_inst = inst; L.cell_vcm = (double*)dst; L.lds_bytes = c->lds; L.cap_max = c->cap_max; L.ovf = c->split_ok ? c->ovf : nullptr; L.exp_max = c->exp_max; L.wg_threads = c->wg_threads; L.cstride = c->cstride; L.xcd_blocked = c->xcd_blocked;
             HIPCHK(c, launch_particles(L, s));
             return 0;
         }
@@ -1206,7 +1231,7 @@ int lbmpcd_autotune(const lbmpcd_params* p, int32_t n_inst, void* dev_workspace,
                 break;
             }
             // the shape the library takes with tile_target = wg_threads = 0
-            const int default_wg = (c->part_fp == 64 && c->cap_max > 4 * 256) ? 512 : 256;
+            const int default_wg = default_wg_threads(c->part_fp, c->cap_max, c->exp_max, c->total_tiles);
             lbmpcd_destroy(c);
             const double per = (double)ms / lb_steps;
             ++out->tried;

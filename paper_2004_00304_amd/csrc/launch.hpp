@@ -67,7 +67,8 @@ struct ParticleLaunch {
     int xcd_blocked;              // 1: each XCD's workgroups take a contiguous range of tiles
     long long cstride;            // bytes between component arrays (pos[k] = pos[0] + k cstride, vel[k] = pos[0] + (dim + k) cstride, id after vel)
     size_t lds_bytes;
-    uint32_t* ovf;                // [2 + tiles] overflow list of a two-pass launch (zero-initialised), or null
+    uint32_t* ovf;                // [2 + tiles] overflow list of a two-pass launch (zero-initialised), or
+                                  // null: the context does not take the two-pass form
     int exp_max;                  // largest expected tile occupancy (particles per cell x cells per tile)
 };
 
