@@ -312,8 +312,9 @@ __device__ __forceinline__ void interp_axis(int Lx, int periodic, double X, int&
     double wx = xs - fl;
     int j1 = j0 + 1;
     if (periodic) {
-        j0 = ((j0 % Lx) + Lx) % Lx;
-        j1 = ((j1 % Lx) + Lx) % Lx;
+        // X lies in [0, Lx) (a cell centre), so j0 >= -1 and j1 <= Lx
+        if (j0 < 0) j0 += Lx;
+        if (j1 >= Lx) j1 -= Lx;
         i0 = j0; i1 = j1; w0 = 1.0 - wx; w1 = wx;
         return;
     }
@@ -361,9 +362,19 @@ __global__ void __launch_bounds__(WG) k_interp(const InstDesc* __restrict__ D, i
     const InstDesc& d = D[ii];
     long long q = gid - d.ufine_off;
     const int Cx = d.Cx, NB = d.NB;
-    int I = (int)(q % Cx);
-    int Jb = (int)((q / Cx) % NB);
-    int K = (int)(q / ((long long)Cx * NB));
+    int I, Jb, K;
+    if (q < 0x7FFFFFFFLL) {
+        // 32-bit decode (an instance's buffer cells number fewer than 2^31
+        // unless it is enormous)
+        const uint32_t qu = (uint32_t)q, row = qu / (uint32_t)Cx;
+        I = (int)(qu - row * (uint32_t)Cx);
+        K = (int)(row / (uint32_t)NB);
+        Jb = (int)(row - (uint32_t)K * (uint32_t)NB);
+    } else {
+        I = (int)(q % Cx);
+        Jb = (int)((q / Cx) % NB);
+        K = (int)(q / ((long long)Cx * NB));
+    }
     int J = (Jb < d.buf_lo * d.r) ? Jb : Jb + (d.R - NB);
     const double r = (double)d.r;
     double X = ((double)I + 0.5) / r;
