@@ -347,10 +347,19 @@ def test_chapman_enskog_xz_shear_parity(env):
     assert np.abs(orc.tfine()[4]).max() > 1e-3
 
 
-@pytest.mark.parametrize("collision,part_fp", [(0, 32), (1, 32), (0, 64)])
-def test_parity_overflow_pass(env, collision, part_fp):
-    """Binary32 SRD and MPCD-AT, and binary64 SRD (256-thread workgroups),
-    particles in tiles of 4x4x2 cells at 45 per cell (1440
+OVERFLOW_CASES = {
+    "srd_fp32": dict(part_fp=32),
+    "at_fp32": dict(part_fp=32, collision=1),
+    "srd_fp64": dict(part_fp=64),
+    "srd_fp32_deterministic": dict(part_fp=32, deterministic=1),
+    "ce_fp32": dict(part_fp=32, reinject=1, init_flow=1, ce_nu=2.0),
+}
+
+
+@pytest.mark.parametrize("case", list(OVERFLOW_CASES))
+def test_parity_overflow_pass(env, case):
+    """Binary32 SRD, MPCD-AT, deterministic SRD and the Chapman-Enskog
+    exchange, and binary64 SRD (256-thread workgroups), particles in tiles of 4x4x2 cells at 45 per cell (1440
     expected, 1984 slots) run as two launches per MPCD step: six slots per
     thread (1536 per tile), then an eight-slot pass over the tiles that held
     more.  A tile's Poisson count passes 1536 now and then (the oracle's own
@@ -359,9 +368,10 @@ def test_parity_overflow_pass(env, collision, part_fp):
     matches the oracle, and the largest tile fill seen is above 1536, so the
     second launch took part."""
     O, lbmpcd = env
-    p = W.small_3d(part_fp=part_fp, ppc=45, tile=(4, 4, 2), g=(1e-4, 0.0, 0.0), collision=collision,
-                   wg_threads=256)
-    banner(f"parity overflow pass: 45 ppc, 4x4x2 tiles, 12 LB steps, collision {collision}, fp{part_fp}")
+    kw = OVERFLOW_CASES[case]
+    part_fp = kw["part_fp"]
+    p = W.small_3d(ppc=45, tile=(4, 4, 2), g=(1e-4, 0.0, 0.0), wg_threads=256, **kw)
+    banner(f"parity overflow pass: 45 ppc, 4x4x2 tiles, 12 LB steps, {case}")
     sim = lbmpcd.Sim(p)
     orc = O.Oracle(_params(p))
     sim.step(12)
