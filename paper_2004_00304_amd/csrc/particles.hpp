@@ -1053,7 +1053,9 @@ static hipError_t launch_p2(const ParticleLaunch& L, hipStream_t s) {
 // particles stay at four waves and spill 24 bytes per lane instead of 108.
 // A tile holding
 // more than 1536 particles is skipped and listed by that launch and
-// processed by a second, eight-slot launch over the list.  It is rare: the
+// processed by a second launch over the list (512 threads, four slots per
+// thread: a listed tile waits on one tile's latency, which more threads
+// shorten).  It is rare: the
 // tile's expected occupancy plus two standard deviations of its Poisson
 // count must stay within 1536 for this form to be taken.
 inline bool split_applies(const ParticleLaunch& L) {
@@ -1066,7 +1068,7 @@ inline bool split_applies(const ParticleLaunch& L) {
 template <class Modes, int DIM, typename PT>
 static hipError_t launch_split_dim(const ParticleLaunch& L, hipStream_t s) {
     hipError_t e = Modes::template run<DIM, PT, 256, 6, 1>(L, s);
-    if (e == hipSuccess) e = Modes::template run<DIM, PT, 256, 8, 2>(L, s);
+    if (e == hipSuccess) e = Modes::template run<DIM, PT, 512, 4, 2>(L, s);
     return e;
 }
 

@@ -361,7 +361,7 @@ def test_parity_overflow_pass(env, case):
     """Binary32 SRD, MPCD-AT, deterministic SRD and the Chapman-Enskog
     exchange, and binary64 SRD (256-thread workgroups), particles in tiles of 4x4x2 cells at 45 per cell (1440
     expected, 1984 slots) run as two launches per MPCD step: six slots per
-    thread (1536 per tile), then an eight-slot pass over the tiles that held
+    thread (1536 per tile), then a pass of 512 threads x 4 slots over the tiles that held
     more.  A tile's Poisson count passes 1536 now and then (the oracle's own
     binning of this seed does so by the twelfth LB step); such a tile is
     skipped by the first launch and processed whole by the second.  The run
